@@ -1,0 +1,188 @@
+"""Recursive FP64 counterfactual regret minimisation (vanilla CFR and CFR+).
+
+Test infrastructure (oracle): not part of the product path.
+
+State: ``T`` (iterations done), ``R[q]`` cumulative counterfactual regret and
+``S[q]`` cumulative weighted strategy, q indexing Q_+ in input order. These are
+the paper's running means written as sums: the average regret of Eq.
+(average_counterfactual_regret) is R / T, and the average strategy of Eq.
+(average_strategy_profile) is S normalised per infoset. Regret matching is
+scale invariant, so R and R / T give the same next strategy.
+
+One iteration, with every infoset using the same strategy sigma^(T+1) (the
+simultaneous schedule of Section 3.2):
+
+1. sigma = regret matching of R (Eq. next_strategy_profile): positive parts
+   normalised, or uniform when their sum is exactly 0; chance plays sigma_0.
+2. A recursive walk carries (pi_1, pi_2, pi_c), the products of each player's
+   and chance's edge probabilities from the root, and returns the node's
+   expected payoff for player 1 (Eq. expected_payoff; u_2 = -u_1).
+   At a node d of player i in infoset h, with child values w_a and node value
+   u = sum_a sigma(h,a) w_a, it adds
+       r~(h,a) += pi_{-i}(d) * sgn_i * (w_a - u)
+   where pi_{-i}(d) is the excepted reach of Eq. (excepted_reach_probability)
+   and sgn_1 = +1, sgn_2 = -1: summed over d in h this is the instantaneous
+   counterfactual regret of Eq. (instantaneous_counterfactual_regret) with the
+   division by the counterfactual reach multiplied out; and it adds
+       pibar(h) += pi_i(d)
+   the player reach of Eq. (player_reach_probability), read with the own-reach
+   recursion (the printed recursion multiplies the excepted reach; the matrix
+   form with the hatted strategies matrix confirms the own-reach reading).
+3. Regret update: vanilla R += r~; CFR+ R = max(R + r~, 0).
+4. Average update: S(h,a) += w * pibar(h) * sigma(h,a), with w = 1 (vanilla,
+   Eq. average_strategy_profile) or w = T + 1 (CFR+ linear averaging).
+5. T += 1.
+
+CFR+ is only cited by the paper; it is read here as regret matching on
+cumulative regrets clipped at zero after each update, linear averaging with no
+delay, the same simultaneous schedule and the same uniform fallback.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+from .tree import Tree
+
+VANILLA, CFR_PLUS = "vanilla", "cfr+"
+
+
+@dataclass
+class State:
+    T: int
+    R: list
+    S: list
+
+    @staticmethod
+    def zeros(tree: Tree) -> "State":
+        return State(0, [0.0] * tree.Q, [0.0] * tree.Q)
+
+    def copy(self) -> "State":
+        return State(self.T, list(self.R), list(self.S))
+
+
+def regret_matching(r: list) -> list:
+    """Eq. (next_strategy_profile) for one infoset."""
+    pos = [x if x > 0.0 else 0.0 for x in r]
+    total = sum(pos)
+    if total > 0.0:
+        return [x / total for x in pos]
+    return [1.0 / len(r)] * len(r)
+
+
+def current_strategy(tree: Tree, R: list) -> list:
+    """sigma over Q_+ from cumulative regrets."""
+    sigma = [0.0] * tree.Q
+    for h in tree.rational:
+        o, k = tree.qoff[h], tree.nact[h]
+        sigma[o:o + k] = regret_matching(R[o:o + k])
+    return sigma
+
+
+def average_strategy(tree: Tree, S: list) -> list:
+    """S normalised per infoset; uniform where the infoset's weights sum to 0."""
+    out = [0.0] * tree.Q
+    for h in tree.rational:
+        o, k = tree.qoff[h], tree.nact[h]
+        tot = sum(S[o:o + k])
+        out[o:o + k] = [x / tot for x in S[o:o + k]] if tot > 0.0 else [1.0 / k] * k
+    return out
+
+
+def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = False):
+    """One CFR iteration. Returns (new_state, info); ``info`` holds sigma, r~,
+    pibar and, if ``record``, per-node expected payoff u1 and reaches."""
+    sigma = current_strategy(tree, state.R)
+    rt = [0.0] * tree.Q
+    pibar = {h: 0.0 for h in tree.rational}
+    n = tree.n
+    node_u = [0.0] * n if record else None
+    node_reach = [None] * n if record else None
+    children, infoset, player = tree.children, tree.infoset, tree.player
+    qoff, sigma0, u1 = tree.qoff, tree.sigma0, tree.u1
+
+    def walk(v, p1, p2, pc):
+        if record:
+            node_reach[v] = (p1, p2, pc)
+        ch = children[v]
+        if not ch:
+            if record:
+                node_u[v] = u1[v]
+            return u1[v]
+        h = infoset[v]
+        pl = player[h]
+        if pl == 0:
+            probs = sigma0[h]
+            u = 0.0
+            for a, c in enumerate(ch):
+                u += probs[a] * walk(c, p1, p2, pc * probs[a])
+        else:
+            o = qoff[h]
+            w = []
+            for a, c in enumerate(ch):
+                s = sigma[o + a]
+                if pl == 1:
+                    w.append(walk(c, p1 * s, p2, pc))
+                else:
+                    w.append(walk(c, p1, p2 * s, pc))
+            u = 0.0
+            for a in range(len(ch)):
+                u += sigma[o + a] * w[a]
+            if pl == 1:
+                cf, own, sgn = p2 * pc, p1, 1.0
+            else:
+                cf, own, sgn = p1 * pc, p2, -1.0
+            for a in range(len(ch)):
+                rt[o + a] += cf * sgn * (w[a] - u)
+            pibar[h] += own
+        if record:
+            node_u[v] = u
+        return u
+
+    root_value = walk(tree.root, 1.0, 1.0, 1.0)
+
+    R = list(state.R)
+    S = list(state.S)
+    w = 1.0 if variant == VANILLA else float(state.T + 1)
+    for h in tree.rational:
+        o, k = qoff[h], tree.nact[h]
+        for a in range(k):
+            q = o + a
+            if variant == VANILLA:
+                R[q] = R[q] + rt[q]
+            elif variant == CFR_PLUS:
+                R[q] = max(R[q] + rt[q], 0.0)
+            else:
+                raise ValueError(variant)
+            S[q] = S[q] + w * pibar[h] * sigma[q]
+    info = {"sigma": sigma, "rtilde": rt, "pibar": pibar, "root_value": root_value,
+            "next_sigma": current_strategy(tree, R)}
+    if record:
+        info["node_u"] = node_u
+        info["node_reach"] = node_reach
+    return State(state.T + 1, R, S), info
+
+
+def solve(tree: Tree, iterations: int, variant: str = VANILLA, state: State | None = None,
+          callback=None) -> State:
+    st = state.copy() if state is not None else State.zeros(tree)
+    for _ in range(iterations):
+        st, _info = iterate(tree, st, variant)
+        if callback is not None:
+            callback(st)
+    return st
+
+
+def expected_value(tree: Tree, profile: list) -> float:
+    """u_hat(sigma, 1) = sum over terminals of pi(sigma, t) u(t, 1) (Section 2.2)."""
+    def val(v):
+        ch = tree.children[v]
+        if not ch:
+            return tree.u1[v]
+        h = tree.infoset[v]
+        if tree.player[h] == 0:
+            probs = tree.sigma0[h]
+        else:
+            o = tree.qoff[h]
+            probs = profile[o:o + len(ch)]
+        return sum(probs[a] * val(c) for a, c in enumerate(ch))
+    return val(tree.root)
