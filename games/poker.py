@@ -153,12 +153,19 @@ def template_size(n_ranks: int, n_rounds: int, cap: int, stack: int, c0: int = 1
 
 def poker_game(n_ranks: int = 13, n_rounds: int = 3, cap: int = 3, stack: int = 400,
                c0: int = 1, board=(), deal_prob=None, scale: bool = False,
-               name: str | None = None) -> Game:
+               name: str | None = None, max_deals: int | None = None) -> Game:
     """Build the game. ``deal_prob`` (optional) maps the ordered deal list to
-    probabilities; ``board`` holds public cards already dealt before the game."""
+    probabilities; ``board`` holds public cards already dealt before the game.
+    ``max_deals`` keeps only the first deals (a bounded sample of the same game, with the
+    root's probabilities renormalised over the kept deals)."""
     board = tuple(int(x) for x in board)
     free = [r for r in range(n_ranks) if r not in board]
     deals = np.asarray([(a, b) for a in free for b in free if a != b], dtype=np.int64)
+    if max_deals is not None:
+        deals = deals[:max_deals]
+        if deal_prob is not None:
+            deal_prob = np.asarray(deal_prob, dtype=np.float64)[:max_deals]
+            deal_prob = deal_prob / deal_prob.sum()
     nd = len(deals)
     fan = [n_ranks - 2 - len(board) - k for k in range(n_rounds - 1)]
     tpl = _arrays(_Template(n_rounds, fan, cap, stack, c0))

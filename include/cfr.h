@@ -1,0 +1,176 @@
+/*
+ * cfr.h - C ABI of the MI355X (gfx950) counterfactual regret minimisation library.
+ *
+ * One CFR iteration over a finite two-player zero-sum extensive-form game,
+ * computed level by level over a flattened tree (Kim, "GPU-Accelerated
+ * Counterfactual Regret Minimization", Section 3). The calls follow the
+ * paper's statement of the problem: the game is the tuple of Definition 1
+ * (Section 2.1); an iteration computes the expected payoffs of Eq.
+ * (expected_payoff), the excepted and player reach probabilities of Eqs.
+ * (excepted_reach_probability, player_reach_probability), the instantaneous
+ * counterfactual regrets of Eq. (instantaneous_counterfactual_regret), the
+ * average strategy of Eq. (average_strategy_profile) and the next strategy of
+ * Eq. (next_strategy_profile); exploitability judges the average strategy
+ * against the Nash condition of Section 2.2.
+ *
+ * Conventions for every call
+ *  - Return value: CFR_OK (0) or a negative CFR_E* code; the thread-local
+ *    message of the last failure is cfr_last_error(). No exception crosses
+ *    the ABI. Errors of asynchronous GPU work surface at the next call that
+ *    synchronises (average strategy to host, state export, exploitability).
+ *  - Host arrays passed in are borrowed for the duration of the call and
+ *    copied; the library keeps no pointer to them.
+ *  - Device memory: the caller owns the workspace (cfr_plan reports its
+ *    size); the solver lives inside it and owns only host metadata, events and
+ *    the captured iteration graph. The workspace must stay allocated until
+ *    cfr_destroy returns.
+ *  - Streams: all GPU work of a solver is ordered on the hipStream_t given to
+ *    cfr_build (may be the null stream).
+ *  - Infoset-action pairs ("q") are numbered as in the input: rational-player
+ *    infosets in increasing input id, actions in index order (the set Q_+ of
+ *    Section 2.1).
+ */
+#ifndef CFR_MI355X_H
+#define CFR_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFR_OK 0
+#define CFR_EINVAL (-1)   /* null pointer, bad size or bad enum value */
+#define CFR_ENOTTREE (-2) /* no unique root, a cycle, an unreachable node, or a terminal/decision mismatch */
+#define CFR_EACTION (-3)  /* f_a is not a bijection onto A(h), or an infoset is inconsistent */
+#define CFR_ECHANCE (-4)  /* a chance probability < 0, or one chance infoset not summing to 1 (+-1e-9) */
+#define CFR_EZEROSUM (-5) /* payoff_u1 + payoff_u2 != 0 at a terminal */
+#define CFR_ELEVEL (-6)   /* an infoset spans several depths (exploitability needs level-pure infosets) */
+#define CFR_ENOMEM (-7)   /* workspace too small */
+#define CFR_ESTATE (-8)   /* state size mismatch */
+#define CFR_EHIP (-9)     /* HIP runtime error; the message carries hipGetErrorString */
+
+/* The game tuple <T, H, f_h, A, f_a, I, f_i, sigma_0, u> of Definition 1 (Section 2.1).
+ * Node and infoset ids are arbitrary; the library canonicalises them. */
+typedef struct cfr_game {
+    int64_t n_nodes;
+    const int32_t* parent;              /* [n_nodes] parent function f_Pa; -1 at the root */
+    const int32_t* node_infoset;        /* [n_nodes] f_h; -1 at terminal nodes */
+    const int32_t* node_action;         /* [n_nodes] index of the edge into the node within
+                                           A(f_h(parent)), 0..|A|-1; -1 at the root */
+    int32_t n_infosets;
+    const int8_t* infoset_player;       /* [n_infosets] f_i: 0 chance, 1 or 2 */
+    const int32_t* infoset_num_actions; /* [n_infosets] |A(h)| */
+    const double* chance_prob;          /* sigma_0: chance infosets in increasing id order,
+                                           |A(h)| probabilities each, in action order */
+    const double* payoff_u1;            /* [n_nodes] u(t, 1); read at terminals only */
+    const double* payoff_u2;            /* optional [n_nodes] u(t, 2), checked for zero sum */
+} cfr_game;
+
+enum { CFR_VANILLA = 0, CFR_PLUS = 1 };           /* regret update: R += r~ ; R = max(R + r~, 0) */
+enum { CFR_AVG_DEFAULT = -1, CFR_AVG_UNIFORM = 0, CFR_AVG_LINEAR = 1 };
+/* Averaging weight of iteration t (1-based): 1 (uniform, Eq. average_strategy_profile) or t
+ * (linear). DEFAULT = uniform for vanilla, linear for CFR+. */
+
+#define CFR_FLAG_NO_GRAPH 1u /* enqueue kernels directly instead of replaying a captured graph */
+
+typedef struct cfr_config {
+    int32_t variant;   /* CFR_VANILLA or CFR_PLUS */
+    int32_t averaging; /* CFR_AVG_* */
+    uint32_t flags;    /* CFR_FLAG_* */
+    int32_t reserved[5];
+} cfr_config;
+
+/* Sizes of the game in the columns of the paper's game-properties table (Appendix). */
+typedef struct cfr_plan_info {
+    int64_t n_nodes;
+    int64_t n_terminals;
+    int64_t n_infosets;        /* rational-player infosets H_+ */
+    int64_t n_q;               /* infoset-action pairs Q_+ */
+    int64_t n_chance_infosets;
+    int64_t n_chance_q;
+    int32_t max_actions;
+    int32_t depth;             /* D: deepest level */
+    int32_t level_pure;        /* 1 if every infoset lies on one level */
+    int32_t reserved;
+    int64_t workspace_bytes;   /* device bytes cfr_build needs */
+} cfr_plan_info;
+
+typedef struct cfr_solver cfr_solver;
+
+/* Validate the game (see the error codes) and report its sizes and the workspace size. */
+int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out);
+
+/* Flatten the game into the canonical level-ordered layout on the host, copy it into
+ * `workspace` (device memory of at least `bytes`), set T = 0, R = S = 0 and sigma uniform
+ * (Section 3.1, initial strategy), and capture the iteration. `stream` is a hipStream_t. */
+int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, size_t bytes,
+              void* stream, cfr_solver** out);
+
+/* Enqueue n iterations (Section 3.2) on the solver's stream; does not synchronise. */
+int cfr_iterate(cfr_solver* s, int32_t n);
+
+/* Run n iterations with direct launches and a pair of hipEvents around every kernel launch on
+ * the solver's stream (synchronises). kernel_ms[k] receives the summed event time of kernel
+ * kind k over the n iterations and kernel_launches[k] its launch count, for k < n_kinds;
+ * cfr_kernel_name(k) names kind k (empty string past the last kind). The results of the
+ * iterations are the same as cfr_iterate's. */
+int cfr_iterate_timed(cfr_solver* s, int32_t n, double* kernel_ms, int64_t* kernel_launches,
+                      int32_t n_kinds);
+const char* cfr_kernel_name(int32_t kind);
+
+/* Average strategy sigma-bar = S / sum_a S per infoset, uniform where that sum is 0
+ * (Eq. average_strategy_profile), written to out[q] for the n_q pairs in input order.
+ * out_on_device != 0: `out` is device memory, the call enqueues and returns;
+ * otherwise `out` is host memory and the call synchronises. */
+int cfr_average_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device);
+
+/* Current strategy sigma^(T+1) = regret matching of R (Eq. next_strategy_profile): the
+ * strategy the next iteration will play, in input pair order. Same memory convention as
+ * cfr_average_strategy. */
+int cfr_current_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device);
+
+/* Best-response values of both players against the average strategy and the
+ * exploitability (BR_1 + BR_2) / 2 (Section 2.2). Synchronises. Needs level-pure
+ * infosets (CFR_ELEVEL otherwise). br_value may be NULL. */
+int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]);
+
+/* Solver state in input pair order: T (iterations done), cumulative regrets R and
+ * cumulative average-strategy weights S (R / T is the average regret of Eq.
+ * average_counterfactual_regret). Host arrays; both calls synchronise. */
+int cfr_get_state(cfr_solver* s, int64_t* T, float* R, float* S, int64_t n_q);
+int cfr_set_state(cfr_solver* s, int64_t T, const float* R, const float* S, int64_t n_q);
+
+/* Canonical layout export for checking (host copy, synchronises). `name` is one of
+ * level_offset, node_id, parent, child_begin, node_player, node_infoset, node_edge,
+ * infoset_id, infoset_player, q_offset, chance_id, cq_offset, member_offset, members,
+ * chance_prob, payoff, q_input. cfr_layout_bytes returns the size (< 0 for an unknown name). */
+int64_t cfr_layout_bytes(cfr_solver* s, const char* name);
+int cfr_get_layout(cfr_solver* s, const char* name, void* out, int64_t bytes);
+
+/* Per-node values of the last iteration in canonical node order (host, synchronises):
+ * u1[v] = expected payoff of player 1 (Eq. expected_payoff) and reach[3 * v + k] =
+ * product of player 1's (k = 0), player 2's (k = 1) and chance's (k = 2) edge
+ * probabilities from the root, for decision nodes (terminal entries are unspecified).
+ * Either pointer may be NULL. */
+int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes);
+
+/* Host-only flattening, for checking the canonical layout without a GPU: build the layout
+ * of `game` on the host (validation as in cfr_plan), then read arrays by the names listed for
+ * cfr_get_layout. The handle owns host memory only. */
+typedef struct cfr_host_layout cfr_host_layout;
+int cfr_host_layout_create(const cfr_game* game, cfr_host_layout** out);
+int64_t cfr_host_layout_bytes(const cfr_host_layout* layout, const char* name);
+int cfr_host_layout_get(const cfr_host_layout* layout, const char* name, void* out, int64_t bytes);
+int cfr_host_layout_destroy(cfr_host_layout* layout);
+
+/* Release host resources; the caller then frees the workspace. */
+int cfr_destroy(cfr_solver* s);
+
+const char* cfr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFR_MI355X_H */

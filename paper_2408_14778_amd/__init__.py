@@ -1,0 +1,8 @@
+"""MI355X-native CFR: one counterfactual-regret-minimisation iteration over a flattened,
+level-ordered game tree, computed by hand-written gfx950 HIP kernels behind a C ABI
+(include/cfr.h). This package holds the kernels' sources (csrc/), the build step and
+the thin ctypes binding."""
+from ._native import CfrError, load  # noqa: F401
+from .solver import Solver, host_layout, plan  # noqa: F401
+
+__all__ = ["Solver", "plan", "host_layout", "CfrError", "load"]

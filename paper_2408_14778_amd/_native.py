@@ -1,0 +1,132 @@
+"""ctypes binding of the C ABI in include/cfr.h: argument marshalling only.
+
+Every step of the computation runs in the gfx950 library; if the library is
+missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcfr_mi355x.so")
+
+CFR_OK = 0
+ERRORS = {
+    -1: "CFR_EINVAL", -2: "CFR_ENOTTREE", -3: "CFR_EACTION", -4: "CFR_ECHANCE",
+    -5: "CFR_EZEROSUM", -6: "CFR_ELEVEL", -7: "CFR_ENOMEM", -8: "CFR_ESTATE", -9: "CFR_EHIP",
+}
+CFR_VANILLA, CFR_PLUS = 0, 1
+CFR_AVG_DEFAULT, CFR_AVG_UNIFORM, CFR_AVG_LINEAR = -1, 0, 1
+CFR_FLAG_NO_GRAPH = 1
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class CfrGame(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int64),
+        ("parent", _i32p),
+        ("node_infoset", _i32p),
+        ("node_action", _i32p),
+        ("n_infosets", ctypes.c_int32),
+        ("infoset_player", _i8p),
+        ("infoset_num_actions", _i32p),
+        ("chance_prob", _f64p),
+        ("payoff_u1", _f64p),
+        ("payoff_u2", _f64p),
+    ]
+
+
+class CfrConfig(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int32),
+        ("averaging", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32 * 5),
+    ]
+
+
+class CfrPlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_nodes", ctypes.c_int64),
+        ("n_terminals", ctypes.c_int64),
+        ("n_infosets", ctypes.c_int64),
+        ("n_q", ctypes.c_int64),
+        ("n_chance_infosets", ctypes.c_int64),
+        ("n_chance_q", ctypes.c_int64),
+        ("max_actions", ctypes.c_int32),
+        ("depth", ctypes.c_int32),
+        ("level_pure", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_int64),
+    ]
+
+
+# name -> (restype, argtypes); exactly the entry points declared in include/cfr.h
+SIGNATURES = {
+    "cfr_plan": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.POINTER(CfrConfig),
+                                ctypes.POINTER(CfrPlanInfo)]),
+    "cfr_build": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.POINTER(CfrConfig),
+                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_void_p)]),
+    "cfr_iterate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "cfr_iterate_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, _i64p,
+                                         ctypes.c_int32]),
+    "cfr_kernel_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "cfr_average_strategy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_int]),
+    "cfr_current_strategy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_int]),
+    "cfr_exploitability": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
+    "cfr_get_state": (ctypes.c_int, [ctypes.c_void_p, _i64p, _f32p, _f32p, ctypes.c_int64]),
+    "cfr_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _f32p, _f32p,
+                                     ctypes.c_int64]),
+    "cfr_layout_bytes": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_char_p]),
+    "cfr_get_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
+                                      ctypes.c_int64]),
+    "cfr_get_node_values": (ctypes.c_int, [ctypes.c_void_p, _f32p, _f32p, ctypes.c_int64]),
+    "cfr_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "cfr_host_layout_create": (ctypes.c_int, [ctypes.POINTER(CfrGame),
+                                              ctypes.POINTER(ctypes.c_void_p)]),
+    "cfr_host_layout_bytes": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_char_p]),
+    "cfr_host_layout_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
+                                           ctypes.c_int64]),
+    "cfr_host_layout_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "cfr_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load the library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with paper_2408_14778_amd.build.build() "
+                "(hipcc, gfx950). There is no fallback path.")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class CfrError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        self.code = code
+        super().__init__(f"{ERRORS.get(code, code)}: {message}")
+
+
+def check(code: int) -> None:
+    if code != CFR_OK:
+        msg = load().cfr_last_error()
+        raise CfrError(code, msg.decode() if msg else "")

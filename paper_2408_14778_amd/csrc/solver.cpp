@@ -1,0 +1,558 @@
+// C ABI of the library (include/cfr.h): planning, building, iterating, exports.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <utility>
+#include <string>
+#include <vector>
+
+#include "../../include/cfr.h"
+#include "flatten.hpp"
+#include "kernels.hpp"
+
+struct cfr_solver {
+    cfr::Dev dev{};
+    int variant = CFR_VANILLA;
+    int linear = 0;
+    bool use_graph = true;
+    bool level_pure = true;
+    int64_t T = 0;
+    int64_t n_terminals = 0;
+    int32_t max_actions = 0;
+    std::vector<int32_t> level_offset;          // host copy, D + 2
+    std::vector<int32_t> infoset_level_offset;  // host copy, D + 2
+    hipStream_t stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_err(hipError_t e, const char* what) {
+    return set_err(CFR_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                            \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_err(e_, what); \
+    } while (0)
+
+// Bump allocator over the caller's workspace, 256-byte aligned pieces.
+struct Carve {
+    uintptr_t base;
+    size_t off = 0;
+    explicit Carve(void* p) : base(reinterpret_cast<uintptr_t>(p)) {}
+    template <class T>
+    T* take(int64_t count) {
+        off = (off + 255) & ~size_t{255};
+        T* p = reinterpret_cast<T*>(base + off);
+        off += static_cast<size_t>(count > 0 ? count : 1) * sizeof(T);
+        return p;
+    }
+};
+
+// Lays out every device array; with base = nullptr it only measures.
+size_t carve(cfr::Dev& d, void* base, int64_t N, int64_t Hp, int64_t Qp, int64_t H0, int64_t Q0,
+             int64_t M, int32_t D) {
+    Carve c(base);
+    d.N = N; d.Hp = Hp; d.Qp = Qp; d.H0 = H0; d.Q0 = Q0; d.M = M; d.D = D;
+    d.parent = c.take<int32_t>(N);
+    d.child_begin = c.take<int32_t>(N + 1);
+    d.node_player = c.take<int8_t>(N);
+    d.node_infoset = c.take<int32_t>(N);
+    d.node_edge = c.take<int32_t>(N);
+    d.node_id = c.take<int32_t>(N);
+    d.level_offset = c.take<int32_t>(D + 2);
+    d.infoset_id = c.take<int32_t>(Hp);
+    d.infoset_player = c.take<int8_t>(Hp);
+    d.q_offset = c.take<int32_t>(Hp + 1);
+    d.chance_id = c.take<int32_t>(H0);
+    d.cq_offset = c.take<int32_t>(H0 + 1);
+    d.member_offset = c.take<int32_t>(Hp + 1);
+    d.members = c.take<int32_t>(M);
+    d.q_input = c.take<int32_t>(Qp);
+    d.payoff = c.take<float>(N);
+    d.prob = c.take<float>(Qp + Q0);
+    d.R = c.take<float>(Qp);
+    d.S = c.take<float>(Qp);
+    d.rtilde = c.take<float>(Qp);
+    d.pibar = c.take<float>(Hp);
+    d.value = c.take<float>(N);
+    d.reach = c.take<float>(3 * N);
+    d.T = c.take<int64_t>(1);
+    d.avgprob = c.take<float>(Qp + Q0);
+    d.br_reach = c.take<float>(N);
+    d.br_value = c.take<float>(N);
+    d.best = c.take<int32_t>(Hp);
+    d.stage = c.take<float>(2 * Qp);
+    d.out2 = c.take<double>(2);
+    return (c.off + 255) & ~size_t{255};
+}
+
+int check_hip(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_err(e, what);
+    return CFR_OK;
+}
+
+template <class T>
+int upload(T* dst, const std::vector<T>& src, hipStream_t st) {
+    if (src.empty()) return CFR_OK;
+    HIP_TRY(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st),
+            "upload");
+    return CFR_OK;
+}
+
+int capture(cfr_solver* s) {
+    hipStream_t cap;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "create capture stream");
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_err(e, "begin capture");
+    }
+    cfr::launch_iteration(s->dev, s->level_offset.data(), s->variant, s->linear, cap);
+    e = hipStreamEndCapture(cap, &s->graph);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return hip_err(e, "end capture");
+    HIP_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0), "instantiate graph");
+    return CFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cfr_last_error(void) { return g_err.c_str(); }
+
+int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out) {
+    if (game == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (config != nullptr && (config->variant < 0 || config->variant > 1))
+        return set_err(CFR_EINVAL, "bad variant");
+    cfr::Layout L;
+    std::string err;
+    const int rc = cfr::plan_sizes(*game, L, err);
+    if (rc != CFR_OK) return set_err(rc, err);
+    int64_t M = 0;
+    for (int64_t v = 0; v < game->n_nodes; ++v) {
+        const int32_t h = game->node_infoset[v];
+        if (h >= 0 && game->infoset_player[h] != 0) ++M;
+    }
+    cfr::Dev d{};
+    std::memset(out, 0, sizeof *out);
+    out->n_nodes = L.N;
+    out->n_terminals = L.n_terminals;
+    out->n_infosets = L.Hp;
+    out->n_q = L.Qp;
+    out->n_chance_infosets = L.H0;
+    out->n_chance_q = L.Q0;
+    out->max_actions = L.max_actions;
+    out->depth = L.D;
+    out->level_pure = L.level_pure ? 1 : 0;
+    out->workspace_bytes = static_cast<int64_t>(carve(d, nullptr, L.N, L.Hp, L.Qp, L.H0, L.Q0, M, L.D));
+    return CFR_OK;
+}
+
+int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, size_t bytes,
+              void* stream, cfr_solver** out) {
+    if (game == nullptr || workspace == nullptr || out == nullptr)
+        return set_err(CFR_EINVAL, "null argument");
+    cfr_config cfg{};
+    cfg.variant = CFR_VANILLA;
+    cfg.averaging = CFR_AVG_DEFAULT;
+    if (config != nullptr) cfg = *config;
+    if (cfg.variant < 0 || cfg.variant > 1) return set_err(CFR_EINVAL, "bad variant");
+    if (cfg.averaging < -1 || cfg.averaging > 1) return set_err(CFR_EINVAL, "bad averaging");
+    cfr::Layout L;
+    std::string err;
+    int rc = cfr::flatten(*game, L, err);
+    if (rc != CFR_OK) return set_err(rc, err);
+    const int64_t M = static_cast<int64_t>(L.members.size());
+    cfr::Dev d{};
+    const size_t need = carve(d, nullptr, L.N, L.Hp, L.Qp, L.H0, L.Q0, M, L.D);
+    if (bytes < need)
+        return set_err(CFR_ENOMEM, "workspace has " + std::to_string(bytes) + " bytes, needs " +
+                                       std::to_string(need));
+    carve(d, workspace, L.N, L.Hp, L.Qp, L.H0, L.Q0, M, L.D);
+
+    auto* s = new cfr_solver();
+    s->dev = d;
+    s->variant = cfg.variant;
+    s->linear = cfg.averaging == CFR_AVG_DEFAULT ? (cfg.variant == CFR_PLUS) : cfg.averaging;
+    s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
+    s->level_pure = L.level_pure;
+    s->n_terminals = L.n_terminals;
+    s->max_actions = L.max_actions;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->level_offset = L.level_offset;
+    // infosets are numbered by first appearance, so with level-pure infosets each level's
+    // infosets form a contiguous id range
+    s->infoset_level_offset.assign(L.D + 2, static_cast<int32_t>(L.Hp));
+    {
+        int32_t h = 0;
+        for (int32_t l = 0; l <= L.D; ++l) {
+            s->infoset_level_offset[l] = h;
+            while (h < L.Hp && L.members[L.member_offset[h]] < L.level_offset[l + 1]) ++h;
+        }
+        s->infoset_level_offset[L.D + 1] = static_cast<int32_t>(L.Hp);
+    }
+    hipStream_t st = s->stream;
+    std::vector<float> prob_tail(L.Qp + L.Q0, 0.0f);
+    for (int64_t i = 0; i < L.Q0; ++i) prob_tail[L.Qp + i] = L.chance_prob[i];
+    if ((rc = upload(d.parent, L.parent, st)) || (rc = upload(d.child_begin, L.child_begin, st)) ||
+        (rc = upload(d.node_player, L.node_player, st)) ||
+        (rc = upload(d.node_infoset, L.node_infoset, st)) ||
+        (rc = upload(d.node_edge, L.node_edge, st)) || (rc = upload(d.node_id, L.node_id, st)) ||
+        (rc = upload(d.level_offset, L.level_offset, st)) ||
+        (rc = upload(d.infoset_id, L.infoset_id, st)) ||
+        (rc = upload(d.infoset_player, L.infoset_player, st)) ||
+        (rc = upload(d.q_offset, L.q_offset, st)) || (rc = upload(d.chance_id, L.chance_id, st)) ||
+        (rc = upload(d.cq_offset, L.cq_offset, st)) ||
+        (rc = upload(d.member_offset, L.member_offset, st)) ||
+        (rc = upload(d.members, L.members, st)) || (rc = upload(d.q_input, L.q_input, st)) ||
+        (rc = upload(d.payoff, L.payoff, st)) || (rc = upload(d.prob, prob_tail, st))) {
+        delete s;
+        return rc;
+    }
+    cfr::launch_reset(d, st);
+    if ((rc = check_hip("reset")) != CFR_OK) {
+        delete s;
+        return rc;
+    }
+    // host vectors are released when L goes out of scope: wait for the copies first
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_err(e, "build synchronise");
+    }
+    if (s->use_graph && (rc = capture(s)) != CFR_OK) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return CFR_OK;
+}
+
+int cfr_iterate(cfr_solver* s, int32_t n) {
+    if (s == nullptr || n < 0) return set_err(CFR_EINVAL, "bad solver or count");
+    for (int32_t i = 0; i < n; ++i) {
+        if (s->use_graph) {
+            HIP_TRY(hipGraphLaunch(s->exec, s->stream), "graph launch");
+        } else {
+            cfr::launch_iteration(s->dev, s->level_offset.data(), s->variant, s->linear, s->stream);
+            const int rc = check_hip("iteration launch");
+            if (rc != CFR_OK) return rc;
+        }
+    }
+    s->T += n;
+    return CFR_OK;
+}
+
+namespace {
+struct EventTimer : cfr::LaunchTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kinds;
+    size_t used = 0;
+    hipError_t err = hipSuccess;
+    hipEvent_t next() {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            const hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) err = r;
+            ev.push_back(e);
+        }
+        return ev[used++];
+    }
+    void before(int kind, hipStream_t st) override {
+        kinds.push_back(kind);
+        const hipError_t r = hipEventRecord(next(), st);
+        if (r != hipSuccess) err = r;
+    }
+    void after(int, hipStream_t st) override {
+        const hipError_t r = hipEventRecord(next(), st);
+        if (r != hipSuccess) err = r;
+    }
+    ~EventTimer() override {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace
+
+const char* cfr_kernel_name(int32_t kind) { return cfr::kernel_kind_name(kind); }
+
+int cfr_iterate_timed(cfr_solver* s, int32_t n, double* kernel_ms, int64_t* kernel_launches,
+                      int32_t n_kinds) {
+    if (s == nullptr || n < 0 || n_kinds < 0 || (n_kinds > 0 && (kernel_ms == nullptr ||
+                                                                  kernel_launches == nullptr)))
+        return set_err(CFR_EINVAL, "bad argument");
+    for (int32_t k = 0; k < n_kinds; ++k) {
+        kernel_ms[k] = 0.0;
+        kernel_launches[k] = 0;
+    }
+    EventTimer timer;
+    for (int32_t i = 0; i < n; ++i) {
+        timer.used = 0;
+        timer.kinds.clear();
+        cfr::launch_iteration(s->dev, s->level_offset.data(), s->variant, s->linear, s->stream, &timer);
+        int rc = check_hip("timed iteration launch");
+        if (rc != CFR_OK) return rc;
+        if (timer.err != hipSuccess) return hip_err(timer.err, "event record");
+        HIP_TRY(hipStreamSynchronize(s->stream), "timed iteration synchronise");
+        for (size_t j = 0; j < timer.kinds.size(); ++j) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, timer.ev[2 * j], timer.ev[2 * j + 1]), "event time");
+            const int k = timer.kinds[j];
+            if (k < n_kinds) {
+                kernel_ms[k] += ms;
+                kernel_launches[k] += 1;
+            }
+        }
+        s->T += 1;
+    }
+    return CFR_OK;
+}
+
+int cfr_average_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device) {
+    if (s == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    cfr::launch_average(s->dev, s->stream);
+    if (out_on_device) {
+        cfr::launch_scatter_q(s->dev, s->dev.avgprob, out, s->stream);
+        return check_hip("average strategy");
+    }
+    cfr::launch_scatter_q(s->dev, s->dev.avgprob, s->dev.stage, s->stream);
+    HIP_TRY(hipMemcpyAsync(out, s->dev.stage, n_q * sizeof(float), hipMemcpyDeviceToHost, s->stream),
+            "average strategy copy");
+    HIP_TRY(hipStreamSynchronize(s->stream), "average strategy synchronise");
+    return CFR_OK;
+}
+
+int cfr_current_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device) {
+    if (s == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    if (out_on_device) {
+        cfr::launch_scatter_q(s->dev, s->dev.prob, out, s->stream);
+        return check_hip("current strategy");
+    }
+    cfr::launch_scatter_q(s->dev, s->dev.prob, s->dev.stage, s->stream);
+    HIP_TRY(hipMemcpyAsync(out, s->dev.stage, n_q * sizeof(float), hipMemcpyDeviceToHost, s->stream),
+            "current strategy copy");
+    HIP_TRY(hipStreamSynchronize(s->stream), "current strategy synchronise");
+    return CFR_OK;
+}
+
+int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]) {
+    if (s == nullptr || expl == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (!s->level_pure) return set_err(CFR_ELEVEL, "an infoset spans several levels");
+    cfr::launch_average(s->dev, s->stream);
+    for (int player = 1; player <= 2; ++player)
+        cfr::launch_best_response(s->dev, s->level_offset.data(), s->infoset_level_offset.data(),
+                                  player, s->stream);
+    int rc = check_hip("best response launch");
+    if (rc != CFR_OK) return rc;
+    double br[2];
+    HIP_TRY(hipMemcpyAsync(br, s->dev.out2, sizeof br, hipMemcpyDeviceToHost, s->stream), "br copy");
+    HIP_TRY(hipStreamSynchronize(s->stream), "exploitability synchronise");
+    *expl = 0.5 * (br[0] + br[1]);
+    if (br_value != nullptr) {
+        br_value[0] = br[0];
+        br_value[1] = br[1];
+    }
+    return CFR_OK;
+}
+
+int cfr_get_state(cfr_solver* s, int64_t* T, float* R, float* S, int64_t n_q) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    if (T != nullptr) *T = s->T;
+    const float* srcs[2] = {s->dev.R, s->dev.S};
+    float* dsts[2] = {R, S};
+    for (int k = 0; k < 2; ++k) {
+        if (dsts[k] == nullptr) continue;
+        cfr::launch_scatter_q(s->dev, srcs[k], s->dev.stage, s->stream);
+        HIP_TRY(hipMemcpyAsync(dsts[k], s->dev.stage, n_q * sizeof(float), hipMemcpyDeviceToHost,
+                               s->stream), "state copy");
+        HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
+    }
+    return CFR_OK;
+}
+
+int cfr_set_state(cfr_solver* s, int64_t T, const float* R, const float* S, int64_t n_q) {
+    if (s == nullptr || R == nullptr || S == nullptr || T < 0)
+        return set_err(CFR_EINVAL, "null argument or negative T");
+    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    const float* srcs[2] = {R, S};
+    float* dsts[2] = {s->dev.R, s->dev.S};
+    for (int k = 0; k < 2; ++k) {
+        HIP_TRY(hipMemcpyAsync(s->dev.stage, srcs[k], n_q * sizeof(float), hipMemcpyHostToDevice,
+                               s->stream), "state copy");
+        cfr::launch_gather_q(s->dev, s->dev.stage, dsts[k], s->stream);
+        // the staging buffer is reused: keep the two transfers apart
+        HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
+    }
+    cfr::launch_regret_match(s->dev, s->stream);
+    cfr::launch_set_T(s->dev, T, s->stream);
+    HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
+    s->T = T;
+    return check_hip("set state");
+}
+
+int64_t cfr_layout_bytes(cfr_solver* s, const char* name) {
+    if (s == nullptr || name == nullptr) return CFR_EINVAL;
+    const cfr::Dev& d = s->dev;
+    const std::string n(name);
+    if (n == "level_offset") return (d.D + 2) * 4;
+    if (n == "node_id" || n == "parent" || n == "node_infoset" || n == "node_edge") return d.N * 4;
+    if (n == "child_begin") return (d.N + 1) * 4;
+    if (n == "node_player") return d.N;
+    if (n == "infoset_id") return d.Hp * 4;
+    if (n == "infoset_player") return d.Hp;
+    if (n == "q_offset" || n == "member_offset") return (d.Hp + 1) * 4;
+    if (n == "chance_id") return d.H0 * 4;
+    if (n == "cq_offset") return (d.H0 + 1) * 4;
+    if (n == "members") return d.M * 4;
+    if (n == "chance_prob") return d.Q0 * 4;
+    if (n == "payoff") return d.N * 4;
+    if (n == "q_input") return d.Qp * 4;
+    return CFR_EINVAL;
+}
+
+int cfr_get_layout(cfr_solver* s, const char* name, void* out, int64_t bytes) {
+    const int64_t need = cfr_layout_bytes(s, name);
+    if (need < 0) return set_err(CFR_EINVAL, "unknown layout array");
+    if (out == nullptr || bytes != need) return set_err(CFR_EINVAL, "wrong output size");
+    const cfr::Dev& d = s->dev;
+    const std::string n(name);
+    const void* src = nullptr;
+    if (n == "level_offset") src = d.level_offset;
+    else if (n == "node_id") src = d.node_id;
+    else if (n == "parent") src = d.parent;
+    else if (n == "child_begin") src = d.child_begin;
+    else if (n == "node_player") src = d.node_player;
+    else if (n == "node_infoset") src = d.node_infoset;
+    else if (n == "node_edge") src = d.node_edge;
+    else if (n == "infoset_id") src = d.infoset_id;
+    else if (n == "infoset_player") src = d.infoset_player;
+    else if (n == "q_offset") src = d.q_offset;
+    else if (n == "chance_id") src = d.chance_id;
+    else if (n == "cq_offset") src = d.cq_offset;
+    else if (n == "member_offset") src = d.member_offset;
+    else if (n == "members") src = d.members;
+    else if (n == "chance_prob") src = d.prob + d.Qp;
+    else if (n == "payoff") src = d.payoff;
+    else if (n == "q_input") src = d.q_input;
+    if (bytes == 0) return CFR_OK;
+    HIP_TRY(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, s->stream), "layout copy");
+    HIP_TRY(hipStreamSynchronize(s->stream), "layout synchronise");
+    return CFR_OK;
+}
+
+int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (n_nodes != s->dev.N) return set_err(CFR_EINVAL, "n_nodes does not match the game");
+    const int64_t N = s->dev.N;
+    if (u1 != nullptr)
+        HIP_TRY(hipMemcpyAsync(u1, s->dev.value, N * sizeof(float), hipMemcpyDeviceToHost, s->stream),
+                "value copy");
+    std::vector<float> planes;
+    if (reach != nullptr) {
+        planes.resize(3 * N);
+        HIP_TRY(hipMemcpyAsync(planes.data(), s->dev.reach, 3 * N * sizeof(float),
+                               hipMemcpyDeviceToHost, s->stream), "reach copy");
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream), "node values synchronise");
+    if (reach != nullptr)
+        for (int64_t v = 0; v < N; ++v)
+            for (int k = 0; k < 3; ++k) reach[3 * v + k] = planes[k * N + v];
+    return CFR_OK;
+}
+
+int cfr_destroy(cfr_solver* s) {
+    if (s == nullptr) return CFR_OK;
+    (void)hipStreamSynchronize(s->stream);
+    if (s->exec != nullptr) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph != nullptr) (void)hipGraphDestroy(s->graph);
+    delete s;
+    return CFR_OK;
+}
+
+}  // extern "C"
+
+struct cfr_host_layout {
+    cfr::Layout L;
+};
+
+namespace {
+
+// (pointer, bytes) of a named host layout array
+std::pair<const void*, int64_t> host_array(const cfr::Layout& L, const std::string& n) {
+    auto v = [](const auto& vec) {
+        return std::pair<const void*, int64_t>(
+            vec.data(), static_cast<int64_t>(vec.size() * sizeof(vec[0])));
+    };
+    if (n == "level_offset") return v(L.level_offset);
+    if (n == "node_id") return v(L.node_id);
+    if (n == "parent") return v(L.parent);
+    if (n == "child_begin") return v(L.child_begin);
+    if (n == "node_player") return v(L.node_player);
+    if (n == "node_infoset") return v(L.node_infoset);
+    if (n == "node_edge") return v(L.node_edge);
+    if (n == "infoset_id") return v(L.infoset_id);
+    if (n == "infoset_player") return v(L.infoset_player);
+    if (n == "q_offset") return v(L.q_offset);
+    if (n == "chance_id") return v(L.chance_id);
+    if (n == "cq_offset") return v(L.cq_offset);
+    if (n == "member_offset") return v(L.member_offset);
+    if (n == "members") return v(L.members);
+    if (n == "chance_prob") return v(L.chance_prob);
+    if (n == "payoff") return v(L.payoff);
+    if (n == "q_input") return v(L.q_input);
+    return {nullptr, -1};
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfr_host_layout_create(const cfr_game* game, cfr_host_layout** out) {
+    if (game == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    auto* h = new cfr_host_layout();
+    std::string err;
+    const int rc = cfr::flatten(*game, h->L, err);
+    if (rc != CFR_OK) {
+        delete h;
+        return set_err(rc, err);
+    }
+    *out = h;
+    return CFR_OK;
+}
+
+int64_t cfr_host_layout_bytes(const cfr_host_layout* layout, const char* name) {
+    if (layout == nullptr || name == nullptr) return CFR_EINVAL;
+    const auto a = host_array(layout->L, name);
+    return a.second < 0 ? CFR_EINVAL : a.second;
+}
+
+int cfr_host_layout_get(const cfr_host_layout* layout, const char* name, void* out, int64_t bytes) {
+    if (layout == nullptr || name == nullptr) return set_err(CFR_EINVAL, "null argument");
+    const auto a = host_array(layout->L, name);
+    if (a.second < 0) return set_err(CFR_EINVAL, "unknown layout array");
+    if (bytes != a.second || (bytes > 0 && out == nullptr)) return set_err(CFR_EINVAL, "wrong output size");
+    if (bytes > 0) std::memcpy(out, a.first, static_cast<size_t>(bytes));
+    return CFR_OK;
+}
+
+int cfr_host_layout_destroy(cfr_host_layout* layout) {
+    delete layout;
+    return CFR_OK;
+}
+
+}  // extern "C"

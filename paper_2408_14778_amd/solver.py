@@ -1,0 +1,217 @@
+"""Python face of the library: a CFR solver over one game on one GPU.
+
+PyTorch supplies only the workspace (a uint8 device tensor) and the stream;
+every step of the computation runs in the gfx950 library behind the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _native as N
+
+VARIANTS = {"vanilla": N.CFR_VANILLA, "cfr+": N.CFR_PLUS}
+AVERAGING = {None: N.CFR_AVG_DEFAULT, "uniform": N.CFR_AVG_UNIFORM, "linear": N.CFR_AVG_LINEAR}
+
+LAYOUT_DTYPES = {
+    "level_offset": np.int32, "node_id": np.int32, "parent": np.int32, "child_begin": np.int32,
+    "node_player": np.int8, "node_infoset": np.int32, "node_edge": np.int32,
+    "infoset_id": np.int32, "infoset_player": np.int8, "q_offset": np.int32,
+    "chance_id": np.int32, "cq_offset": np.int32, "member_offset": np.int32,
+    "members": np.int32, "chance_prob": np.float32, "payoff": np.float32, "q_input": np.int32,
+}
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class GameArgs:
+    """Holds contiguous copies of a game's arrays and the ctypes struct pointing at them."""
+
+    def __init__(self, game):
+        self.parent = np.ascontiguousarray(game.parent, dtype=np.int32)
+        self.node_infoset = np.ascontiguousarray(game.node_infoset, dtype=np.int32)
+        self.node_action = np.ascontiguousarray(game.node_action, dtype=np.int32)
+        self.infoset_player = np.ascontiguousarray(game.infoset_player, dtype=np.int8)
+        self.infoset_num_actions = np.ascontiguousarray(game.infoset_num_actions, dtype=np.int32)
+        self.chance_prob = np.ascontiguousarray(game.chance_prob, dtype=np.float64)
+        if self.chance_prob.size == 0:
+            self.chance_prob = np.zeros(1, dtype=np.float64)
+        self.payoff_u1 = np.ascontiguousarray(game.payoff_u1, dtype=np.float64)
+        self.payoff_u2 = (None if game.payoff_u2 is None
+                          else np.ascontiguousarray(game.payoff_u2, dtype=np.float64))
+        self.struct = N.CfrGame(
+            n_nodes=self.parent.shape[0],
+            parent=_ptr(self.parent, ctypes.c_int32),
+            node_infoset=_ptr(self.node_infoset, ctypes.c_int32),
+            node_action=_ptr(self.node_action, ctypes.c_int32),
+            n_infosets=self.infoset_player.shape[0],
+            infoset_player=_ptr(self.infoset_player, ctypes.c_int8),
+            infoset_num_actions=_ptr(self.infoset_num_actions, ctypes.c_int32),
+            chance_prob=_ptr(self.chance_prob, ctypes.c_double),
+            payoff_u1=_ptr(self.payoff_u1, ctypes.c_double),
+            payoff_u2=(None if self.payoff_u2 is None else _ptr(self.payoff_u2, ctypes.c_double)),
+        )
+
+
+def make_config(variant: str = "vanilla", averaging=None, graph: bool = True) -> N.CfrConfig:
+    if variant not in VARIANTS:
+        raise ValueError(f"variant must be one of {list(VARIANTS)}")
+    cfg = N.CfrConfig()
+    cfg.variant = VARIANTS[variant]
+    cfg.averaging = AVERAGING[averaging]
+    cfg.flags = 0 if graph else N.CFR_FLAG_NO_GRAPH
+    return cfg
+
+
+def plan(game, variant: str = "vanilla", averaging=None) -> dict:
+    lib = N.load()
+    args = GameArgs(game)
+    cfg = make_config(variant, averaging)
+    info = N.CfrPlanInfo()
+    N.check(lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg), ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
+
+
+def host_layout(game, names=None) -> dict:
+    """The canonical layout flattened on the host by the library (no GPU needed)."""
+    lib = N.load()
+    args = GameArgs(game)
+    h = ctypes.c_void_p()
+    N.check(lib.cfr_host_layout_create(ctypes.byref(args.struct), ctypes.byref(h)))
+    try:
+        out = {}
+        for name in (names or LAYOUT_DTYPES):
+            nbytes = lib.cfr_host_layout_bytes(h, name.encode())
+            if nbytes < 0:
+                raise KeyError(name)
+            dt = np.dtype(LAYOUT_DTYPES[name])
+            arr = np.empty(nbytes // dt.itemsize, dtype=dt)
+            N.check(lib.cfr_host_layout_get(h, name.encode(), arr.ctypes.data_as(ctypes.c_void_p),
+                                            nbytes))
+            out[name] = arr
+        return out
+    finally:
+        lib.cfr_host_layout_destroy(h)
+
+
+class Solver:
+    """CFR (vanilla or CFR+) over one game, resident on one GPU."""
+
+    def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
+                 graph: bool = True, stream=None):
+        import torch
+
+        self._lib = N.load()
+        self.variant = variant
+        args = GameArgs(game)
+        cfg = make_config(variant, averaging, graph)
+        info = N.CfrPlanInfo()
+        N.check(self._lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg),
+                                   ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8,
+                                     device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        N.check(self._lib.cfr_build(ctypes.byref(args.struct), ctypes.byref(cfg),
+                                    ctypes.c_void_p(self.workspace.data_ptr()),
+                                    ctypes.c_size_t(int(info.workspace_bytes)),
+                                    ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(handle)))
+        self._h = handle
+        self.n_q = int(info.n_q)
+        self.n_nodes = int(info.n_nodes)
+
+    # -- iteration ------------------------------------------------------------------
+    def iterate(self, n: int = 1) -> None:
+        N.check(self._lib.cfr_iterate(self._h, int(n)))
+
+    def iterate_timed(self, n: int) -> dict:
+        """n iterations with hipEvents around every kernel launch: {kernel: (launches, ms)}."""
+        kinds = 16
+        ms = np.zeros(kinds, dtype=np.float64)
+        cnt = np.zeros(kinds, dtype=np.int64)
+        N.check(self._lib.cfr_iterate_timed(self._h, int(n), _ptr(ms, ctypes.c_double),
+                                            _ptr(cnt, ctypes.c_int64), kinds))
+        out = {}
+        for k in range(kinds):
+            name = self._lib.cfr_kernel_name(k).decode()
+            if name and cnt[k]:
+                out[name] = (int(cnt[k]), float(ms[k]))
+        return out
+
+    def synchronize(self) -> None:
+        self.stream.synchronize()
+
+    # -- results --------------------------------------------------------------------
+    def average_strategy(self) -> np.ndarray:
+        out = np.empty(self.n_q, dtype=np.float32)
+        N.check(self._lib.cfr_average_strategy(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                               self.n_q, 0))
+        return out
+
+    def current_strategy(self) -> np.ndarray:
+        """sigma^(T+1): the strategy the next iteration plays (input pair order)."""
+        out = np.empty(self.n_q, dtype=np.float32)
+        N.check(self._lib.cfr_current_strategy(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                               self.n_q, 0))
+        return out
+
+    def average_strategy_device(self, out) -> None:
+        """Write the average strategy into a float32 device tensor of n_q elements."""
+        assert out.dtype.itemsize == 4 and out.numel() == self.n_q and out.is_cuda
+        N.check(self._lib.cfr_average_strategy(self._h, ctypes.c_void_p(out.data_ptr()),
+                                               self.n_q, 1))
+
+    def exploitability(self) -> dict:
+        expl = ctypes.c_double()
+        br = (ctypes.c_double * 2)()
+        N.check(self._lib.cfr_exploitability(self._h, ctypes.byref(expl), br))
+        return {"expl": expl.value, "br1": br[0], "br2": br[1], "nash_conv": br[0] + br[1]}
+
+    def get_state(self):
+        T = ctypes.c_int64()
+        R = np.empty(self.n_q, dtype=np.float32)
+        S = np.empty(self.n_q, dtype=np.float32)
+        N.check(self._lib.cfr_get_state(self._h, ctypes.byref(T), _ptr(R, ctypes.c_float),
+                                        _ptr(S, ctypes.c_float), self.n_q))
+        return int(T.value), R, S
+
+    def set_state(self, T: int, R, S) -> None:
+        R = np.ascontiguousarray(R, dtype=np.float32)
+        S = np.ascontiguousarray(S, dtype=np.float32)
+        N.check(self._lib.cfr_set_state(self._h, int(T), _ptr(R, ctypes.c_float),
+                                        _ptr(S, ctypes.c_float), R.shape[0]))
+
+    def layout(self, name: str) -> np.ndarray:
+        nbytes = self._lib.cfr_layout_bytes(self._h, name.encode())
+        if nbytes < 0:
+            raise KeyError(name)
+        dt = np.dtype(LAYOUT_DTYPES[name])
+        out = np.empty(nbytes // dt.itemsize, dtype=dt)
+        N.check(self._lib.cfr_get_layout(self._h, name.encode(),
+                                          out.ctypes.data_as(ctypes.c_void_p), nbytes))
+        return out
+
+    def node_values(self):
+        """(u1[N], reach[N, 3]) of the last iteration, canonical node order."""
+        u1 = np.empty(self.n_nodes, dtype=np.float32)
+        reach = np.empty((self.n_nodes, 3), dtype=np.float32)
+        N.check(self._lib.cfr_get_node_values(self._h, _ptr(u1, ctypes.c_float),
+                                              _ptr(reach, ctypes.c_float), self.n_nodes))
+        return u1, reach
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            N.check(self._lib.cfr_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,135 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports every
+entry point the header declares, validation reports the documented error
+codes, and the host flattener emits the oracle's canonical layout bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import games
+from oracle.layout import canonical_layout
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2408_14778_amd import _native
+    return _native.load()
+
+
+def test_every_declared_symbol_is_exported():
+    header = open(os.path.join(ROOT, "include", "cfr.h")).read()
+    names = set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(cfr_\w+)\s*\(", header, re.M))
+    assert len(names) >= 19
+    lib = _lib()
+    from paper_2408_14778_amd import _native
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+        assert n in _native.SIGNATURES, f"{n} has no binding"
+
+
+def test_plan_sizes():
+    from paper_2408_14778_amd import plan
+    p = plan(games.kuhn_like(3, "joint"))
+    assert (p["n_nodes"], p["n_terminals"], p["n_infosets"], p["n_q"], p["depth"]) == (55, 30, 12, 24, 4)
+    assert p["level_pure"] == 1 and p["workspace_bytes"] > 0
+    p = plan(games.leduc_like(6, 2, deal="joint"))
+    assert (p["n_nodes"], p["n_terminals"], p["n_infosets"], p["n_q"]) == (100981, 59928, 4032, 9408)
+
+
+def _copy(g):
+    import copy
+    return copy.deepcopy(g)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda g: g.parent.__setitem__(0, 3), "CFR_ENOTTREE"),                 # two roots / cycle
+    (lambda g: g.parent.__setitem__(5, 5), "CFR_ENOTTREE"),                 # self parent
+    (lambda g: g.node_action.__setitem__(2, 1), "CFR_EACTION"),              # duplicate action
+    (lambda g: g.node_action.__setitem__(2, 7), "CFR_EACTION"),              # out of range
+    (lambda g: g.chance_prob.__setitem__(0, 0.5), "CFR_ECHANCE"),            # sum != 1
+    (lambda g: g.chance_prob.__setitem__(0, -0.1), "CFR_ECHANCE"),
+    (lambda g: setattr(g, "payoff_u2", g.payoff_u2 + 1.0), "CFR_EZEROSUM"),
+    (lambda g: g.infoset_player.__setitem__(1, 5), "CFR_EINVAL"),
+])
+def test_validation_error_codes(mutate, code):
+    from paper_2408_14778_amd import CfrError, plan
+    g = _copy(games.kuhn_like(3, "joint"))
+    mutate(g)
+    with pytest.raises(CfrError) as e:
+        plan(g)
+    assert str(e.value).startswith(code)
+
+
+def test_terminal_with_infoset_rejected():
+    from paper_2408_14778_amd import CfrError, plan
+    g = _copy(games.kuhn_like(3, "joint"))
+    term = int(np.flatnonzero(g.node_infoset < 0)[0])
+    g.node_infoset[term] = 0
+    with pytest.raises(CfrError, match="CFR_ENOTTREE"):
+        plan(g)
+
+
+def test_non_level_pure_game_is_flagged():
+    # one infoset whose two members sit at depths 1 and 2
+    from paper_2408_14778_amd import plan
+    b = games.GameBuilder("skew")
+    root = b.node(-1, -1)
+    b.decide(root, b.infoset_id("c", 0, 2, [0.5, 0.5]))
+    x = b.node(root, 0)
+    y = b.node(root, 1)
+    hp = b.infoset_id("p1", 1, 2)
+    b.decide(x, hp)
+    b.decide(y, b.infoset_id("c2", 0, 1, [1.0]))
+    z = b.node(y, 0)
+    b.decide(z, hp)
+    for v in (x, z):
+        for a in range(2):
+            b.terminal(b.node(v, a), float(a))
+    p = plan(b.build())
+    assert p["level_pure"] == 0
+
+
+LAYOUT_GAMES = [
+    lambda: games.kuhn_like(3, "joint"),
+    lambda: games.kuhn_like(3, "sequential").permuted(4),
+    lambda: games.leduc_like(3, 2, deal="sequential"),
+    lambda: games.leduc_like(6, 2, deal="joint"),
+    lambda: games.leduc_like(6, 2, deal="joint").permuted(9),
+    lambda: games.random_game(11, deal="sequential", depth=5),
+    lambda: games.random_game(12, deal="none", depth=6),
+    lambda: games.rock_paper_scissors(),
+    lambda: games.subgame(103),
+]
+
+
+@pytest.mark.parametrize("maker", LAYOUT_GAMES)
+def test_host_layout_bit_exact(maker):
+    from paper_2408_14778_amd import host_layout
+    g = maker()
+    a = host_layout(g)
+    b = canonical_layout(g)
+    for k, v in a.items():
+        assert v.dtype == b[k].dtype, k
+        assert np.array_equal(v, b[k]), k
+
+
+def test_host_layout_bit_exact_large(large_game):
+    from paper_2408_14778_amd import host_layout
+    a = host_layout(large_game)
+    b = canonical_layout(large_game)
+    for k, v in a.items():
+        assert np.array_equal(v, b[k]), k
+
+
+def test_single_node_game():
+    from paper_2408_14778_amd import host_layout, plan
+    g = games.Game("single", np.array([-1], np.int32), np.array([-1], np.int32),
+                   np.array([-1], np.int32), np.zeros(0, np.int8), np.zeros(0, np.int32),
+                   np.zeros(0), np.array([0.25]))
+    p = plan(g)
+    assert p["n_nodes"] == 1 and p["depth"] == 0 and p["n_q"] == 0
+    lay = host_layout(g)
+    assert lay["level_offset"].tolist() == [0, 1] and lay["payoff"].tolist() == [0.25]

@@ -1,0 +1,272 @@
+"""GPU parity: the gfx950 path, called through the C ABI, against the FP64 oracle.
+
+Tolerances (the FP32 GPU path against FP64 on the same fp32-representable inputs):
+* index and level arrays: bit-exact;
+* one iteration from an identical seeded state: every array (R', S', sigma', node
+  values, reaches) within 1e-6 norm-wise, max|gpu - oracle| / max|oracle|; the next
+  strategy elementwise except at infosets sitting on regret matching's uniform
+  fallback (oracle sum of positive regrets below 1e-6 max|R'|), which are counted;
+* exploitability after T iterations: within 1e-4 of the oracle's.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import games
+from oracle import br, cfr
+from oracle.layout import canonical_layout
+from oracle.sampled import InfosetSampler
+from oracle.tree import Tree
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _solver(g, variant="vanilla", **kw):
+    from paper_2408_14778_amd import Solver
+    return Solver(g, variant, **kw)
+
+
+def _rel(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = max(float(np.abs(ref).max()) if ref.size else 0.0, 1e-30)
+    return float(np.abs(gpu - ref).max()) / scale if ref.size else 0.0
+
+
+SMALL_GAMES = {
+    "kuhn": lambda: games.kuhn_like(3, "joint"),
+    "kuhn_seq": lambda: games.kuhn_like(3, "sequential"),
+    "leduc3x2": lambda: games.leduc_like(3, 2, deal="sequential"),
+    "leduc6x2": lambda: games.leduc_like(6, 2, deal="joint"),
+    "rand_joint": lambda: games.random_game(21, deal="joint", depth=5, n_types=(3, 3)),
+    "rand_seq": lambda: games.random_game(22, deal="sequential", depth=6),
+    "rand_perfect": lambda: games.random_game(23, deal="none", depth=7),
+    "rps": lambda: games.rock_paper_scissors(),
+    "subgame": lambda: games.subgame(102),
+}
+
+
+@pytest.mark.parametrize("name", ["kuhn", "leduc6x2", "rand_seq", "subgame"])
+def test_device_layout_bit_exact(name):
+    g = SMALL_GAMES[name]()
+    s = _solver(g)
+    ref = canonical_layout(g)
+    for k in ("level_offset", "node_id", "parent", "child_begin", "node_player", "node_infoset",
+              "node_edge", "infoset_id", "infoset_player", "q_offset", "chance_id", "cq_offset",
+              "member_offset", "members", "chance_prob", "payoff", "q_input"):
+        assert np.array_equal(s.layout(k), ref[k]), k
+
+
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
+@pytest.mark.parametrize("name", sorted(SMALL_GAMES))
+def test_one_iteration_parity(name, variant):
+    g = SMALL_GAMES[name]()
+    T, R, S = games.random_state(g, seed=len(name), nonnegative=(variant == "cfr+"))
+    s = _solver(g, variant)
+    s.set_state(T, R, S)
+    s.iterate(1)
+    T2, R2, S2 = s.get_state()
+    sig2 = s.current_strategy()
+    u1, reach = s.node_values()
+
+    t = Tree(g)
+    st = cfr.State(T, [float(x) for x in R], [float(x) for x in S])
+    new, info = cfr.iterate(t, st, variant, record=True)
+    assert T2 == T + 1
+    assert _rel(R2, new.R) <= 1e-6
+    assert _rel(S2, new.S) <= 1e-6
+    nid = s.layout("node_id")
+    ref_u = np.asarray(info["node_u"])[nid]
+    assert _rel(u1, ref_u) <= 1e-6
+    ref_reach = np.asarray([info["node_reach"][v] for v in nid])
+    dec = s.layout("node_player") >= 0
+    for k in range(3):
+        assert _rel(reach[dec, k], ref_reach[dec, k]) <= 1e-6
+    # next strategy, away from the uniform-fallback discontinuity
+    ref_sig = np.asarray(info["next_sigma"])
+    scale = max(float(np.abs(new.R).max()), 1e-30)
+    skipped = 0
+    for h in t.rational:
+        o, k = t.qoff[h], t.nact[h]
+        pos = sum(max(x, 0.0) for x in new.R[o:o + k])
+        if 0.0 < pos < 1e-6 * scale:
+            skipped += 1
+            continue
+        np.testing.assert_allclose(sig2[o:o + k], ref_sig[o:o + k], rtol=0, atol=2e-6)
+    assert skipped <= max(1, len(t.rational) // 100)
+
+
+@pytest.mark.parametrize("name,variant,iters", [
+    ("kuhn", "vanilla", 10000),
+    ("kuhn", "cfr+", 1000),
+    ("rand_joint", "vanilla", 600),
+    ("rand_seq", "cfr+", 600),
+    ("leduc3x2", "vanilla", 200),
+])
+def test_exploitability_after_T_iterations(name, variant, iters):
+    g = SMALL_GAMES[name]()
+    s = _solver(g, variant)
+    s.iterate(iters)
+    e = s.exploitability()
+    t = Tree(g)
+    st = cfr.solve(t, iters, variant)
+    ref = br.exploitability(t, cfr.average_strategy(t, st.S))
+    assert abs(e["expl"] - ref["expl"]) <= 1e-4, (e, ref)
+    assert e["expl"] >= -1e-6
+
+
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
+def test_medium_game_exploitability_against_golden(variant):
+    gold = json.load(open(os.path.join(HERE, "golden", "medium_game_expl.json")))
+    ref = gold[variant]
+    g = games.leduc_like(6, 2, deal="joint")
+    s = _solver(g, variant)
+    s.iterate(ref["iterations"])
+    e = s.exploitability()
+    assert abs(e["expl"] - ref["expl"]) <= 1e-4, (e, ref)
+
+
+@pytest.mark.parametrize("name", ["kuhn", "leduc3x2", "rand_seq", "subgame"])
+def test_best_response_on_the_gpu_average(name):
+    g = SMALL_GAMES[name]()
+    s = _solver(g, "cfr+")
+    s.iterate(37)
+    avg = s.average_strategy().astype(np.float64)
+    e = s.exploitability()
+    t = Tree(g)
+    ref = br.exploitability(t, avg.tolist())
+    scale = max(1.0, float(np.abs(g.payoff_u1).max()))
+    assert abs(e["br1"] - ref["br1"]) <= 1e-5 * scale
+    assert abs(e["br2"] - ref["br2"]) <= 1e-5 * scale
+    # the average strategy itself matches the oracle's
+    st = cfr.solve(t, 37, "cfr+")
+    assert _rel(avg, cfr.average_strategy(t, st.S)) <= 1e-5
+
+
+def test_graph_replay_matches_direct_launches():
+    g = games.leduc_like(3, 2, deal="sequential")
+    a = _solver(g, "cfr+", graph=True)
+    b = _solver(g, "cfr+", graph=False)
+    for _ in range(3):
+        a.iterate(7)
+        b.iterate(7)
+        Ta, Ra, Sa = a.get_state()
+        Tb, Rb, Sb = b.get_state()
+        assert Ta == Tb
+        assert _rel(Ra, Rb) <= 1e-6 and _rel(Sa, Sb) <= 1e-6
+
+
+def test_average_strategy_to_device():
+    import torch
+    g = games.kuhn_like(3, "joint")
+    s = _solver(g)
+    s.iterate(5)
+    out = torch.empty(s.n_q, dtype=torch.float32, device="cuda")
+    s.average_strategy_device(out)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), s.average_strategy())
+
+
+def test_state_roundtrip_and_resume():
+    g = games.random_game(31, deal="joint", depth=5)
+    a = _solver(g, "cfr+")
+    a.iterate(25)
+    T, R, S = a.get_state()
+    b = _solver(g, "cfr+")
+    b.set_state(T, R, S)
+    a.iterate(10)
+    b.iterate(10)
+    Ta, Ra, Sa = a.get_state()
+    Tb, Rb, Sb = b.get_state()
+    assert Ta == Tb == 35
+    assert _rel(Rb, Ra) <= 1e-6 and _rel(Sb, Sa) <= 1e-6
+
+
+def test_single_node_and_single_action_games():
+    g = games.Game("single", np.array([-1], np.int32), np.array([-1], np.int32),
+                   np.array([-1], np.int32), np.zeros(0, np.int8), np.zeros(0, np.int32),
+                   np.zeros(0), np.array([0.25]))
+    s = _solver(g)
+    s.iterate(3)
+    e = s.exploitability()
+    assert e["br1"] == pytest.approx(0.25) and e["br2"] == pytest.approx(-0.25)
+    g = games.random_game(5, deal="none", depth=4, max_actions=1)
+    s = _solver(g)
+    s.iterate(2)
+    assert s.exploitability()["expl"] == pytest.approx(0.0, abs=1e-6)
+
+
+def test_non_level_pure_game_iterates_but_refuses_exploitability():
+    from paper_2408_14778_amd import CfrError
+    b = games.GameBuilder("skew")
+    root = b.node(-1, -1)
+    b.decide(root, b.infoset_id("c", 0, 2, [0.5, 0.5]))
+    x, y = b.node(root, 0), b.node(root, 1)
+    hp = b.infoset_id("p1", 1, 2)
+    b.decide(x, hp)
+    b.decide(y, b.infoset_id("c2", 0, 1, [1.0]))
+    z = b.node(y, 0)
+    b.decide(z, hp)
+    for v, base in ((x, 0.0), (z, 1.0)):
+        for a in range(2):
+            b.terminal(b.node(v, a), base + a)
+    g = b.build()
+    s = _solver(g)
+    s.iterate(4)
+    t = Tree(g)
+    st = cfr.solve(t, 4)
+    _, R, S = s.get_state()
+    assert _rel(R, st.R) <= 1e-6 and _rel(S, st.S) <= 1e-6
+    with pytest.raises(CfrError, match="CFR_ELEVEL"):
+        s.exploitability()
+
+
+def test_large_game_one_iteration_sampled(large_game):
+    """Full-size large workload (21,509,281 nodes), CFR+, seeded state: R', S' of sampled
+    infosets against the oracle computed one infoset at a time, plus whole-array
+    properties. FP32 error bound: D levels of products and sums with payoffs up to 400
+    give about D * 2^-24 relative to the largest magnitudes; 1e-5 norm-wise covers it."""
+    g = large_game
+    T, R, S = games.random_state(g, seed=2, nonnegative=True)
+    s = _solver(g, "cfr+")
+    s.set_state(T, R, S)
+    s.iterate(1)
+    T2, R2, S2 = s.get_state()
+    sig = s.current_strategy()
+    assert T2 == T + 1
+    assert np.all(R2 >= 0) and np.all(S2 >= S - 1e-6 * np.abs(S).max())
+    samp = InfosetSampler(g)
+    rng = np.random.default_rng(2)
+    rational = np.flatnonzero(g.infoset_player != 0)
+    # infosets at the two deepest decision levels have small subtrees
+    lay = s.layout("level_offset")
+    nid = s.layout("node_id")
+    deep_nodes = nid[lay[-4]:lay[-2]]
+    deep_h = np.unique(g.node_infoset[deep_nodes])
+    deep_h = deep_h[(deep_h >= 0) & (g.infoset_player[np.maximum(deep_h, 0)] != 0)]
+    picks = rng.choice(deep_h, size=24, replace=False).tolist()
+    ref_R, gpu_R, ref_S, gpu_S = [], [], [], []
+    for h in picks:
+        out = samp.update(R, S, T, int(h), "cfr+")
+        ref_R += out["R"]
+        ref_S += out["S"]
+        gpu_R += R2[out["q"]].tolist()
+        gpu_S += S2[out["q"]].tolist()
+    err_R, err_S = _rel(gpu_R, ref_R), _rel(gpu_S, ref_S)
+    print(f"large game sampled relative error: R {err_R:.3e} S {err_S:.3e}", flush=True)
+    assert err_R <= 1e-5 and err_S <= 1e-5
+    # next strategy sums to one on every infoset
+    qo = np.concatenate([[0], np.cumsum(g.infoset_num_actions[rational])])
+    sums = np.add.reduceat(sig.astype(np.float64), qo[:-1])
+    assert np.abs(sums - 1.0).max() < 1e-5
+
+
+def test_large_game_exploitability_is_nonnegative(large_game):
+    s = _solver(large_game, "cfr+")
+    s.iterate(3)
+    e = s.exploitability()
+    assert np.isfinite(e["expl"]) and e["expl"] >= -1e-3
