@@ -33,43 +33,68 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(lay: dict, kernel: str) -> float:
-    """Bytes one average launch of `kernel` must move, from the layout's level counts.
-
-    value_level (per level, internal parent p with children c): child_begin 4, node_player 1
-    for every node of the level, value write 4 per internal node, reach 12 + infoset 4 per
-    player node; per child c: node_edge 4, value 4, sigma gather 4, and for a player child
-    the regret accumulation 8 (read + write); pibar 8 per player node.
-    reach_level (per level): node_player 1 per node; per decision node: parent 4, edge 4,
-    sigma gather 4, parent reach 12, reach write 12.
-    infoset_update: per pair R 8, S 8, rtilde 8, sigma 8; per infoset q_offset 4, pibar 8.
-    """
+def level_counts(lay: dict) -> list:
+    """Per level: nodes, decision nodes, player nodes (members), chance nodes, children of
+    player nodes, children of chance nodes, infosets, infoset-action pairs, and the number
+    of distinct parents of the level's decision nodes."""
     lo = lay["level_offset"]
     player = lay["node_player"]
-    D = len(lo) - 2
-    if kernel == "value_level":
-        tot = 0.0
-        for l in range(D):
-            a, b = lo[l], lo[l + 1]
-            pl = player[a:b]
-            n_int = int((pl >= 0).sum())
-            n_play = int((pl >= 1).sum())
-            ca, cb = lo[l + 1], lo[l + 2]
-            par_pl = player[lay["parent"][ca:cb]]
-            n_ch = cb - ca
-            n_pch = int((par_pl >= 1).sum())
-            tot += (b - a) * 1 + n_int * (4 + 4) + n_play * (12 + 4 + 8) + n_ch * 12 + n_pch * 8
-        return tot / max(D, 1)
-    if kernel == "reach_level":
-        tot = 0.0
-        for l in range(1, D):
-            a, b = lo[l], lo[l + 1]
-            n_dec = int((player[a:b] >= 0).sum())
-            tot += (b - a) * 1 + n_dec * (4 + 4 + 4 + 12 + 12)
+    cb = lay["child_begin"].astype(np.int64)
+    nch = np.diff(cb)
+    mo = lay["member_offset"]
+    first = lay["members"][mo[:-1]] if len(mo) > 1 else np.zeros(0, dtype=np.int64)
+    hlev = np.searchsorted(lo, first, side="right") - 1
+    qo = lay["q_offset"].astype(np.int64)
+    qk = np.diff(qo)
+    parent = lay["parent"]
+    out = []
+    for l in range(len(lo) - 1):
+        a, b = lo[l], lo[l + 1]
+        pl = player[a:b]
+        dec = pl >= 0
+        out.append({
+            "nodes": b - a, "decision": int(dec.sum()), "player": int((pl >= 1).sum()),
+            "chance": int((pl == 0).sum()),
+            "player_children": int(nch[a:b][pl >= 1].sum()),
+            "chance_children": int(nch[a:b][pl == 0].sum()),
+            "infosets": int((hlev == l).sum()), "q": int(qk[hlev == l].sum()),
+            "parents": int(len(np.unique(parent[a:b][dec]))) if l > 0 else 0,
+        })
+    return out
+
+
+def algorithmic_bytes(lay: dict, kernel: str, counts: list) -> float:
+    """Bytes one average launch of `kernel` must move (each distinct datum once).
+
+    block_reach (level l, one thread per node): node kind 1 B per node; per decision node
+    the parent index 4, edge index 4, edge probability 4 and its reach write 12; the
+    parents' reach 12 per distinct parent.
+    block_up (level l, one thread per infoset or chance node): per infoset its pair offset
+    4, player 1 and member offset 4; per pair sigma 4, R read+write 8, S read+write 8 and
+    the next sigma 4; per member its index 4, child begin 4, child stride 4, reach 12, value
+    write 4 and one value 4 per child; per chance node its index, base and count 12, value
+    write 4 and per child a listed index 4, probability 4 and value 4.
+    value_level / reach_level / infoset_update: the breadth-first node engine's kernels,
+    counted the same way (its regret and player-reach accumulation add 8 B per player child
+    and 8 B per player node).
+    """
+    D = len(counts) - 1
+    if kernel in ("block_reach", "reach_level"):
+        tot = sum(c["nodes"] + c["decision"] * 24 + c["parents"] * 12 for c in counts[1:D])
         return tot / max(D - 1, 1)
+    if kernel == "block_up":
+        levels = [c for c in counts if c["infosets"] + c["chance"] > 0]
+        tot = sum(c["infosets"] * 9 + c["q"] * 24 + c["player"] * 28 + c["player_children"] * 4
+                  + c["chance"] * 16 + c["chance_children"] * 12 for c in levels)
+        return tot / max(len(levels), 1)
+    if kernel == "value_level":
+        tot = sum(c["nodes"] + c["decision"] * 8 + c["player"] * (12 + 4 + 8)
+                  + (c["player_children"] + c["chance_children"]) * 12
+                  + c["player_children"] * 8 for c in counts[:D])
+        return tot / max(D, 1)
     if kernel == "infoset_update":
-        Hp = len(lay["q_offset"]) - 1
-        Qp = int(lay["q_offset"][-1])
+        Qp = sum(c["q"] for c in counts)
+        Hp = sum(c["infosets"] for c in counts)
         return Qp * 32 + Hp * 12
     return 0.0
 
@@ -105,6 +130,7 @@ def main() -> int:
     ap.add_argument("--timed-kernel-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exploitability", action="store_true")
+    ap.add_argument("--engine", choices=["auto", "node"], default="auto")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -122,7 +148,7 @@ def main() -> int:
     g = games.large_game()
     log(f"game built: {g.n_nodes} nodes in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    s = Solver(g, "cfr+", device="cuda:0")
+    s = Solver(g, "cfr+", device="cuda:0", engine=args.engine)
     torch.cuda.synchronize()
     log(f"solver built (flatten + upload + graph capture) in {time.perf_counter() - t0:.1f}s; "
         f"workspace {s.info['workspace_bytes'] / 2**30:.2f} GiB")
@@ -141,11 +167,13 @@ def main() -> int:
 
     # per-kernel durations, hipEvents around every launch on the solver's stream
     kt = s.iterate_timed(args.timed_kernel_steps)
-    lay = {k: s.layout(k) for k in ("level_offset", "node_player", "parent", "q_offset")}
+    lay = {k: s.layout(k) for k in ("level_offset", "node_player", "parent", "q_offset",
+                                     "child_begin", "member_offset", "members")}
+    counts = level_counts(lay)
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
     avg_s = total_ms / launches * 1e-3
-    bytes_per_launch = algorithmic_bytes(lay, dom)
+    bytes_per_launch = algorithmic_bytes(lay, dom, counts)
     achieved = bytes_per_launch / avg_s / 1e9
     kernels = {k: {"launches": n, "avg_us": ms / n * 1e3,
                    "share": ms / sum(v[1] for v in kt.values())} for k, (n, ms) in kt.items()}
@@ -167,7 +195,8 @@ def main() -> int:
         "config": {"workload": "large poker game: 13 ranks, 3 rounds, fold/call/pot/all-in, "
                                "cap 3, stack 400, CFR+ (linear averaging), seed 2",
                    "nodes": g.n_nodes, "infosets": s.info["n_infosets"], "q": s.info["n_q"],
-                   "depth": s.info["depth"]},
+                   "depth": s.info["depth"],
+                   "engine": ["node", "public-block"][s.info["engine"]]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},

@@ -73,7 +73,9 @@ enum { CFR_AVG_DEFAULT = -1, CFR_AVG_UNIFORM = 0, CFR_AVG_LINEAR = 1 };
 /* Averaging weight of iteration t (1-based): 1 (uniform, Eq. average_strategy_profile) or t
  * (linear). DEFAULT = uniform for vanilla, linear for CFR+. */
 
-#define CFR_FLAG_NO_GRAPH 1u /* enqueue kernels directly instead of replaying a captured graph */
+#define CFR_FLAG_NO_GRAPH 1u    /* enqueue kernels directly instead of replaying a captured graph */
+#define CFR_FLAG_NODE_ENGINE 2u  /* use the breadth-first node engine even where the public-block
+                                    engine applies (level-pure infosets, at most 16 actions) */
 
 typedef struct cfr_config {
     int32_t variant;   /* CFR_VANILLA or CFR_PLUS */
@@ -93,7 +95,7 @@ typedef struct cfr_plan_info {
     int32_t max_actions;
     int32_t depth;             /* D: deepest level */
     int32_t level_pure;        /* 1 if every infoset lies on one level */
-    int32_t reserved;
+    int32_t engine;            /* 0: breadth-first node engine, 1: public-block engine */
     int64_t workspace_bytes;   /* device bytes cfr_build needs */
 } cfr_plan_info;
 
@@ -158,7 +160,10 @@ int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes)
 
 /* Host-only flattening, for checking the canonical layout without a GPU: build the layout
  * of `game` on the host (validation as in cfr_plan), then read arrays by the names listed for
- * cfr_get_layout. The handle owns host memory only. */
+ * cfr_get_layout. For level-pure games the public-block execution plan is built too and its
+ * arrays are readable as x_canon_of, x_parent, x_edge, x_meta, x_child_begin, x_child_stride,
+ * x_child_list, x_infoset_canon, x_q_offset, x_member_offset, x_members, x_h_level_offset,
+ * x_chance_nodes, x_c_level_offset, x_q_input. The handle owns host memory only. */
 typedef struct cfr_host_layout cfr_host_layout;
 int cfr_host_layout_create(const cfr_game* game, cfr_host_layout** out);
 int64_t cfr_host_layout_bytes(const cfr_host_layout* layout, const char* name);

@@ -19,6 +19,7 @@ ERRORS = {
 CFR_VANILLA, CFR_PLUS = 0, 1
 CFR_AVG_DEFAULT, CFR_AVG_UNIFORM, CFR_AVG_LINEAR = -1, 0, 1
 CFR_FLAG_NO_GRAPH = 1
+CFR_FLAG_NODE_ENGINE = 2
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i8p = ctypes.POINTER(ctypes.c_int8)
@@ -62,7 +63,7 @@ class CfrPlanInfo(ctypes.Structure):
         ("max_actions", ctypes.c_int32),
         ("depth", ctypes.c_int32),
         ("level_pure", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("engine", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_int64),
     ]
 

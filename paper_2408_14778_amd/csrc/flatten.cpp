@@ -150,9 +150,12 @@ int plan_sizes(const cfr_game& g, Layout& L, std::string& err) {
     if (rc != CFR_OK) return rc;
     L.N = g.n_nodes;
     L.D = static_cast<int32_t>(w.level_offset.size()) - 2;
-    L.n_terminals = 0;
-    for (int64_t v = 0; v < g.n_nodes; ++v)
+    L.n_terminals = L.n_chance_nodes = L.n_members = 0;
+    for (int64_t v = 0; v < g.n_nodes; ++v) {
         if (w.child_off[v + 1] == w.child_off[v]) ++L.n_terminals;
+        else if (g.infoset_player[g.node_infoset[v]] == 0) ++L.n_chance_nodes;
+        else ++L.n_members;
+    }
     L.Hp = L.Qp = L.H0 = L.Q0 = 0;
     L.max_actions = 0;
     for (int32_t h = 0; h < g.n_infosets; ++h) {
@@ -264,6 +267,9 @@ int flatten(const cfr_game& g, Layout& L, std::string& err) {
         }
     }
     L.child_begin[n] = static_cast<int32_t>(n);
+    L.n_chance_nodes = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (L.node_player[i] == 0) ++L.n_chance_nodes;
     for (int64_t i = 0; i < n; ++i) {
         const int32_t p = L.parent[i];
         if (p < 0) { L.node_edge[i] = -1; continue; }
@@ -280,6 +286,7 @@ int flatten(const cfr_game& g, Layout& L, std::string& err) {
         if (L.node_player[i] >= 1) ++L.member_offset[L.node_infoset[i] + 1];
     for (int64_t h = 0; h < L.Hp; ++h) L.member_offset[h + 1] += L.member_offset[h];
     L.members.resize(L.member_offset[L.Hp]);
+    L.n_members = static_cast<int64_t>(L.members.size());
     {
         std::vector<int32_t> fill(L.member_offset.begin(), L.member_offset.end() - 1);
         for (int64_t i = 0; i < n; ++i)

@@ -22,7 +22,7 @@
 namespace cfr {
 
 struct Layout {
-    int64_t N = 0, n_terminals = 0;
+    int64_t N = 0, n_terminals = 0, n_chance_nodes = 0, n_members = 0;
     int64_t Hp = 0, Qp = 0, H0 = 0, Q0 = 0;
     int32_t D = 0, max_actions = 0;
     bool level_pure = true;

@@ -271,13 +271,14 @@ __global__ void k_gather_q(int64_t Qp, const int32_t* __restrict__ q_input,
 
 }  // namespace
 
-void launch_reset(const Dev& d, hipStream_t st) {
+void launch_reset(const Dev& d, hipStream_t st, bool node_arrays) {
     if (d.Qp > 0) hipLaunchKernelGGL(k_reset_q, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st, d.Qp,
-                                     d.R, d.S, d.rtilde);
-    if (d.Hp > 0) hipLaunchKernelGGL(k_reset_h, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
-                                     d.pibar);
-    hipLaunchKernelGGL(k_reset_nodes, dim3(blocks_for(d.N)), dim3(kBlock), 0, st, d.N,
-                       d.node_player, d.payoff, d.value, d.reach);
+                                     d.R, d.S, node_arrays ? d.rtilde : d.stage);
+    if (d.Hp > 0 && node_arrays)
+        hipLaunchKernelGGL(k_reset_h, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp, d.pibar);
+    if (node_arrays)
+        hipLaunchKernelGGL(k_reset_nodes, dim3(blocks_for(d.N)), dim3(kBlock), 0, st, d.N,
+                           d.node_player, d.payoff, d.value, d.reach);
     if (d.Q0 > 0)
         hipLaunchKernelGGL(k_copy_tail, dim3(blocks_for(d.Q0)), dim3(kBlock), 0, st, d.Q0,
                            d.prob + d.Qp, d.avgprob + d.Qp);
@@ -288,7 +289,7 @@ void launch_reset(const Dev& d, hipStream_t st) {
 void launch_regret_match(const Dev& d, hipStream_t st) {
     if (d.Hp > 0)
         hipLaunchKernelGGL(k_regret_match, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
-                           d.q_offset, d.R, d.prob);
+                           d.sq_offset, d.R, d.prob);
 }
 
 void launch_set_T(const Dev& d, int64_t value, hipStream_t st) {
@@ -339,7 +340,7 @@ void launch_iteration(const Dev& d, const int32_t* lo, int variant, int linear, 
 
 void launch_average(const Dev& d, hipStream_t st) {
     if (d.Hp > 0)
-        hipLaunchKernelGGL(k_average, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp, d.q_offset,
+        hipLaunchKernelGGL(k_average, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp, d.sq_offset,
                            d.S, d.avgprob);
 }
 
@@ -370,13 +371,13 @@ void launch_best_response(const Dev& d, const int32_t* lo, const int32_t* hlo, i
 void launch_scatter_q(const Dev& d, const float* src, float* dst, hipStream_t st) {
     if (d.Qp > 0)
         hipLaunchKernelGGL(k_scatter_q, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st, d.Qp,
-                           d.q_input, src, dst);
+                           d.sq_input, src, dst);
 }
 
 void launch_gather_q(const Dev& d, const float* src, float* dst, hipStream_t st) {
     if (d.Qp > 0)
         hipLaunchKernelGGL(k_gather_q, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st, d.Qp,
-                           d.q_input, src, dst);
+                           d.sq_input, src, dst);
 }
 
 }  // namespace cfr

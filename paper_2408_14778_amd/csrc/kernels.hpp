@@ -44,10 +44,15 @@ struct Dev {
     int32_t* best;          // Hp
     float* stage;           // 2 * Qp (state and average-strategy transfers)
     double* out2;           // 2 best-response values
+    // pair numbering of the state arrays (canonical for the node engine, exec for the
+    // block engine)
+    int32_t* sq_offset;     // Hp + 1
+    int32_t* sq_input;      // Qp
 };
 
 // Zero R, S, accumulators and T; sigma uniform; values at terminals; root reach 1.
-void launch_reset(const Dev& d, hipStream_t st);
+// node_arrays = false skips the canonical per-node state (the block engine resets its own).
+void launch_reset(const Dev& d, hipStream_t st, bool node_arrays = true);
 // sigma = regret matching of R (all infosets).
 void launch_regret_match(const Dev& d, hipStream_t st);
 // Kernel kinds of one iteration, for per-kernel timing.

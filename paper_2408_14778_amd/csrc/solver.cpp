@@ -9,9 +9,16 @@
 #include "../../include/cfr.h"
 #include "flatten.hpp"
 #include "kernels.hpp"
+#include "xkernels.hpp"
+#include "xplan.hpp"
+
+enum { ENGINE_NODE = 0, ENGINE_BLOCK = 1 };
 
 struct cfr_solver {
     cfr::Dev dev{};
+    cfr::XDev xdev{};
+    int engine = ENGINE_NODE;
+    std::vector<int32_t> x_level_offset, x_h_level_offset, x_c_level_offset;
     int variant = CFR_VANILLA;
     int linear = 0;
     bool use_graph = true;
@@ -59,10 +66,25 @@ struct Carve {
     }
 };
 
-// Lays out every device array; with base = nullptr it only measures.
-size_t carve(cfr::Dev& d, void* base, int64_t N, int64_t Hp, int64_t Qp, int64_t H0, int64_t Q0,
-             int64_t M, int32_t D) {
+// Sizes the device arrays depend on.
+struct Sizes {
+    int64_t N = 0, Hp = 0, Qp = 0, H0 = 0, Q0 = 0, M = 0, C = 0, L = 0;
+    int32_t D = 0, max_actions = 0;
+    int engine = ENGINE_NODE;
+};
+
+int choose_engine(bool level_pure, int32_t max_actions, uint32_t flags) {
+    if ((flags & CFR_FLAG_NODE_ENGINE) != 0 || !level_pure || max_actions > 16) return ENGINE_NODE;
+    return ENGINE_BLOCK;
+}
+
+// Lays out every device array; with base = nullptr it only measures. Canonical layout
+// arrays are always present (they are exported); per-iteration state follows the engine.
+size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
     Carve c(base);
+    const int64_t N = z.N, Hp = z.Hp, Qp = z.Qp, H0 = z.H0, Q0 = z.Q0, M = z.M;
+    const int32_t D = z.D;
+    d = cfr::Dev{};
     d.N = N; d.Hp = Hp; d.Qp = Qp; d.H0 = H0; d.Q0 = Q0; d.M = M; d.D = D;
     d.parent = c.take<int32_t>(N);
     d.child_begin = c.take<int32_t>(N + 1);
@@ -83,8 +105,6 @@ size_t carve(cfr::Dev& d, void* base, int64_t N, int64_t Hp, int64_t Qp, int64_t
     d.prob = c.take<float>(Qp + Q0);
     d.R = c.take<float>(Qp);
     d.S = c.take<float>(Qp);
-    d.rtilde = c.take<float>(Qp);
-    d.pibar = c.take<float>(Hp);
     d.value = c.take<float>(N);
     d.reach = c.take<float>(3 * N);
     d.T = c.take<int64_t>(1);
@@ -94,6 +114,43 @@ size_t carve(cfr::Dev& d, void* base, int64_t N, int64_t Hp, int64_t Qp, int64_t
     d.best = c.take<int32_t>(Hp);
     d.stage = c.take<float>(2 * Qp);
     d.out2 = c.take<double>(2);
+    d.sq_offset = d.q_offset;
+    d.sq_input = d.q_input;
+    x = cfr::XDev{};
+    if (z.engine == ENGINE_NODE) {
+        d.rtilde = c.take<float>(Qp);
+        d.pibar = c.take<float>(Hp);
+    } else {
+        x.N = N; x.Hp = Hp; x.Qp = Qp; x.Q0 = Q0; x.M = M; x.L = z.L; x.C = z.C;
+        x.D = D; x.max_actions = z.max_actions;
+        x.parent = c.take<int32_t>(N);
+        x.edge = c.take<int32_t>(N);
+        x.meta = c.take<int8_t>(N);
+        x.child_begin = c.take<int32_t>(N);
+        x.child_stride = c.take<int32_t>(N);
+        x.child_list = c.take<int32_t>(z.L);
+        x.canon_of = c.take<int32_t>(N);
+        x.q_offset = c.take<int32_t>(Hp + 1);
+        x.iplayer = c.take<int8_t>(Hp);
+        x.member_offset = c.take<int32_t>(Hp + 1);
+        x.members = c.take<int32_t>(M);
+        x.chance_nodes = c.take<int32_t>(z.C);
+        x.chance_base = c.take<int32_t>(z.C);
+        x.chance_k = c.take<int32_t>(z.C);
+        x.q_input = c.take<int32_t>(Qp);
+        x.payoff = c.take<float>(N);
+        x.prob = d.prob;
+        x.R = d.R;
+        x.S = d.S;
+        x.value = d.value;
+        x.reach = d.reach;
+        x.T = d.T;
+        x.br_reach = d.br_reach;
+        x.br_value = d.br_value;
+        x.out2 = d.out2;
+        d.sq_offset = x.q_offset;
+        d.sq_input = x.q_input;
+    }
     return (c.off + 255) & ~size_t{255};
 }
 
@@ -111,6 +168,13 @@ int upload(T* dst, const std::vector<T>& src, hipStream_t st) {
     return CFR_OK;
 }
 
+void launch_one_iteration(cfr_solver* s, hipStream_t st, cfr::LaunchTimer* timer) {
+    if (s->engine == ENGINE_BLOCK)
+        cfr::launch_x_iteration(s->xdev, s->variant, s->linear, st, timer);
+    else
+        cfr::launch_iteration(s->dev, s->level_offset.data(), s->variant, s->linear, st, timer);
+}
+
 int capture(cfr_solver* s) {
     hipStream_t cap;
     HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "create capture stream");
@@ -119,7 +183,7 @@ int capture(cfr_solver* s) {
         (void)hipStreamDestroy(cap);
         return hip_err(e, "begin capture");
     }
-    cfr::launch_iteration(s->dev, s->level_offset.data(), s->variant, s->linear, cap);
+    launch_one_iteration(s, cap, nullptr);
     e = hipStreamEndCapture(cap, &s->graph);
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess) return hip_err(e, "end capture");
@@ -141,12 +205,12 @@ int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out)
     std::string err;
     const int rc = cfr::plan_sizes(*game, L, err);
     if (rc != CFR_OK) return set_err(rc, err);
-    int64_t M = 0;
-    for (int64_t v = 0; v < game->n_nodes; ++v) {
-        const int32_t h = game->node_infoset[v];
-        if (h >= 0 && game->infoset_player[h] != 0) ++M;
-    }
+    Sizes z;
+    z.N = L.N; z.Hp = L.Hp; z.Qp = L.Qp; z.H0 = L.H0; z.Q0 = L.Q0; z.M = L.n_members;
+    z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
+    z.engine = choose_engine(L.level_pure, L.max_actions, config ? config->flags : 0u);
     cfr::Dev d{};
+    cfr::XDev x{};
     std::memset(out, 0, sizeof *out);
     out->n_nodes = L.N;
     out->n_terminals = L.n_terminals;
@@ -157,9 +221,36 @@ int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out)
     out->max_actions = L.max_actions;
     out->depth = L.D;
     out->level_pure = L.level_pure ? 1 : 0;
-    out->workspace_bytes = static_cast<int64_t>(carve(d, nullptr, L.N, L.Hp, L.Qp, L.H0, L.Q0, M, L.D));
+    out->engine = z.engine;
+    out->workspace_bytes = static_cast<int64_t>(carve(d, x, nullptr, z));
     return CFR_OK;
 }
+
+namespace {
+
+// Copies the block plan to the device and fills the solver's exec view.
+int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
+    cfr::XDev& x = s->xdev;
+    int rc;
+    if ((rc = upload(x.parent, P.parent, st)) || (rc = upload(x.edge, P.edge, st)) ||
+        (rc = upload(x.meta, P.meta, st)) || (rc = upload(x.child_begin, P.child_begin, st)) ||
+        (rc = upload(x.child_stride, P.child_stride, st)) ||
+        (rc = upload(x.child_list, P.child_list, st)) || (rc = upload(x.canon_of, P.canon_of, st)) ||
+        (rc = upload(x.q_offset, P.q_offset, st)) || (rc = upload(x.iplayer, P.infoset_player, st)) ||
+        (rc = upload(x.member_offset, P.member_offset, st)) ||
+        (rc = upload(x.members, P.members, st)) || (rc = upload(x.chance_nodes, P.chance_nodes, st)) ||
+        (rc = upload(x.q_input, P.q_input, st)) || (rc = upload(x.payoff, P.payoff, st)))
+        return rc;
+    s->x_level_offset = P.level_offset;
+    s->x_h_level_offset = P.h_level_offset;
+    s->x_c_level_offset = P.c_level_offset;
+    x.level_offset_host = s->x_level_offset.data();
+    x.h_level_offset_host = s->x_h_level_offset.data();
+    x.c_level_offset_host = s->x_c_level_offset.data();
+    return CFR_OK;
+}
+
+}  // namespace
 
 int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, size_t bytes,
               void* stream, cfr_solver** out) {
@@ -175,16 +266,27 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     std::string err;
     int rc = cfr::flatten(*game, L, err);
     if (rc != CFR_OK) return set_err(rc, err);
-    const int64_t M = static_cast<int64_t>(L.members.size());
+    Sizes z;
+    z.N = L.N; z.Hp = L.Hp; z.Qp = L.Qp; z.H0 = L.H0; z.Q0 = L.Q0; z.M = L.n_members;
+    z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
+    z.engine = choose_engine(L.level_pure, L.max_actions, cfg.flags);
+    cfr::ExecPlan P;
+    if (z.engine == ENGINE_BLOCK) {
+        rc = cfr::build_exec_plan(L, P, err);
+        if (rc != CFR_OK) return set_err(rc, err);
+    }
     cfr::Dev d{};
-    const size_t need = carve(d, nullptr, L.N, L.Hp, L.Qp, L.H0, L.Q0, M, L.D);
+    cfr::XDev x{};
+    const size_t need = carve(d, x, nullptr, z);
     if (bytes < need)
         return set_err(CFR_ENOMEM, "workspace has " + std::to_string(bytes) + " bytes, needs " +
                                        std::to_string(need));
-    carve(d, workspace, L.N, L.Hp, L.Qp, L.H0, L.Q0, M, L.D);
+    carve(d, x, workspace, z);
 
     auto* s = new cfr_solver();
     s->dev = d;
+    s->xdev = x;
+    s->engine = z.engine;
     s->variant = cfg.variant;
     s->linear = cfg.averaging == CFR_AVG_DEFAULT ? (cfg.variant == CFR_PLUS) : cfg.averaging;
     s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
@@ -222,12 +324,30 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         delete s;
         return rc;
     }
-    cfr::launch_reset(d, st);
+    std::vector<int32_t> cbase, ck;
+    if (s->engine == ENGINE_BLOCK) {
+        // chance units: prob index of action 0 and the action count
+        cbase.resize(P.C);
+        ck.resize(P.C);
+        for (int64_t i = 0; i < P.C; ++i) {
+            const int32_t c = P.canon_of[P.chance_nodes[i]];
+            const int32_t hc = L.node_infoset[c];
+            cbase[i] = static_cast<int32_t>(L.Qp + L.cq_offset[hc]);
+            ck[i] = L.cq_offset[hc + 1] - L.cq_offset[hc];
+        }
+        if ((rc = upload_plan(s, P, st)) || (rc = upload(s->xdev.chance_base, cbase, st)) ||
+            (rc = upload(s->xdev.chance_k, ck, st))) {
+            delete s;
+            return rc;
+        }
+    }
+    cfr::launch_reset(d, st, s->engine == ENGINE_NODE);
+    if (s->engine == ENGINE_BLOCK) cfr::launch_x_reset(s->xdev, st);
     if ((rc = check_hip("reset")) != CFR_OK) {
         delete s;
         return rc;
     }
-    // host vectors are released when L goes out of scope: wait for the copies first
+    // host vectors are released when L and P go out of scope: wait for the copies first
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         delete s;
@@ -247,7 +367,7 @@ int cfr_iterate(cfr_solver* s, int32_t n) {
         if (s->use_graph) {
             HIP_TRY(hipGraphLaunch(s->exec, s->stream), "graph launch");
         } else {
-            cfr::launch_iteration(s->dev, s->level_offset.data(), s->variant, s->linear, s->stream);
+            launch_one_iteration(s, s->stream, nullptr);
             const int rc = check_hip("iteration launch");
             if (rc != CFR_OK) return rc;
         }
@@ -286,7 +406,11 @@ struct EventTimer : cfr::LaunchTimer {
 };
 }  // namespace
 
-const char* cfr_kernel_name(int32_t kind) { return cfr::kernel_kind_name(kind); }
+// Kernel kinds: the node engine's kinds first, then the block engine's.
+const char* cfr_kernel_name(int32_t kind) {
+    if (kind < cfr::K_NUM_KINDS) return cfr::kernel_kind_name(kind);
+    return cfr::xkernel_kind_name(kind);
+}
 
 int cfr_iterate_timed(cfr_solver* s, int32_t n, double* kernel_ms, int64_t* kernel_launches,
                       int32_t n_kinds) {
@@ -301,7 +425,7 @@ int cfr_iterate_timed(cfr_solver* s, int32_t n, double* kernel_ms, int64_t* kern
     for (int32_t i = 0; i < n; ++i) {
         timer.used = 0;
         timer.kinds.clear();
-        cfr::launch_iteration(s->dev, s->level_offset.data(), s->variant, s->linear, s->stream, &timer);
+        launch_one_iteration(s, s->stream, &timer);
         int rc = check_hip("timed iteration launch");
         if (rc != CFR_OK) return rc;
         if (timer.err != hipSuccess) return hip_err(timer.err, "event record");
@@ -353,9 +477,13 @@ int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]) {
     if (s == nullptr || expl == nullptr) return set_err(CFR_EINVAL, "null argument");
     if (!s->level_pure) return set_err(CFR_ELEVEL, "an infoset spans several levels");
     cfr::launch_average(s->dev, s->stream);
-    for (int player = 1; player <= 2; ++player)
-        cfr::launch_best_response(s->dev, s->level_offset.data(), s->infoset_level_offset.data(),
-                                  player, s->stream);
+    for (int player = 1; player <= 2; ++player) {
+        if (s->engine == ENGINE_BLOCK)
+            cfr::launch_x_best_response(s->xdev, s->dev.avgprob, player, s->stream);
+        else
+            cfr::launch_best_response(s->dev, s->level_offset.data(), s->infoset_level_offset.data(),
+                                      player, s->stream);
+    }
     int rc = check_hip("best response launch");
     if (rc != CFR_OK) return rc;
     double br[2];
@@ -459,19 +587,24 @@ int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes)
     if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
     if (n_nodes != s->dev.N) return set_err(CFR_EINVAL, "n_nodes does not match the game");
     const int64_t N = s->dev.N;
+    std::vector<float> val(u1 != nullptr ? N : 0), planes(reach != nullptr ? 3 * N : 0);
+    std::vector<int32_t> canon(s->engine == ENGINE_BLOCK ? N : 0);
     if (u1 != nullptr)
-        HIP_TRY(hipMemcpyAsync(u1, s->dev.value, N * sizeof(float), hipMemcpyDeviceToHost, s->stream),
-                "value copy");
-    std::vector<float> planes;
-    if (reach != nullptr) {
-        planes.resize(3 * N);
+        HIP_TRY(hipMemcpyAsync(val.data(), s->dev.value, N * sizeof(float), hipMemcpyDeviceToHost,
+                               s->stream), "value copy");
+    if (reach != nullptr)
         HIP_TRY(hipMemcpyAsync(planes.data(), s->dev.reach, 3 * N * sizeof(float),
                                hipMemcpyDeviceToHost, s->stream), "reach copy");
-    }
+    if (s->engine == ENGINE_BLOCK)
+        HIP_TRY(hipMemcpyAsync(canon.data(), s->xdev.canon_of, N * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s->stream), "order copy");
     HIP_TRY(hipStreamSynchronize(s->stream), "node values synchronise");
-    if (reach != nullptr)
-        for (int64_t v = 0; v < N; ++v)
-            for (int k = 0; k < 3; ++k) reach[3 * v + k] = planes[k * N + v];
+    for (int64_t x = 0; x < N; ++x) {
+        const int64_t v = s->engine == ENGINE_BLOCK ? canon[x] : x;  // canonical position
+        if (u1 != nullptr) u1[v] = val[x];
+        if (reach != nullptr)
+            for (int k = 0; k < 3; ++k) reach[3 * v + k] = planes[k * N + x];
+    }
     return CFR_OK;
 }
 
@@ -488,6 +621,8 @@ int cfr_destroy(cfr_solver* s) {
 
 struct cfr_host_layout {
     cfr::Layout L;
+    cfr::ExecPlan P;
+    bool has_plan = false;
 };
 
 namespace {
@@ -518,6 +653,37 @@ std::pair<const void*, int64_t> host_array(const cfr::Layout& L, const std::stri
     return {nullptr, -1};
 }
 
+std::pair<const void*, int64_t> plan_array(const cfr::ExecPlan& P, const std::string& n) {
+    auto v = [](const auto& vec) {
+        return std::pair<const void*, int64_t>(
+            vec.data(), static_cast<int64_t>(vec.size() * sizeof(vec[0])));
+    };
+    if (n == "x_canon_of") return v(P.canon_of);
+    if (n == "x_parent") return v(P.parent);
+    if (n == "x_edge") return v(P.edge);
+    if (n == "x_meta") return v(P.meta);
+    if (n == "x_child_begin") return v(P.child_begin);
+    if (n == "x_child_stride") return v(P.child_stride);
+    if (n == "x_child_list") return v(P.child_list);
+    if (n == "x_infoset_canon") return v(P.infoset_canon);
+    if (n == "x_q_offset") return v(P.q_offset);
+    if (n == "x_member_offset") return v(P.member_offset);
+    if (n == "x_members") return v(P.members);
+    if (n == "x_h_level_offset") return v(P.h_level_offset);
+    if (n == "x_chance_nodes") return v(P.chance_nodes);
+    if (n == "x_c_level_offset") return v(P.c_level_offset);
+    if (n == "x_q_input") return v(P.q_input);
+    return {nullptr, -1};
+}
+
+std::pair<const void*, int64_t> any_array(const cfr_host_layout* h, const std::string& n) {
+    if (n.rfind("x_", 0) == 0) {
+        if (!h->has_plan) return {nullptr, -1};
+        return plan_array(h->P, n);
+    }
+    return host_array(h->L, n);
+}
+
 }  // namespace
 
 extern "C" {
@@ -526,10 +692,18 @@ int cfr_host_layout_create(const cfr_game* game, cfr_host_layout** out) {
     if (game == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
     auto* h = new cfr_host_layout();
     std::string err;
-    const int rc = cfr::flatten(*game, h->L, err);
+    int rc = cfr::flatten(*game, h->L, err);
     if (rc != CFR_OK) {
         delete h;
         return set_err(rc, err);
+    }
+    if (h->L.level_pure) {
+        rc = cfr::build_exec_plan(h->L, h->P, err);
+        if (rc != CFR_OK) {
+            delete h;
+            return set_err(rc, err);
+        }
+        h->has_plan = true;
     }
     *out = h;
     return CFR_OK;
@@ -537,13 +711,13 @@ int cfr_host_layout_create(const cfr_game* game, cfr_host_layout** out) {
 
 int64_t cfr_host_layout_bytes(const cfr_host_layout* layout, const char* name) {
     if (layout == nullptr || name == nullptr) return CFR_EINVAL;
-    const auto a = host_array(layout->L, name);
+    const auto a = any_array(layout, name);
     return a.second < 0 ? CFR_EINVAL : a.second;
 }
 
 int cfr_host_layout_get(const cfr_host_layout* layout, const char* name, void* out, int64_t bytes) {
     if (layout == nullptr || name == nullptr) return set_err(CFR_EINVAL, "null argument");
-    const auto a = host_array(layout->L, name);
+    const auto a = any_array(layout, name);
     if (a.second < 0) return set_err(CFR_EINVAL, "unknown layout array");
     if (bytes != a.second || (bytes > 0 && out == nullptr)) return set_err(CFR_EINVAL, "wrong output size");
     if (bytes > 0) std::memcpy(out, a.first, static_cast<size_t>(bytes));

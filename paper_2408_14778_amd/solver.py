@@ -56,23 +56,35 @@ class GameArgs:
         )
 
 
-def make_config(variant: str = "vanilla", averaging=None, graph: bool = True) -> N.CfrConfig:
+def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
+                engine: str = "auto") -> N.CfrConfig:
     if variant not in VARIANTS:
         raise ValueError(f"variant must be one of {list(VARIANTS)}")
+    if engine not in ("auto", "node"):
+        raise ValueError("engine must be 'auto' (public-block engine where it applies) or 'node'")
     cfg = N.CfrConfig()
     cfg.variant = VARIANTS[variant]
     cfg.averaging = AVERAGING[averaging]
-    cfg.flags = 0 if graph else N.CFR_FLAG_NO_GRAPH
+    cfg.flags = (0 if graph else N.CFR_FLAG_NO_GRAPH) | (N.CFR_FLAG_NODE_ENGINE if engine == "node" else 0)
     return cfg
 
 
-def plan(game, variant: str = "vanilla", averaging=None) -> dict:
+def plan(game, variant: str = "vanilla", averaging=None, engine: str = "auto") -> dict:
     lib = N.load()
     args = GameArgs(game)
-    cfg = make_config(variant, averaging)
+    cfg = make_config(variant, averaging, engine=engine)
     info = N.CfrPlanInfo()
     N.check(lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg), ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
+
+
+PLAN_DTYPES = {
+    "x_canon_of": np.int32, "x_parent": np.int32, "x_edge": np.int32, "x_meta": np.int8,
+    "x_child_begin": np.int32, "x_child_stride": np.int32, "x_child_list": np.int32,
+    "x_infoset_canon": np.int32, "x_q_offset": np.int32, "x_member_offset": np.int32,
+    "x_members": np.int32, "x_h_level_offset": np.int32, "x_chance_nodes": np.int32,
+    "x_c_level_offset": np.int32, "x_q_input": np.int32,
+}
 
 
 def host_layout(game, names=None) -> dict:
@@ -87,7 +99,7 @@ def host_layout(game, names=None) -> dict:
             nbytes = lib.cfr_host_layout_bytes(h, name.encode())
             if nbytes < 0:
                 raise KeyError(name)
-            dt = np.dtype(LAYOUT_DTYPES[name])
+            dt = np.dtype(LAYOUT_DTYPES.get(name) or PLAN_DTYPES[name])
             arr = np.empty(nbytes // dt.itemsize, dtype=dt)
             N.check(lib.cfr_host_layout_get(h, name.encode(), arr.ctypes.data_as(ctypes.c_void_p),
                                             nbytes))
@@ -101,13 +113,13 @@ class Solver:
     """CFR (vanilla or CFR+) over one game, resident on one GPU."""
 
     def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
-                 graph: bool = True, stream=None):
+                 graph: bool = True, stream=None, engine: str = "auto"):
         import torch
 
         self._lib = N.load()
         self.variant = variant
         args = GameArgs(game)
-        cfg = make_config(variant, averaging, graph)
+        cfg = make_config(variant, averaging, graph, engine)
         info = N.CfrPlanInfo()
         N.check(self._lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg),
                                    ctypes.byref(info)))
