@@ -122,6 +122,22 @@ int cfr_iterate_timed(cfr_solver* s, int32_t n, double* kernel_ms, int64_t* kern
                       int32_t n_kinds);
 const char* cfr_kernel_name(int32_t kind);
 
+/* Like cfr_iterate_timed but per launch: after n iterations, for each of the *n_launches
+ * launches of one iteration (in launch order, up to max_launches are written), the summed
+ * event time over the n iterations, its kernel kind (cfr_kernel_name), the tree level it
+ * processes (-1 if none) and its number of work items. Synchronises. */
+int cfr_iterate_profile(cfr_solver* s, int32_t n, double* launch_ms, int32_t* launch_kind,
+                        int32_t* launch_level, int64_t* launch_units, int32_t max_launches,
+                        int32_t* n_launches);
+
+/* Launch shapes of the public-block engine: a launch of u work items uses
+ * up_threads[b] (bottom-up) or reach_threads[b] (top-down) threads per workgroup with
+ * b = min(floor(log2 u), n_buckets - 1); multiples of 64 in [64, 1024]. n_buckets = 0 restores
+ * the default (256). Re-captures the iteration graph; the results do not depend on the shape.
+ * Used by the autotuner; CFR_EINVAL for the node engine. */
+int cfr_set_launch_shape(cfr_solver* s, const int32_t* up_threads, const int32_t* reach_threads,
+                         int32_t n_buckets);
+
 /* Average strategy sigma-bar = S / sum_a S per infoset, uniform where that sum is 0
  * (Eq. average_strategy_profile), written to out[q] for the n_q pairs in input order.
  * out_on_device != 0: `out` is device memory, the call enqueues and returns;
@@ -169,6 +185,23 @@ int cfr_host_layout_create(const cfr_game* game, cfr_host_layout** out);
 int64_t cfr_host_layout_bytes(const cfr_host_layout* layout, const char* name);
 int cfr_host_layout_get(const cfr_host_layout* layout, const char* name, void* out, int64_t bytes);
 int cfr_host_layout_destroy(cfr_host_layout* layout);
+
+/* Batched solving: n_games independent games (e.g. the subgames of a larger game) solved
+ * together. They are laid out as one forest, level-major (level l holds level l of every game,
+ * in game order) over the public-block plan, so each level of every game is processed by one
+ * launch and one iteration of all games is one graph replay. All games must have level-pure
+ * infosets and at most 16 actions per infoset (CFR_ELEVEL / CFR_EINVAL otherwise). The batch
+ * solver accepts cfr_iterate, cfr_iterate_timed, cfr_average_strategy, cfr_current_strategy,
+ * cfr_get_state, cfr_set_state and cfr_destroy; infoset-action pairs are numbered by
+ * concatenating the games' input pair orders (game 0 first). */
+int cfr_plan_batch(const cfr_game* games, int32_t n_games, const cfr_config* config,
+                   cfr_plan_info* out);
+int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* config,
+                    void* workspace, size_t bytes, void* stream, cfr_solver** out);
+/* Per-game exploitability (BR_1 + BR_2) / 2 of the average strategy (Section 2.2), for
+ * n_games entries; br_values (optional) receives 2 * n_games values, player 1 then player 2
+ * for each game. Synchronises. */
+int cfr_exploitability_batch(cfr_solver* s, double* expl, double* br_values, int32_t n_games);
 
 /* Release host resources; the caller then frees the workspace. */
 int cfr_destroy(cfr_solver* s);

@@ -79,6 +79,9 @@ SIGNATURES = {
     "cfr_iterate_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, _i64p,
                                          ctypes.c_int32]),
     "cfr_kernel_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "cfr_iterate_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, _i32p, _i32p,
+                                           _i64p, ctypes.c_int32, _i32p]),
+    "cfr_set_launch_shape": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, ctypes.c_int32]),
     "cfr_average_strategy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_int]),
     "cfr_current_strategy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -98,6 +101,12 @@ SIGNATURES = {
     "cfr_host_layout_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
                                            ctypes.c_int64]),
     "cfr_host_layout_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "cfr_plan_batch": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_int32,
+                                      ctypes.POINTER(CfrConfig), ctypes.POINTER(CfrPlanInfo)]),
+    "cfr_build_batch": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_int32,
+                                       ctypes.POINTER(CfrConfig), ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "cfr_exploitability_batch": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int32]),
     "cfr_last_error": (ctypes.c_char_p, []),
 }
 

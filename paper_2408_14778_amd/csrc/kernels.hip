@@ -308,12 +308,12 @@ const char* kernel_kind_name(int kind) {
 
 void launch_iteration(const Dev& d, const int32_t* lo, int variant, int linear, hipStream_t st,
                       LaunchTimer* timer) {
-    auto pre = [&](int k) { if (timer) timer->before(k, st); };
+    auto pre = [&](int k, int l, int64_t n) { if (timer) timer->before(k, l, n, st); };
     auto post = [&](int k) { if (timer) timer->after(k, st); };
     // top-down: levels 1 .. D-1 (level D holds terminals only)
     for (int32_t l = 1; l < d.D; ++l) {
         const int32_t a = lo[l], b = lo[l + 1];
-        pre(K_REACH);
+        pre(K_REACH, l, b - a);
         hipLaunchKernelGGL(k_reach_level, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b, d.N,
                            d.parent, d.node_player, d.node_edge, d.prob, d.reach);
         post(K_REACH);
@@ -321,19 +321,19 @@ void launch_iteration(const Dev& d, const int32_t* lo, int variant, int linear, 
     // bottom-up: levels D-1 .. 0
     for (int32_t l = d.D - 1; l >= 0; --l) {
         const int32_t a = lo[l], b = lo[l + 1];
-        pre(K_VALUE);
+        pre(K_VALUE, l, b - a);
         hipLaunchKernelGGL(k_value_level, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b, d.N,
                            d.child_begin, d.node_player, d.node_infoset, d.node_edge, d.prob,
                            d.value, d.reach, d.rtilde, d.pibar);
         post(K_VALUE);
     }
     if (d.Hp > 0) {
-        pre(K_INFOSET);
+        pre(K_INFOSET, -1, d.Hp);
         hipLaunchKernelGGL(k_infoset_update, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
                            d.q_offset, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T, variant, linear);
         post(K_INFOSET);
     }
-    pre(K_TICK);
+    pre(K_TICK, -1, 1);
     hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, d.T);
     post(K_TICK);
 }

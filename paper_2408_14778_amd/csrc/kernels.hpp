@@ -59,9 +59,10 @@ void launch_regret_match(const Dev& d, hipStream_t st);
 enum KernelKind { K_REACH = 0, K_VALUE = 1, K_INFOSET = 2, K_TICK = 3, K_NUM_KINDS = 4 };
 const char* kernel_kind_name(int kind);
 
-// Optional per-launch event pairs: record(kind) is called before and after each launch.
+// Optional per-launch hooks, called before and after each launch of an iteration with the
+// kernel kind, the tree level it processes (-1 if none) and its number of work items.
 struct LaunchTimer {
-    virtual void before(int kind, hipStream_t st) = 0;
+    virtual void before(int kind, int level, int64_t units, hipStream_t st) = 0;
     virtual void after(int kind, hipStream_t st) = 0;
     virtual ~LaunchTimer() = default;
 };

@@ -1,7 +1,10 @@
 // C ABI of the library (include/cfr.h): planning, building, iterating, exports.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <thread>
 #include <utility>
 #include <string>
 #include <vector>
@@ -18,7 +21,10 @@ struct cfr_solver {
     cfr::Dev dev{};
     cfr::XDev xdev{};
     int engine = ENGINE_NODE;
+    int32_t n_games = 1;       // > 1: a batch (forest); canonical exports are unavailable
+    bool canonical = true;     // the canonical layout arrays are on the device
     std::vector<int32_t> x_level_offset, x_h_level_offset, x_c_level_offset;
+    std::vector<int32_t> up_block, reach_block;  // launch shapes (empty: defaults)
     int variant = CFR_VANILLA;
     int linear = 0;
     bool use_graph = true;
@@ -71,6 +77,8 @@ struct Sizes {
     int64_t N = 0, Hp = 0, Qp = 0, H0 = 0, Q0 = 0, M = 0, C = 0, L = 0;
     int32_t D = 0, max_actions = 0;
     int engine = ENGINE_NODE;
+    bool canonical = true;   // false for a batch: only the execution plan is on the device
+    int32_t n_games = 1;
 };
 
 int choose_engine(bool level_pure, int32_t max_actions, uint32_t flags) {
@@ -86,21 +94,23 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
     const int32_t D = z.D;
     d = cfr::Dev{};
     d.N = N; d.Hp = Hp; d.Qp = Qp; d.H0 = H0; d.Q0 = Q0; d.M = M; d.D = D;
-    d.parent = c.take<int32_t>(N);
-    d.child_begin = c.take<int32_t>(N + 1);
-    d.node_player = c.take<int8_t>(N);
-    d.node_infoset = c.take<int32_t>(N);
-    d.node_edge = c.take<int32_t>(N);
-    d.node_id = c.take<int32_t>(N);
-    d.level_offset = c.take<int32_t>(D + 2);
-    d.infoset_id = c.take<int32_t>(Hp);
-    d.infoset_player = c.take<int8_t>(Hp);
-    d.q_offset = c.take<int32_t>(Hp + 1);
-    d.chance_id = c.take<int32_t>(H0);
-    d.cq_offset = c.take<int32_t>(H0 + 1);
-    d.member_offset = c.take<int32_t>(Hp + 1);
-    d.members = c.take<int32_t>(M);
-    d.q_input = c.take<int32_t>(Qp);
+    if (z.canonical) {
+        d.parent = c.take<int32_t>(N);
+        d.child_begin = c.take<int32_t>(N + 1);
+        d.node_player = c.take<int8_t>(N);
+        d.node_infoset = c.take<int32_t>(N);
+        d.node_edge = c.take<int32_t>(N);
+        d.node_id = c.take<int32_t>(N);
+        d.level_offset = c.take<int32_t>(D + 2);
+        d.infoset_id = c.take<int32_t>(Hp);
+        d.infoset_player = c.take<int8_t>(Hp);
+        d.q_offset = c.take<int32_t>(Hp + 1);
+        d.chance_id = c.take<int32_t>(H0);
+        d.cq_offset = c.take<int32_t>(H0 + 1);
+        d.member_offset = c.take<int32_t>(Hp + 1);
+        d.members = c.take<int32_t>(M);
+        d.q_input = c.take<int32_t>(Qp);
+    }
     d.payoff = c.take<float>(N);
     d.prob = c.take<float>(Qp + Q0);
     d.R = c.take<float>(Qp);
@@ -113,7 +123,7 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
     d.br_value = c.take<float>(N);
     d.best = c.take<int32_t>(Hp);
     d.stage = c.take<float>(2 * Qp);
-    d.out2 = c.take<double>(2);
+    d.out2 = c.take<double>(2 * static_cast<int64_t>(z.n_games));
     d.sq_offset = d.q_offset;
     d.sq_input = d.q_input;
     x = cfr::XDev{};
@@ -324,19 +334,9 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         delete s;
         return rc;
     }
-    std::vector<int32_t> cbase, ck;
     if (s->engine == ENGINE_BLOCK) {
-        // chance units: prob index of action 0 and the action count
-        cbase.resize(P.C);
-        ck.resize(P.C);
-        for (int64_t i = 0; i < P.C; ++i) {
-            const int32_t c = P.canon_of[P.chance_nodes[i]];
-            const int32_t hc = L.node_infoset[c];
-            cbase[i] = static_cast<int32_t>(L.Qp + L.cq_offset[hc]);
-            ck[i] = L.cq_offset[hc + 1] - L.cq_offset[hc];
-        }
-        if ((rc = upload_plan(s, P, st)) || (rc = upload(s->xdev.chance_base, cbase, st)) ||
-            (rc = upload(s->xdev.chance_k, ck, st))) {
+        if ((rc = upload_plan(s, P, st)) || (rc = upload(s->xdev.chance_base, P.chance_base, st)) ||
+            (rc = upload(s->xdev.chance_k, P.chance_k, st))) {
             delete s;
             return rc;
         }
@@ -379,7 +379,8 @@ int cfr_iterate(cfr_solver* s, int32_t n) {
 namespace {
 struct EventTimer : cfr::LaunchTimer {
     std::vector<hipEvent_t> ev;
-    std::vector<int> kinds;
+    std::vector<int> kinds, levels;
+    std::vector<int64_t> units;
     size_t used = 0;
     hipError_t err = hipSuccess;
     hipEvent_t next() {
@@ -391,8 +392,10 @@ struct EventTimer : cfr::LaunchTimer {
         }
         return ev[used++];
     }
-    void before(int kind, hipStream_t st) override {
+    void before(int kind, int level, int64_t n, hipStream_t st) override {
         kinds.push_back(kind);
+        levels.push_back(level);
+        units.push_back(n);
         const hipError_t r = hipEventRecord(next(), st);
         if (r != hipSuccess) err = r;
     }
@@ -425,6 +428,8 @@ int cfr_iterate_timed(cfr_solver* s, int32_t n, double* kernel_ms, int64_t* kern
     for (int32_t i = 0; i < n; ++i) {
         timer.used = 0;
         timer.kinds.clear();
+        timer.levels.clear();
+        timer.units.clear();
         launch_one_iteration(s, s->stream, &timer);
         int rc = check_hip("timed iteration launch");
         if (rc != CFR_OK) return rc;
@@ -441,6 +446,73 @@ int cfr_iterate_timed(cfr_solver* s, int32_t n, double* kernel_ms, int64_t* kern
         }
         s->T += 1;
     }
+    return CFR_OK;
+}
+
+int cfr_iterate_profile(cfr_solver* s, int32_t n, double* launch_ms, int32_t* launch_kind,
+                        int32_t* launch_level, int64_t* launch_units, int32_t max_launches,
+                        int32_t* n_launches) {
+    if (s == nullptr || n < 1 || n_launches == nullptr || max_launches < 0)
+        return set_err(CFR_EINVAL, "bad argument");
+    EventTimer timer;
+    std::vector<double> acc;
+    for (int32_t i = 0; i < n; ++i) {
+        timer.used = 0;
+        timer.kinds.clear();
+        timer.levels.clear();
+        timer.units.clear();
+        launch_one_iteration(s, s->stream, &timer);
+        int rc = check_hip("profiled iteration launch");
+        if (rc != CFR_OK) return rc;
+        if (timer.err != hipSuccess) return hip_err(timer.err, "event record");
+        HIP_TRY(hipStreamSynchronize(s->stream), "profiled iteration synchronise");
+        acc.resize(timer.kinds.size(), 0.0);
+        for (size_t j = 0; j < timer.kinds.size(); ++j) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, timer.ev[2 * j], timer.ev[2 * j + 1]), "event time");
+            acc[j] += ms;
+        }
+        s->T += 1;
+    }
+    *n_launches = static_cast<int32_t>(timer.kinds.size());
+    for (size_t j = 0; j < timer.kinds.size() && static_cast<int32_t>(j) < max_launches; ++j) {
+        if (launch_ms) launch_ms[j] = acc[j];
+        if (launch_kind) launch_kind[j] = timer.kinds[j];
+        if (launch_level) launch_level[j] = timer.levels[j];
+        if (launch_units) launch_units[j] = timer.units[j];
+    }
+    return CFR_OK;
+}
+
+int cfr_set_launch_shape(cfr_solver* s, const int32_t* up_threads, const int32_t* reach_threads,
+                         int32_t n_buckets) {
+    if (s == nullptr || n_buckets < 0 || n_buckets > cfr::kShapeBuckets)
+        return set_err(CFR_EINVAL, "bad argument");
+    if (s->engine != ENGINE_BLOCK) return set_err(CFR_EINVAL, "launch shapes apply to the block engine");
+    auto fill = [&](const int32_t* src, std::vector<int32_t>& dst) -> bool {
+        dst.assign(cfr::kShapeBuckets, 256);
+        if (src == nullptr) return true;
+        for (int32_t b = 0; b < cfr::kShapeBuckets; ++b) {
+            const int32_t t = src[std::min(b, n_buckets - 1)];
+            if (t < 64 || t > 1024 || (t % 64) != 0) return false;
+            dst[b] = t;
+        }
+        return true;
+    };
+    if (n_buckets == 0) {
+        s->up_block.clear();
+        s->reach_block.clear();
+    } else if (!fill(up_threads, s->up_block) || !fill(reach_threads, s->reach_block)) {
+        return set_err(CFR_EINVAL, "threads per workgroup must be a multiple of 64 in [64, 1024]");
+    }
+    s->xdev.up_block = s->up_block.empty() ? nullptr : s->up_block.data();
+    s->xdev.reach_block = s->reach_block.empty() ? nullptr : s->reach_block.data();
+    HIP_TRY(hipStreamSynchronize(s->stream), "launch shape synchronise");
+    if (s->exec != nullptr) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph != nullptr) (void)hipGraphDestroy(s->graph);
+    s->exec = nullptr;
+    s->graph = nullptr;
+    if (s->use_graph) return capture(s);
     return CFR_OK;
 }
 
@@ -475,6 +547,7 @@ int cfr_current_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_devi
 
 int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]) {
     if (s == nullptr || expl == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (s->n_games != 1) return set_err(CFR_EINVAL, "a batch reports cfr_exploitability_batch");
     if (!s->level_pure) return set_err(CFR_ELEVEL, "an infoset spans several levels");
     cfr::launch_average(s->dev, s->stream);
     for (int player = 1; player <= 2; ++player) {
@@ -534,7 +607,7 @@ int cfr_set_state(cfr_solver* s, int64_t T, const float* R, const float* S, int6
 }
 
 int64_t cfr_layout_bytes(cfr_solver* s, const char* name) {
-    if (s == nullptr || name == nullptr) return CFR_EINVAL;
+    if (s == nullptr || name == nullptr || !s->canonical) return CFR_EINVAL;
     const cfr::Dev& d = s->dev;
     const std::string n(name);
     if (n == "level_offset") return (d.D + 2) * 4;
@@ -585,6 +658,7 @@ int cfr_get_layout(cfr_solver* s, const char* name, void* out, int64_t bytes) {
 
 int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes) {
     if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (!s->canonical) return set_err(CFR_EINVAL, "node values are not exported for a batch");
     if (n_nodes != s->dev.N) return set_err(CFR_EINVAL, "n_nodes does not match the game");
     const int64_t N = s->dev.N;
     std::vector<float> val(u1 != nullptr ? N : 0), planes(reach != nullptr ? 3 * N : 0);
@@ -614,6 +688,192 @@ int cfr_destroy(cfr_solver* s) {
     if (s->exec != nullptr) (void)hipGraphExecDestroy(s->exec);
     if (s->graph != nullptr) (void)hipGraphDestroy(s->graph);
     delete s;
+    return CFR_OK;
+}
+
+}  // extern "C"
+
+
+namespace {
+
+// Flattens and plans every game on host threads; all must be level pure with <= 16 actions.
+int plan_games(const cfr_game* games, int32_t n, std::vector<cfr::ExecPlan>& plans,
+               int32_t& max_actions, std::string& err) {
+    plans.assign(n, cfr::ExecPlan());
+    std::vector<int> codes(n, CFR_OK);
+    std::vector<std::string> errs(n);
+    std::vector<int32_t> maxa(n, 0);
+    std::atomic<int32_t> next{0};
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto work = [&]() {
+        for (int32_t g = next++; g < n; g = next++) {
+            cfr::Layout L;
+            int rc = cfr::flatten(games[g], L, errs[g]);
+            if (rc == CFR_OK && !L.level_pure) {
+                rc = CFR_ELEVEL;
+                errs[g] = "an infoset spans several levels";
+            }
+            if (rc == CFR_OK && L.max_actions > 16) {
+                rc = CFR_EINVAL;
+                errs[g] = "more than 16 actions in an infoset";
+            }
+            if (rc == CFR_OK) rc = cfr::build_exec_plan(L, plans[g], errs[g]);
+            maxa[g] = L.max_actions;
+            codes[g] = rc;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 0; t < std::min<unsigned>(hw, static_cast<unsigned>(n)); ++t) pool.emplace_back(work);
+    for (auto& t : pool) t.join();
+    max_actions = 0;
+    for (int32_t g = 0; g < n; ++g) {
+        if (codes[g] != CFR_OK) {
+            err = "game " + std::to_string(g) + ": " + errs[g];
+            return codes[g];
+        }
+        max_actions = std::max(max_actions, maxa[g]);
+    }
+    return CFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfr_plan_batch(const cfr_game* games, int32_t n_games, const cfr_config* config,
+                   cfr_plan_info* out) {
+    if (games == nullptr || out == nullptr || n_games < 1) return set_err(CFR_EINVAL, "bad argument");
+    if (config != nullptr && (config->variant < 0 || config->variant > 1))
+        return set_err(CFR_EINVAL, "bad variant");
+    Sizes z;
+    z.engine = ENGINE_BLOCK;
+    z.canonical = false;
+    z.n_games = n_games;
+    int64_t terminals = 0;
+    for (int32_t g = 0; g < n_games; ++g) {
+        cfr::Layout L;
+        std::string err;
+        const int rc = cfr::plan_sizes(games[g], L, err);
+        if (rc != CFR_OK) return set_err(rc, "game " + std::to_string(g) + ": " + err);
+        if (!L.level_pure) return set_err(CFR_ELEVEL, "game " + std::to_string(g) + " is not level pure");
+        if (L.max_actions > 16) return set_err(CFR_EINVAL, "more than 16 actions in an infoset");
+        z.N += L.N; z.Hp += L.Hp; z.Qp += L.Qp; z.H0 += L.H0; z.Q0 += L.Q0; z.M += L.n_members;
+        z.C += L.n_chance_nodes; z.L += L.N;
+        z.D = std::max(z.D, L.D);
+        z.max_actions = std::max(z.max_actions, L.max_actions);
+        terminals += L.n_terminals;
+    }
+    cfr::Dev d{};
+    cfr::XDev x{};
+    std::memset(out, 0, sizeof *out);
+    out->n_nodes = z.N;
+    out->n_terminals = terminals;
+    out->n_infosets = z.Hp;
+    out->n_q = z.Qp;
+    out->n_chance_infosets = z.H0;
+    out->n_chance_q = z.Q0;
+    out->max_actions = z.max_actions;
+    out->depth = z.D;
+    out->level_pure = 1;
+    out->engine = ENGINE_BLOCK;
+    out->workspace_bytes = static_cast<int64_t>(carve(d, x, nullptr, z));
+    return CFR_OK;
+}
+
+int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* config,
+                    void* workspace, size_t bytes, void* stream, cfr_solver** out) {
+    if (games == nullptr || workspace == nullptr || out == nullptr || n_games < 1)
+        return set_err(CFR_EINVAL, "bad argument");
+    cfr_config cfg{};
+    cfg.variant = CFR_VANILLA;
+    cfg.averaging = CFR_AVG_DEFAULT;
+    if (config != nullptr) cfg = *config;
+    if (cfg.variant < 0 || cfg.variant > 1) return set_err(CFR_EINVAL, "bad variant");
+    if (cfg.averaging < -1 || cfg.averaging > 1) return set_err(CFR_EINVAL, "bad averaging");
+    std::string err;
+    std::vector<cfr::ExecPlan> plans;
+    int32_t max_actions = 0;
+    int rc = plan_games(games, n_games, plans, max_actions, err);
+    if (rc != CFR_OK) return set_err(rc, err);
+    cfr::ExecPlan F;
+    rc = cfr::build_forest_plan(plans, F, err);
+    if (rc != CFR_OK) return set_err(rc, err);
+    plans.clear();
+    plans.shrink_to_fit();
+    Sizes z;
+    z.N = F.N; z.Hp = F.Hp; z.Qp = F.Qp; z.Q0 = F.Q0; z.M = F.M; z.C = F.C; z.L = F.L; z.D = F.D;
+    z.max_actions = max_actions;
+    z.engine = ENGINE_BLOCK;
+    z.canonical = false;
+    z.n_games = n_games;
+    cfr::Dev d{};
+    cfr::XDev x{};
+    // cfr_plan_batch bounds the explicit child lists by the node count, so a workspace of the
+    // planned size always covers the exact need
+    const size_t need = carve(d, x, nullptr, z);
+    if (bytes < need)
+        return set_err(CFR_ENOMEM, "workspace has " + std::to_string(bytes) + " bytes, needs " +
+                                       std::to_string(need));
+    carve(d, x, workspace, z);
+    auto* s = new cfr_solver();
+    s->dev = d;
+    s->xdev = x;
+    s->engine = ENGINE_BLOCK;
+    s->n_games = n_games;
+    s->canonical = false;
+    s->variant = cfg.variant;
+    s->linear = cfg.averaging == CFR_AVG_DEFAULT ? (cfg.variant == CFR_PLUS) : cfg.averaging;
+    s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
+    s->level_pure = true;
+    s->max_actions = max_actions;
+    s->stream = static_cast<hipStream_t>(stream);
+    hipStream_t st = s->stream;
+    std::vector<float> prob_tail(F.Qp + F.Q0, 0.0f);
+    std::copy(F.chance_prob.begin(), F.chance_prob.end(), prob_tail.begin() + F.Qp);
+    if ((rc = upload_plan(s, F, st)) || (rc = upload(s->xdev.chance_base, F.chance_base, st)) ||
+        (rc = upload(s->xdev.chance_k, F.chance_k, st)) || (rc = upload(d.prob, prob_tail, st))) {
+        delete s;
+        return rc;
+    }
+    cfr::launch_reset(d, st, false);
+    cfr::launch_x_reset(s->xdev, st);
+    if ((rc = check_hip("reset")) != CFR_OK) {
+        delete s;
+        return rc;
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_err(e, "build synchronise");
+    }
+    if (s->use_graph && (rc = capture(s)) != CFR_OK) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return CFR_OK;
+}
+
+int cfr_exploitability_batch(cfr_solver* s, double* expl, double* br_values, int32_t n_games) {
+    if (s == nullptr || expl == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (n_games != s->n_games) return set_err(CFR_EINVAL, "n_games does not match the batch");
+    if (s->engine != ENGINE_BLOCK) return set_err(CFR_EINVAL, "not a batch solver");
+    cfr::launch_average(s->dev, s->stream);
+    for (int player = 1; player <= 2; ++player)
+        cfr::launch_x_best_response(s->xdev, s->dev.avgprob, player, s->stream);
+    int rc = check_hip("best response launch");
+    if (rc != CFR_OK) return rc;
+    std::vector<double> br(2 * static_cast<size_t>(n_games));
+    HIP_TRY(hipMemcpyAsync(br.data(), s->dev.out2, br.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream), "br copy");
+    HIP_TRY(hipStreamSynchronize(s->stream), "exploitability synchronise");
+    for (int32_t g = 0; g < n_games; ++g) {
+        expl[g] = 0.5 * (br[2 * g] + br[2 * g + 1]);
+        if (br_values != nullptr) {
+            br_values[2 * g] = br[2 * g];
+            br_values[2 * g + 1] = br[2 * g + 1];
+        }
+    }
     return CFR_OK;
 }
 

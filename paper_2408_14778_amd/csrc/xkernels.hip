@@ -23,6 +23,14 @@ constexpr int kBlock = 256;
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
+inline int pick(const int32_t* table, int64_t units) {
+    return table != nullptr ? table[shape_bucket(units)] : kBlock;
+}
+
+inline unsigned blocks_of(int64_t n, int threads) {
+    return static_cast<unsigned>((n + threads - 1) / threads);
+}
+
 __device__ __forceinline__ int64_t gid() {
     return static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
 }
@@ -149,28 +157,30 @@ __global__ void k_x_up(int32_t hlo, int32_t nh, int32_t clo, int32_t nc, int is_
     if (is_root_level) *T += 1;
 }
 
-__global__ void k_x_reset_nodes(int64_t N, const int8_t* __restrict__ meta,
+// Level 0 holds the root of every game of the plan (one for a single game, one per
+// subgame for a forest): their reach is 1.
+__global__ void k_x_reset_nodes(int64_t N, int32_t n_roots, const int8_t* __restrict__ meta,
                                 const float* __restrict__ payoff, float* __restrict__ value,
                                 float* __restrict__ reach) {
     const int64_t x = gid();
     if (x >= N) return;
     value[x] = (meta[x] & 3) == 0 ? payoff[x] : 0.0f;
-    if (x == 0) {
-        reach[0] = 1.0f;
-        reach[N] = 1.0f;
-        reach[2 * N] = 1.0f;
+    if (x < n_roots) {
+        reach[x] = 1.0f;
+        reach[N + x] = 1.0f;
+        reach[2 * N + x] = 1.0f;
     }
 }
 
 // ---- best response over the plan (Section 2.2)
 
-__global__ void k_x_br_init(int64_t N, const int8_t* __restrict__ meta,
+__global__ void k_x_br_init(int64_t N, int32_t n_roots, const int8_t* __restrict__ meta,
                             const float* __restrict__ payoff, float sgn,
                             float* __restrict__ br_value, float* __restrict__ br_reach) {
     const int64_t x = gid();
     if (x >= N) return;
     br_value[x] = (meta[x] & 3) == 0 ? sgn * payoff[x] : 0.0f;
-    if (x == 0) br_reach[0] = 1.0f;
+    if (x < n_roots) br_reach[x] = 1.0f;
 }
 
 // pi_{-i}: chance and opponent edge probabilities only.
@@ -251,8 +261,11 @@ __global__ void k_x_tick(int64_t* T) {
     if (gid() == 0) *T += 1;
 }
 
-__global__ void k_x_store_root(const float* __restrict__ br_value, double* out) {
-    if (gid() == 0) *out = static_cast<double>(br_value[0]);
+// Best-response value of every root (level 0, in game order) into out[g * 2 + player - 1].
+__global__ void k_x_store_roots(int32_t n_roots, int player, const float* __restrict__ br_value,
+                                double* out) {
+    const int64_t g = gid();
+    if (g < n_roots) out[2 * g + player - 1] = static_cast<double>(br_value[g]);
 }
 
 __global__ void k_x_permute_values(int64_t N, const int32_t* __restrict__ canon_of,
@@ -263,6 +276,12 @@ __global__ void k_x_permute_values(int64_t N, const int32_t* __restrict__ canon_
 
 }  // namespace
 
+int shape_bucket(int64_t units) {
+    int b = 0;
+    while (b + 1 < kShapeBuckets && (int64_t{1} << (b + 1)) <= units) ++b;
+    return b;
+}
+
 const char* xkernel_kind_name(int kind) {
     switch (kind) {
         case XK_REACH: return "block_reach";
@@ -272,8 +291,8 @@ const char* xkernel_kind_name(int kind) {
 }
 
 void launch_x_reset(const XDev& x, hipStream_t st) {
-    hipLaunchKernelGGL(k_x_reset_nodes, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N, x.meta,
-                       x.payoff, x.value, x.reach);
+    hipLaunchKernelGGL(k_x_reset_nodes, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N,
+                       x.level_offset_host[1], x.meta, x.payoff, x.value, x.reach);
 }
 
 template <int KMAX>
@@ -281,42 +300,47 @@ static void launch_up(const XDev& x, int32_t l, int variant, int linear, hipStre
     const int32_t hlo = x.h_level_offset_host[l], nh = x.h_level_offset_host[l + 1] - hlo;
     const int32_t clo = x.c_level_offset_host[l], nc = x.c_level_offset_host[l + 1] - clo;
     if (nh + nc == 0) return;
-    hipLaunchKernelGGL((k_x_up<KMAX>), dim3(blocks_for(static_cast<int64_t>(nh) + nc)), dim3(kBlock),
-                       0, st, hlo, nh, clo, nc, l == 0 ? 1 : 0, x.N, x.child_begin,
+    const int64_t units = static_cast<int64_t>(nh) + nc;
+    const int threads = pick(x.up_block, units);
+    hipLaunchKernelGGL((k_x_up<KMAX>), dim3(blocks_of(units, threads)), dim3(threads), 0, st, hlo, nh, clo, nc, (l == 0 && x.level_offset_host[1] == 1) ? 1 : 0, x.N,
+                       x.child_begin,
                        x.child_stride, x.child_list, x.q_offset, x.iplayer, x.member_offset,
                        x.members, x.chance_nodes, x.chance_base, x.chance_k, x.prob, x.value,
                        x.reach, x.R, x.S, x.T, variant, linear);
 }
 
 void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st, LaunchTimer* timer) {
-    auto pre = [&](int k) { if (timer) timer->before(k, st); };
+    auto pre = [&](int k, int l, int64_t n) { if (timer) timer->before(k, l, n, st); };
     auto post = [&](int k) { if (timer) timer->after(k, st); };
     const int32_t* lo = x.level_offset_host;
     for (int32_t l = 1; l < x.D; ++l) {
-        pre(XK_REACH);
-        hipLaunchKernelGGL(k_x_reach, dim3(blocks_for(lo[l + 1] - lo[l])), dim3(kBlock), 0, st,
-                           lo[l], lo[l + 1], x.N, x.parent, x.edge, x.meta, x.prob, x.reach);
+        const int64_t units = lo[l + 1] - lo[l];
+        const int threads = pick(x.reach_block, units);
+        pre(XK_REACH, l, units);
+        hipLaunchKernelGGL(k_x_reach, dim3(blocks_of(units, threads)), dim3(threads), 0, st, lo[l],
+                           lo[l + 1], x.N, x.parent, x.edge, x.meta, x.prob, x.reach);
         post(XK_REACH);
     }
     for (int32_t l = x.D; l >= 0; --l) {
         const int32_t nunits = x.h_level_offset_host[l + 1] - x.h_level_offset_host[l] +
                                x.c_level_offset_host[l + 1] - x.c_level_offset_host[l];
-        if (nunits == 0) {
-            // the root level holds one terminal node only: still count the iteration
-            if (l == 0) hipLaunchKernelGGL(k_x_tick, dim3(1), dim3(64), 0, st, x.T);
-            continue;
-        }
-        pre(XK_UP);
+        if (nunits == 0) continue;
+        pre(XK_UP, l, nunits);
         if (x.max_actions <= 4) launch_up<4>(x, l, variant, linear, st);
         else launch_up<16>(x, l, variant, linear, st);
         post(XK_UP);
     }
+    // a single root ticks the iteration counter in its own unit; otherwise (a forest, or a
+    // lone terminal root) a one-thread launch does
+    const bool root_ticks = x.level_offset_host[1] == 1 &&
+                            x.h_level_offset_host[1] + x.c_level_offset_host[1] > 0;
+    if (!root_ticks) hipLaunchKernelGGL(k_x_tick, dim3(1), dim3(64), 0, st, x.T);
 }
 
 void launch_x_best_response(const XDev& x, const float* avgprob, int player, hipStream_t st) {
     const float sgn = player == 1 ? 1.0f : -1.0f;
-    hipLaunchKernelGGL(k_x_br_init, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N, x.meta,
-                       x.payoff, sgn, x.br_value, x.br_reach);
+    hipLaunchKernelGGL(k_x_br_init, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N,
+                       x.level_offset_host[1], x.meta, x.payoff, sgn, x.br_value, x.br_reach);
     const int32_t* lo = x.level_offset_host;
     for (int32_t l = 1; l < x.D; ++l)
         hipLaunchKernelGGL(k_x_br_reach, dim3(blocks_for(lo[l + 1] - lo[l])), dim3(kBlock), 0, st,
@@ -331,7 +355,9 @@ void launch_x_best_response(const XDev& x, const float* avgprob, int player, hip
                            x.chance_nodes, x.chance_base, x.chance_k, avgprob, x.br_reach,
                            x.br_value);
     }
-    hipLaunchKernelGGL(k_x_store_root, dim3(1), dim3(64), 0, st, x.br_value, x.out2 + (player - 1));
+    const int32_t n_roots = x.level_offset_host[1];
+    hipLaunchKernelGGL(k_x_store_roots, dim3(blocks_for(n_roots)), dim3(kBlock), 0, st, n_roots,
+                       player, x.br_value, x.out2);
 }
 
 void launch_x_values_to_canonical(const XDev& x, float* dst, hipStream_t st) {

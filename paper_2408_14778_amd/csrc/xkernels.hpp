@@ -13,9 +13,16 @@ namespace cfr {
 enum XKernelKind { XK_REACH = K_NUM_KINDS, XK_UP = K_NUM_KINDS + 1 };
 const char* xkernel_kind_name(int kind);
 
+// Launch shapes: threads per workgroup for a launch of `units` work items is
+// table[bucket(units)], bucket = floor(log2(units)) clamped to [0, kShapeBuckets).
+constexpr int kShapeBuckets = 32;
+int shape_bucket(int64_t units);
+
 struct XDev {
     int64_t N, Hp, Qp, Q0, M, L, C;
     int32_t D, max_actions;
+    const int32_t* up_block;     // host, kShapeBuckets entries (nullptr: 256 threads)
+    const int32_t* reach_block;  // host, kShapeBuckets entries (nullptr: 256 threads)
     // host copies of the level tables (launch bounds)
     const int32_t* level_offset_host;
     const int32_t* h_level_offset_host;

@@ -2,6 +2,7 @@
 #include "xplan.hpp"
 
 #include <algorithm>
+#include <limits>
 #include <numeric>
 #include <tuple>
 
@@ -150,6 +151,14 @@ int build_exec_plan(const Layout& L, ExecPlan& P, std::string& err) {
     P.h_level_offset[D + 1] = static_cast<int32_t>(P.infoset_canon.size());
     P.c_level_offset[D + 1] = static_cast<int32_t>(P.chance_nodes.size());
     P.C = static_cast<int64_t>(P.chance_nodes.size());
+    P.chance_base.resize(P.C);
+    P.chance_k.resize(P.C);
+    for (int64_t i = 0; i < P.C; ++i) {
+        const int32_t hc = L.node_infoset[P.canon_of[P.chance_nodes[i]]];
+        P.chance_base[i] = static_cast<int32_t>(L.Qp + L.cq_offset[hc]);
+        P.chance_k[i] = L.cq_offset[hc + 1] - L.cq_offset[hc];
+    }
+    P.chance_prob = L.chance_prob;
     if (static_cast<int64_t>(P.infoset_canon.size()) != L.Hp) {
         err = "exec plan lost infosets";
         return CFR_EINVAL;
@@ -227,6 +236,159 @@ int build_exec_plan(const Layout& L, ExecPlan& P, std::string& err) {
         }
     }
     P.L = static_cast<int64_t>(P.child_list.size());
+    return CFR_OK;
+}
+
+int build_forest_plan(const std::vector<ExecPlan>& G, ExecPlan& F, std::string& err) {
+    F = ExecPlan();
+    const size_t n = G.size();
+    if (n == 0) {
+        err = "empty batch";
+        return CFR_EINVAL;
+    }
+    int32_t D = 0;
+    int64_t N = 0, Hp = 0, Qp = 0, Q0 = 0, M = 0, Lc = 0, C = 0;
+    for (const ExecPlan& P : G) {
+        D = std::max(D, P.D);
+        N += P.N; Hp += P.Hp; Qp += P.Qp; Q0 += P.Q0; M += P.M; Lc += P.L; C += P.C;
+    }
+    if (N >= std::numeric_limits<int32_t>::max() || Qp + Q0 >= std::numeric_limits<int32_t>::max()) {
+        err = "batch exceeds the int32 index range";
+        return CFR_EINVAL;
+    }
+    F.N = N; F.D = D; F.Hp = Hp; F.Qp = Qp; F.Q0 = Q0; F.M = M; F.L = Lc; F.C = C;
+    auto lvl = [](const ExecPlan& P, int32_t l, const std::vector<int32_t>& off) {
+        return l <= P.D ? off[l + 1] - off[l] : 0;
+    };
+    // level offsets and per-(game, level) bases for nodes, infosets, chance nodes
+    std::vector<std::vector<int64_t>> nb(n, std::vector<int64_t>(D + 1)), hb = nb, cb = nb;
+    F.level_offset.assign(D + 2, 0);
+    F.h_level_offset.assign(D + 2, 0);
+    F.c_level_offset.assign(D + 2, 0);
+    int64_t pos = 0, hpos = 0, cpos = 0;
+    for (int32_t l = 0; l <= D; ++l) {
+        F.level_offset[l] = static_cast<int32_t>(pos);
+        F.h_level_offset[l] = static_cast<int32_t>(hpos);
+        F.c_level_offset[l] = static_cast<int32_t>(cpos);
+        for (size_t g = 0; g < n; ++g) {
+            nb[g][l] = pos;
+            hb[g][l] = hpos;
+            cb[g][l] = cpos;
+            pos += lvl(G[g], l, G[g].level_offset);
+            hpos += lvl(G[g], l, G[g].h_level_offset);
+            cpos += lvl(G[g], l, G[g].c_level_offset);
+        }
+    }
+    F.level_offset[D + 1] = static_cast<int32_t>(pos);
+    F.h_level_offset[D + 1] = static_cast<int32_t>(hpos);
+    F.c_level_offset[D + 1] = static_cast<int32_t>(cpos);
+    // node and infoset maps of every game into the forest
+    std::vector<std::vector<int32_t>> node_map(n), h_map(n);
+    for (size_t g = 0; g < n; ++g) {
+        const ExecPlan& P = G[g];
+        node_map[g].resize(P.N);
+        h_map[g].resize(P.Hp);
+        for (int32_t l = 0; l <= P.D; ++l) {
+            for (int32_t x = P.level_offset[l]; x < P.level_offset[l + 1]; ++x)
+                node_map[g][x] = static_cast<int32_t>(nb[g][l] + (x - P.level_offset[l]));
+            for (int32_t h = P.h_level_offset[l]; h < P.h_level_offset[l + 1]; ++h)
+                h_map[g][h] = static_cast<int32_t>(hb[g][l] + (h - P.h_level_offset[l]));
+        }
+    }
+    // forest infosets in forest order: pair offsets, players, members
+    std::vector<int32_t> h_game(Hp), h_local(Hp);
+    for (size_t g = 0; g < n; ++g)
+        for (int64_t h = 0; h < G[g].Hp; ++h) {
+            h_game[h_map[g][h]] = static_cast<int32_t>(g);
+            h_local[h_map[g][h]] = static_cast<int32_t>(h);
+        }
+    F.q_offset.assign(Hp + 1, 0);
+    F.member_offset.assign(Hp + 1, 0);
+    F.infoset_player.resize(Hp);
+    F.infoset_canon.resize(Hp);
+    for (int64_t h = 0; h < Hp; ++h) {
+        const ExecPlan& P = G[h_game[h]];
+        const int32_t hl = h_local[h];
+        F.q_offset[h + 1] = F.q_offset[h] + (P.q_offset[hl + 1] - P.q_offset[hl]);
+        F.member_offset[h + 1] = F.member_offset[h] + (P.member_offset[hl + 1] - P.member_offset[hl]);
+        F.infoset_player[h] = P.infoset_player[hl];
+        F.infoset_canon[h] = static_cast<int32_t>(h);
+    }
+    // pair maps: forest pair of (game, local pair); batch input order = concatenated inputs
+    std::vector<int64_t> in_base(n + 1, 0), q0_base(n + 1, 0);
+    for (size_t g = 0; g < n; ++g) {
+        in_base[g + 1] = in_base[g] + G[g].Qp;
+        q0_base[g + 1] = q0_base[g] + G[g].Q0;
+    }
+    std::vector<std::vector<int32_t>> q_map(n);
+    for (size_t g = 0; g < n; ++g) q_map[g].resize(G[g].Qp);
+    F.q_input.resize(Qp);
+    F.members.resize(M);
+    for (int64_t h = 0; h < Hp; ++h) {
+        const int32_t g = h_game[h];
+        const ExecPlan& P = G[g];
+        const int32_t hl = h_local[h];
+        for (int32_t a = 0; a < P.q_offset[hl + 1] - P.q_offset[hl]; ++a) {
+            q_map[g][P.q_offset[hl] + a] = F.q_offset[h] + a;
+            F.q_input[F.q_offset[h] + a] = static_cast<int32_t>(in_base[g] + P.q_input[P.q_offset[hl] + a]);
+        }
+        for (int32_t m = 0; m < P.member_offset[hl + 1] - P.member_offset[hl]; ++m)
+            F.members[F.member_offset[h] + m] = node_map[g][P.members[P.member_offset[hl] + m]];
+    }
+    // per-node arrays
+    F.parent.resize(N);
+    F.edge.resize(N);
+    F.meta.resize(N);
+    F.child_begin.assign(N, 0);
+    F.child_stride.assign(N, 0);
+    F.payoff.resize(N);
+    F.canon_of.resize(N);
+    F.child_list.reserve(Lc);
+    int64_t node_base = 0;
+    for (size_t g = 0; g < n; ++g) {
+        const ExecPlan& P = G[g];
+        const int64_t list_base = static_cast<int64_t>(F.child_list.size());
+        for (int64_t x = 0; x < P.N; ++x) {
+            const int32_t f = node_map[g][x];
+            F.parent[f] = P.parent[x] < 0 ? -1 : node_map[g][P.parent[x]];
+            const int32_t e = P.edge[x];
+            F.edge[f] = e < 0 ? -1
+                        : e < P.Qp ? q_map[g][e]
+                                   : static_cast<int32_t>(Qp + q0_base[g] + (e - P.Qp));
+            F.meta[f] = P.meta[x];
+            F.payoff[f] = P.payoff[x];
+            F.canon_of[f] = static_cast<int32_t>(node_base + P.canon_of[x]);
+            if ((P.meta[x] & 3) == 0) continue;
+            if (P.child_stride[x] != 0) {
+                // children at c0 + a * stride in the game map to the same pattern in the forest:
+                // a game's level is contiguous in the forest level
+                F.child_begin[f] = node_map[g][P.child_begin[x]];
+                F.child_stride[f] = P.child_stride[x];
+            } else {
+                F.child_begin[f] = static_cast<int32_t>(list_base + P.child_begin[x]);
+                F.child_stride[f] = 0;
+            }
+        }
+        for (int32_t c : P.child_list) F.child_list.push_back(node_map[g][c]);
+        node_base += P.N;
+    }
+    // chance units, chance probabilities
+    F.chance_nodes.resize(C);
+    F.chance_base.resize(C);
+    F.chance_k.resize(C);
+    for (size_t g = 0; g < n; ++g) {
+        const ExecPlan& P = G[g];
+        for (int32_t l = 0; l <= P.D; ++l)
+            for (int32_t i = P.c_level_offset[l]; i < P.c_level_offset[l + 1]; ++i) {
+                const int64_t fi = cb[g][l] + (i - P.c_level_offset[l]);
+                F.chance_nodes[fi] = node_map[g][P.chance_nodes[i]];
+                F.chance_base[fi] = static_cast<int32_t>(Qp + q0_base[g] + (P.chance_base[i] - P.Qp));
+                F.chance_k[fi] = P.chance_k[i];
+            }
+        F.chance_prob.insert(F.chance_prob.end(), P.chance_prob.begin(), P.chance_prob.end());
+        F.n_blocks += P.n_blocks;
+        F.n_listed += P.n_listed;
+    }
     return CFR_OK;
 }
 

@@ -49,6 +49,9 @@ struct ExecPlan {
     // chance nodes per level
     std::vector<int32_t> chance_nodes;   // exec indices, level-major
     std::vector<int32_t> c_level_offset; // D + 2
+    std::vector<int32_t> chance_base;    // per chance node: index into [sigma | sigma_0] of action 0
+    std::vector<int32_t> chance_k;       // per chance node: number of actions
+    std::vector<float> chance_prob;      // sigma_0, Q0 entries (the tail of the probability array)
     // pair maps
     std::vector<int32_t> q_input;        // exec pair -> input pair
     int64_t n_blocks = 0;
@@ -57,5 +60,11 @@ struct ExecPlan {
 
 // Requires level-pure infosets. Returns CFR_OK or an error code with a message.
 int build_exec_plan(const Layout& L, ExecPlan& P, std::string& err);
+
+// Forest of independent games, level-major: level l of the forest is level l of game 0, then
+// of game 1, ...; so level 0 holds the games' roots in game order. Infosets and pairs are
+// numbered per level across games; q_input maps a forest pair to its position in the
+// concatenation of the games' input pair orders (game 0's pairs first).
+int build_forest_plan(const std::vector<ExecPlan>& games, ExecPlan& F, std::string& err);
 
 }  // namespace cfr

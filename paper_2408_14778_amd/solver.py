@@ -113,7 +113,7 @@ class Solver:
     """CFR (vanilla or CFR+) over one game, resident on one GPU."""
 
     def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
-                 graph: bool = True, stream=None, engine: str = "auto"):
+                 graph: bool = True, stream=None, engine: str = "auto", tuned: bool = True):
         import torch
 
         self._lib = N.load()
@@ -137,6 +137,9 @@ class Solver:
         self._h = handle
         self.n_q = int(info.n_q)
         self.n_nodes = int(info.n_nodes)
+        if tuned:
+            from . import autotune
+            autotune.apply(self, autotune.load())
 
     # -- iteration ------------------------------------------------------------------
     def iterate(self, n: int = 1) -> None:
@@ -155,6 +158,32 @@ class Solver:
             if name and cnt[k]:
                 out[name] = (int(cnt[k]), float(ms[k]))
         return out
+
+    def iterate_profile(self, n: int) -> list:
+        """n iterations; per launch of one iteration: kernel, level, work items, mean ms."""
+        cap = 4096
+        ms = np.zeros(cap, dtype=np.float64)
+        kind = np.zeros(cap, dtype=np.int32)
+        level = np.zeros(cap, dtype=np.int32)
+        units = np.zeros(cap, dtype=np.int64)
+        nl = ctypes.c_int32()
+        N.check(self._lib.cfr_iterate_profile(self._h, int(n), _ptr(ms, ctypes.c_double),
+                                              _ptr(kind, ctypes.c_int32), _ptr(level, ctypes.c_int32),
+                                              _ptr(units, ctypes.c_int64), cap, ctypes.byref(nl)))
+        return [{"kernel": self._lib.cfr_kernel_name(int(kind[i])).decode(), "level": int(level[i]),
+                 "units": int(units[i]), "ms": float(ms[i]) / n} for i in range(min(nl.value, cap))]
+
+    def set_launch_shape(self, up_threads=None, reach_threads=None) -> None:
+        """Threads per workgroup per log2 bucket of work items (None: default 256)."""
+        if up_threads is None and reach_threads is None:
+            N.check(self._lib.cfr_set_launch_shape(self._h, None, None, 0))
+            return
+        up = np.ascontiguousarray(up_threads if up_threads is not None else [256] * 32, np.int32)
+        re = np.ascontiguousarray(reach_threads if reach_threads is not None else [256] * 32,
+                                  np.int32)
+        n = min(len(up), len(re))
+        N.check(self._lib.cfr_set_launch_shape(self._h, _ptr(up, ctypes.c_int32),
+                                               _ptr(re, ctypes.c_int32), n))
 
     def synchronize(self) -> None:
         self.stream.synchronize()
@@ -227,3 +256,55 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class BatchSolver(Solver):
+    """Many independent games solved together (one forest, one graph replay per iteration).
+
+    Pair vectors (state, strategies) concatenate the games' input pair orders, game 0 first;
+    ``pair_offsets[g]`` is where game g's pairs start."""
+
+    def __init__(self, game_list, variant: str = "cfr+", averaging=None, device: str = "cuda",
+                 graph: bool = True, stream=None, tuned: bool = True):
+        import torch
+
+        self._lib = N.load()
+        self.variant = variant
+        self._args = [GameArgs(g) for g in game_list]
+        n = len(self._args)
+        arr = (N.CfrGame * n)(*[a.struct for a in self._args])
+        cfg = make_config(variant, averaging, graph)
+        info = N.CfrPlanInfo()
+        N.check(self._lib.cfr_plan_batch(arr, n, ctypes.byref(cfg), ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8,
+                                     device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        N.check(self._lib.cfr_build_batch(arr, n, ctypes.byref(cfg),
+                                          ctypes.c_void_p(self.workspace.data_ptr()),
+                                          ctypes.c_size_t(int(info.workspace_bytes)),
+                                          ctypes.c_void_p(self.stream.cuda_stream),
+                                          ctypes.byref(handle)))
+        self._args = None
+        self._h = handle
+        self.n_games = n
+        self.n_q = int(info.n_q)
+        self.n_nodes = int(info.n_nodes)
+        qs = [int(np.sum(g.infoset_num_actions[g.infoset_player != 0])) for g in game_list]
+        self.pair_offsets = np.concatenate([[0], np.cumsum(qs)]).astype(np.int64)
+        if tuned:
+            from . import autotune
+            autotune.apply(self, autotune.load())
+
+    def exploitability(self) -> dict:
+        expl = np.empty(self.n_games, dtype=np.float64)
+        br = np.empty(2 * self.n_games, dtype=np.float64)
+        N.check(self._lib.cfr_exploitability_batch(self._h, _ptr(expl, ctypes.c_double),
+                                                   _ptr(br, ctypes.c_double), self.n_games))
+        return {"expl": expl, "br1": br[0::2], "br2": br[1::2]}
+
+    def split(self, vec):
+        """Per-game slices of a concatenated pair vector."""
+        return [vec[self.pair_offsets[g]:self.pair_offsets[g + 1]] for g in range(self.n_games)]

@@ -1,0 +1,132 @@
+"""GPU checks of batched solving: many subgames laid out as one forest must give, game by
+game, what solving each game alone gives, and what the FP64 oracle gives."""
+import numpy as np
+import pytest
+
+import games
+from oracle import br, cfr
+from oracle.tree import Tree
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max()) / max(float(np.abs(b).max()), 1e-30)
+
+
+def _mixed_games():
+    # subgames of several start rounds and depths, plus small games of other shapes
+    out = [games.subgame(s) for s in (102, 103, 109, 111, 113)]
+    out += [games.kuhn_like(3, "joint"), games.random_game(61, deal="sequential", depth=5),
+            games.leduc_like(3, 2, deal="sequential"), games.rock_paper_scissors()]
+    return out
+
+
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
+def test_batch_one_iteration_matches_single_and_oracle(variant):
+    from paper_2408_14778_amd import BatchSolver, Solver
+    gl = _mixed_games()
+    states = [games.random_state(g, seed=7 + i, nonnegative=(variant == "cfr+"))
+              for i, g in enumerate(gl)]
+    T = 37
+    R = np.concatenate([st[1] for st in states])
+    S = np.concatenate([st[2] for st in states])
+    b = BatchSolver(gl, variant)
+    assert b.n_q == len(R)
+    b.set_state(T, R, S)
+    b.iterate(1)
+    Tb, Rb, Sb = b.get_state()
+    assert Tb == T + 1
+    for g, (Rg, Sg), st in zip(gl, zip(b.split(Rb), b.split(Sb)), states):
+        s = Solver(g, variant)
+        s.set_state(T, st[1], st[2])
+        s.iterate(1)
+        _, Rs, Ss = s.get_state()
+        assert _rel(Rg, Rs) <= 1e-6 and _rel(Sg, Ss) <= 1e-6
+        if g.n_nodes <= 20000:
+            t = Tree(g)
+            new, _ = cfr.iterate(t, cfr.State(T, [float(x) for x in st[1]],
+                                              [float(x) for x in st[2]]), variant)
+            assert _rel(Rg, new.R) <= 1e-6 and _rel(Sg, new.S) <= 1e-6
+
+
+def test_batch_exploitability_per_game():
+    from paper_2408_14778_amd import BatchSolver, Solver
+    gl = _mixed_games()
+    b = BatchSolver(gl, "cfr+")
+    b.iterate(150)
+    e = b.exploitability()
+    assert e["expl"].shape == (len(gl),)
+    for i, g in enumerate(gl):
+        s = Solver(g, "cfr+")
+        s.iterate(150)
+        es = s.exploitability()
+        assert abs(e["expl"][i] - es["expl"]) <= 1e-5 * max(1.0, abs(es["expl"]))
+        if g.n_nodes <= 20000:
+            t = Tree(g)
+            st = cfr.solve(t, 150, "cfr+")
+            ref = br.exploitability(t, cfr.average_strategy(t, st.S))
+            assert abs(e["expl"][i] - ref["expl"]) <= 1e-4
+
+
+def test_batch_average_strategy_splits_by_game():
+    from paper_2408_14778_amd import BatchSolver, Solver
+    gl = _mixed_games()[:4]
+    b = BatchSolver(gl, "vanilla")
+    b.iterate(20)
+    avg = b.split(b.average_strategy())
+    for g, a in zip(gl, avg):
+        s = Solver(g, "vanilla")
+        s.iterate(20)
+        assert _rel(a, s.average_strategy()) <= 1e-5
+
+
+def test_batch_rejects_non_level_pure_game():
+    from paper_2408_14778_amd import BatchSolver, CfrError
+    bld = games.GameBuilder("skew")
+    root = bld.node(-1, -1)
+    bld.decide(root, bld.infoset_id("c", 0, 2, [0.5, 0.5]))
+    x, y = bld.node(root, 0), bld.node(root, 1)
+    hp = bld.infoset_id("p1", 1, 2)
+    bld.decide(x, hp)
+    bld.decide(y, bld.infoset_id("c2", 0, 1, [1.0]))
+    z = bld.node(y, 0)
+    bld.decide(z, hp)
+    for v in (x, z):
+        for a in range(2):
+            bld.terminal(bld.node(v, a), float(a))
+    with pytest.raises(CfrError, match="CFR_ELEVEL"):
+        BatchSolver([games.kuhn_like(3), bld.build()])
+
+
+def test_launch_shapes_do_not_change_results():
+    """Every work item's arithmetic is independent of the workgroup size: bit-identical."""
+    from paper_2408_14778_amd import BatchSolver
+    gl = _mixed_games()
+    ref = BatchSolver(gl, "cfr+", tuned=False)
+    ref.iterate(9)
+    _, R0, S0 = ref.get_state()
+    for threads in (64, 128, 512, 1024):
+        b = BatchSolver(gl, "cfr+", tuned=False)
+        b.set_launch_shape([threads] * 32, [threads] * 32)
+        b.iterate(9)
+        _, R, S = b.get_state()
+        assert np.array_equal(R, R0) and np.array_equal(S, S0), threads
+
+
+def test_autotuner_measures_and_chooses():
+    from paper_2408_14778_amd import BatchSolver, autotune
+    gl = [games.subgame(100 + i) for i in range(12)]
+    b = BatchSolver(gl, "cfr+", tuned=False)
+    b.iterate(2)
+    T0, R0, S0 = b.get_state()
+    m = autotune.measure(b, candidates=(64, 256), iters=2)
+    T1, R1, S1 = b.get_state()
+    assert T1 == T0 and np.array_equal(R1, R0)      # state restored
+    assert "block_up" in m and "block_reach" in m
+    table = autotune.choose(m)
+    assert len(table["up_threads"]) == 32 and set(table["up_threads"]) <= {64, 256}
+    autotune.apply(b, table)
+    b.iterate(1)
