@@ -43,14 +43,16 @@ class _Template:
         self.term: list[int] = []
         self.commit: list[int] = []
         self.depth: list[int] = []
+        self.info: list[tuple] = []    # decision nodes: (c1, c2, raises, last, round, amask)
         self._bet_ids: dict = {}
         self.n_rounds, self.fanouts, self.cap, self.stack = n_rounds, list(fanouts), cap, stack
         self._round(-1, -1, 0, c0, c0, 0, 1, False, (), (), 0)
 
-    def _new(self, parent, action, kind, nact, bet, slot, depth, term=-1, commit=0):
+    def _new(self, parent, action, kind, nact, bet, slot, depth, term=-1, commit=0, info=None):
         self.parent.append(parent); self.action.append(action); self.kind.append(kind)
         self.nact.append(nact); self.bet.append(bet); self.slot.append(slot)
         self.term.append(term); self.commit.append(commit); self.depth.append(depth)
+        self.info.append(info if info is not None else (0, 0, 0, 0, 0, 0))
         return len(self.parent) - 1
 
     def _bet_id(self, path):
@@ -73,7 +75,11 @@ class _Template:
             if me < self.stack:
                 acts.append(("a", self.stack))
         kind = KIND_P1 if actor == 1 else KIND_P2
-        v = self._new(parent, action, kind, len(acts), self._bet_id(path), slot, depth)
+        this_round = path[len(path) - path[::-1].index("|"):] if "|" in path else path
+        last = {"c": 1, "p": 2, "a": 3}.get(this_round[-1], 0) if this_round else 0
+        amask = sum({"f": 1, "c": 2, "p": 4, "a": 8}[a[0]] for a in acts)
+        v = self._new(parent, action, kind, len(acts), self._bet_id(path), slot, depth,
+                      info=(c1, c2, raises, last, rnd, amask))
         for a, act in enumerate(acts):
             if act[0] == "f":
                 self._new(v, a, KIND_TERM, 0, -1, slot, depth + 1,
@@ -114,6 +120,8 @@ def _arrays(t: _Template) -> dict:
         "slot": slots,
         "term": np.asarray(t.term, dtype=np.int64),
         "commit": np.asarray(t.commit, dtype=np.int64),
+        "info": np.asarray(t.info, dtype=np.int64),
+        "depth": np.asarray(t.depth, dtype=np.int64),
         "n": n,
     }
 
@@ -219,6 +227,29 @@ def poker_game(n_ranks: int = 13, n_rounds: int = 3, cap: int = 3, stack: int = 
     node_infoset[1 + dec] = inv
     h_player = (kind[dec[first]]).astype(np.int8)
     h_nact = tpl["nact"][t_idx[dec[first]]]
+    # per-infoset descriptors (from the first member) for the warm-start features
+    fm = dec[first]
+    ti = t_idx[fm]
+    inf = tpl["info"][ti]
+    desc = np.full((n_player_h, 16), -1, dtype=np.int16)
+    pl = kind[fm]
+    desc[:, 0] = pl
+    desc[:, 1] = np.where(pl == KIND_P1, r1[fm], r2[fm])
+    desc[:, 2] = len(board) + inf[:, 4]
+    pubs = [np.full(n_player_h, b, dtype=np.int64) for b in board] + [p1[fm], p2[fm]]
+    pubs = np.stack(pubs[:3], axis=1) if len(pubs) >= 3 else np.stack(
+        pubs + [np.full(n_player_h, -1)] * (3 - len(pubs)), axis=1)
+    desc[:, 3:6] = pubs[:, :3]
+    desc[:, 6] = inf[:, 2]
+    desc[:, 7] = inf[:, 3]
+    desc[:, 8] = np.where(pl == KIND_P1, inf[:, 0], inf[:, 1])
+    desc[:, 9] = np.where(pl == KIND_P1, inf[:, 1], inf[:, 0])
+    desc[:, 10] = stack
+    desc[:, 11] = inf[:, 5]
+    desc[:, 12] = tpl["depth"][ti]
+    desc[:, 13] = cap
+    desc[:, 14] = n_ranks
+    desc[:, 15] = 0
     del key, own, inv
 
     # chance infosets: the root, then every chance node in id order (its own infoset)
@@ -255,7 +286,8 @@ def poker_game(n_ranks: int = 13, n_rounds: int = 3, cap: int = 3, stack: int = 
         payoff_u1=payoff,
         payoff_u2=None,
         meta={"kind": "poker", "n_ranks": n_ranks, "n_rounds": n_rounds, "cap": cap,
-              "stack": stack, "c0": c0, "board": list(board), "deals": nd, "template_nodes": tn},
+              "stack": stack, "c0": c0, "board": list(board), "deals": nd, "template_nodes": tn,
+              "infoset_desc": desc},
     )
 
 
@@ -309,4 +341,8 @@ def subgame(seed: int) -> Game:
     g = poker_game(s["ranks"], s["n_rounds"], s["cap"], s["stack"], s["c0"], s["board"],
                    deal_prob=w / w.sum(), scale=True, name=f"subgame{seed}")
     g.meta.update({k: v for k, v in s.items() if k not in ("b1", "b2")})
+    bel = np.zeros((2, 13), dtype=np.float32)
+    bel[0, :s["ranks"]] = s["b1"]
+    bel[1, :s["ranks"]] = s["b2"]
+    g.meta["beliefs"] = bel
     return g

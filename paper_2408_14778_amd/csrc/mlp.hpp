@@ -1,0 +1,47 @@
+// Warm-start network: descriptor layout and launch wrappers (kernels in mlp.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cfr {
+
+// Per-infoset descriptor of a poker subgame (int16 fields).
+enum DescField {
+    kDPlayer = 0,   // 1 or 2
+    kDOwn = 1,      // own private rank
+    kDRound = 2,    // absolute betting round 0..2
+    kDBoard0 = 3,   // public ranks dealt so far, -1 if none (3 slots)
+    kDRaises = 6,   // raises so far in this round
+    kDLast = 7,     // last action in this round: 0 none, 1 check/call, 2 pot-raise, 3 all-in
+    kDCMe = 8,      // own commitment
+    kDCOpp = 9,     // opponent's commitment
+    kDStack = 10,   // stack
+    kDMask = 11,    // legal slots: bit 0 fold, 1 call, 2 pot-raise, 3 all-in
+    kDDepth = 12,   // depth in the subgame
+    kDCap = 13,     // raise cap
+    kDRanks = 14,   // ranks in the deck
+    kDGame = 15,    // index of the game in the batch (beliefs row)
+    kDescFields = 16
+};
+constexpr int kFeatures = 81;  // meaningful features; the input width pads with zeros
+constexpr int kSlots = 4;      // action slots: fold, call, pot-raise, all-in
+
+void launch_gemm(int M, int N, int K, const void* A, int64_t a_i, int64_t a_k, const void* B,
+                 int64_t b_k, int64_t b_j, const float* bias, int mode, const void* gate, float* Cf,
+                 void* Cb, int64_t ldc, hipStream_t st);
+void launch_softmax_xent(int B, int A, const float* Z, const float* target, const float* mask,
+                         void* dZ, float* loss, hipStream_t st);
+void launch_colsum(int rows, int cols, const void* G, float* out, hipStream_t st);
+void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, void* wb, float lr,
+                 float b1, float b2, float eps, float c1, float c2, hipStream_t st);
+void launch_to_bf16(int64_t n, const float* src, void* dst, hipStream_t st);
+void launch_features(int64_t n, int F, const int16_t* desc, const float* beliefs, void* X,
+                     hipStream_t st);
+void launch_probs_to_pairs(int64_t n, int A, const float* Z, const int16_t* desc,
+                           const int64_t* q_off, float* probs, hipStream_t st);
+void launch_warm_start(int64_t Hp, const int32_t* q_offset, const int32_t* q_input,
+                       const float* probs, float w, float* R, float* S, float* sigma, hipStream_t st);
+
+}  // namespace cfr

@@ -10,7 +10,9 @@
 #include <vector>
 
 #include "../../include/cfr.h"
+#include "../../include/cfr_warmstart.h"
 #include "flatten.hpp"
+#include "mlp.hpp"
 #include "kernels.hpp"
 #include "xkernels.hpp"
 #include "xplan.hpp"
@@ -47,6 +49,14 @@ int set_err(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
+
+}  // namespace
+
+namespace cfr {
+int set_error(int code, const std::string& msg) { return set_err(code, msg); }
+}  // namespace cfr
+
+namespace {
 
 int hip_err(hipError_t e, const char* what) {
     return set_err(CFR_EHIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -878,6 +888,17 @@ int cfr_exploitability_batch(cfr_solver* s, double* expl, double* br_values, int
 }
 
 }  // extern "C"
+
+extern "C" int cfr_warm_start(cfr_solver* s, const float* probs, int64_t n_q, float weight) {
+    if (s == nullptr || probs == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    if (!(weight >= 0.0f)) return set_err(CFR_EINVAL, "weight must be >= 0");
+    cfr::launch_warm_start(s->dev.Hp, s->dev.sq_offset, s->dev.sq_input, probs, weight, s->dev.R,
+                           s->dev.S, s->dev.prob, s->stream);
+    cfr::launch_set_T(s->dev, 0, s->stream);
+    s->T = 0;
+    return check_hip("warm start");
+}
 
 struct cfr_host_layout {
     cfr::Layout L;
