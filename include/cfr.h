@@ -130,11 +130,13 @@ int cfr_iterate_profile(cfr_solver* s, int32_t n, double* launch_ms, int32_t* la
                         int32_t* launch_level, int64_t* launch_units, int32_t max_launches,
                         int32_t* n_launches);
 
-/* Launch shapes of the public-block engine: a launch of u work items uses
- * up_threads[b] (bottom-up) or reach_threads[b] (top-down) threads per workgroup with
- * b = min(floor(log2 u), n_buckets - 1); multiples of 64 in [64, 1024]. n_buckets = 0 restores
- * the default (256). Re-captures the iteration graph; the results do not depend on the shape.
- * Used by the autotuner; CFR_EINVAL for the node engine. */
+/* Launch shapes of the public-block engine. A top-down launch of u nodes uses
+ * reach_threads[b] threads per workgroup (multiples of 64 in [64, 1024]); the bottom-up launch
+ * of a level with u infoset members packs whole infosets into chunks of at most up_threads[b]
+ * members, one workgroup of that many threads per chunk (64, 128, 256 or 512); b = min(floor(
+ * log2 u), n_buckets - 1). n_buckets = 0 restores the defaults (256). Re-captures the iteration
+ * graph; the results do not depend on the shape. Used by the autotuner; CFR_EINVAL for the node
+ * engine. */
 int cfr_set_launch_shape(cfr_solver* s, const int32_t* up_threads, const int32_t* reach_threads,
                          int32_t n_buckets);
 

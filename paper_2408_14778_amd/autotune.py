@@ -24,7 +24,7 @@ import time
 import numpy as np
 
 N_BUCKETS = 32
-CANDIDATES = (64, 128, 256, 512, 1024)
+CANDIDATES = (64, 128, 256, 512)
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "gfx950.json")
 
 

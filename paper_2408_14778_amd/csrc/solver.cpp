@@ -27,6 +27,8 @@ struct cfr_solver {
     bool canonical = true;     // the canonical layout arrays are on the device
     std::vector<int32_t> x_level_offset, x_h_level_offset, x_c_level_offset;
     std::vector<int32_t> up_block, reach_block;  // launch shapes (empty: defaults)
+    std::vector<int32_t> x_member_offset;        // host copy (chunk tables)
+    std::vector<int32_t> x_k_level_offset, chunk_cap, x_m_level_offset;
     int variant = CFR_VANILLA;
     int linear = 0;
     bool use_graph = true;
@@ -157,6 +159,7 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
         x.chance_nodes = c.take<int32_t>(z.C);
         x.chance_base = c.take<int32_t>(z.C);
         x.chance_k = c.take<int32_t>(z.C);
+        x.chunk_first = c.take<int32_t>(Hp + D + 2);
         x.q_input = c.take<int32_t>(Qp);
         x.payoff = c.take<float>(N);
         x.prob = d.prob;
@@ -264,9 +267,18 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     s->x_level_offset = P.level_offset;
     s->x_h_level_offset = P.h_level_offset;
     s->x_c_level_offset = P.c_level_offset;
+    s->x_member_offset = P.member_offset;
+    s->x_k_level_offset = P.k_level_offset;
+    s->chunk_cap.assign(P.D + 1, cfr::kChunk);
+    s->x_m_level_offset.resize(P.D + 2);
+    for (int32_t l = 0; l <= P.D + 1; ++l) s->x_m_level_offset[l] = P.member_offset[P.h_level_offset[l]];
+    x.m_level_offset_host = s->x_m_level_offset.data();
     x.level_offset_host = s->x_level_offset.data();
     x.h_level_offset_host = s->x_h_level_offset.data();
     x.c_level_offset_host = s->x_c_level_offset.data();
+    x.k_level_offset_host = s->x_k_level_offset.data();
+    x.chunk_cap_host = s->chunk_cap.data();
+    if ((rc = upload(x.chunk_first, P.chunk_first, st))) return rc;
     return CFR_OK;
 }
 
@@ -499,24 +511,40 @@ int cfr_set_launch_shape(cfr_solver* s, const int32_t* up_threads, const int32_t
     if (s == nullptr || n_buckets < 0 || n_buckets > cfr::kShapeBuckets)
         return set_err(CFR_EINVAL, "bad argument");
     if (s->engine != ENGINE_BLOCK) return set_err(CFR_EINVAL, "launch shapes apply to the block engine");
-    auto fill = [&](const int32_t* src, std::vector<int32_t>& dst) -> bool {
+    auto fill = [&](const int32_t* src, std::vector<int32_t>& dst, bool chunk) -> bool {
         dst.assign(cfr::kShapeBuckets, 256);
         if (src == nullptr) return true;
         for (int32_t b = 0; b < cfr::kShapeBuckets; ++b) {
             const int32_t t = src[std::min(b, n_buckets - 1)];
-            if (t < 64 || t > 1024 || (t % 64) != 0) return false;
+            const bool ok = chunk ? (t == 64 || t == 128 || t == 256 || t == 512)
+                                  : (t >= 64 && t <= 1024 && (t % 64) == 0);
+            if (!ok) return false;
             dst[b] = t;
         }
         return true;
     };
-    if (n_buckets == 0) {
-        s->up_block.clear();
-        s->reach_block.clear();
-    } else if (!fill(up_threads, s->up_block) || !fill(reach_threads, s->reach_block)) {
-        return set_err(CFR_EINVAL, "threads per workgroup must be a multiple of 64 in [64, 1024]");
-    }
+    std::vector<int32_t> up, reach;
+    if (n_buckets > 0 && (!fill(up_threads, up, true) || !fill(reach_threads, reach, false)))
+        return set_err(CFR_EINVAL,
+                       "bottom-up sizes must be 64, 128, 256 or 512; top-down sizes multiples of 64 "
+                       "in [64, 1024]");
+    s->up_block = up;
+    s->reach_block = reach;
     s->xdev.up_block = s->up_block.empty() ? nullptr : s->up_block.data();
     s->xdev.reach_block = s->reach_block.empty() ? nullptr : s->reach_block.data();
+    // members per bottom-up workgroup, per level, from the level's member count
+    const int32_t D = s->xdev.D;
+    for (int32_t l = 0; l <= D; ++l) {
+        const int64_t members = s->x_m_level_offset[l + 1] - s->x_m_level_offset[l];
+        s->chunk_cap[l] = up.empty() ? cfr::kChunk : up[cfr::shape_bucket(members)];
+    }
+    std::vector<int32_t> chunk_first;
+    cfr::build_chunks(s->x_h_level_offset, s->x_member_offset, s->chunk_cap.data(), chunk_first,
+                      s->x_k_level_offset);
+    s->xdev.k_level_offset_host = s->x_k_level_offset.data();
+    HIP_TRY(hipStreamSynchronize(s->stream), "launch shape synchronise");
+    int rc = upload(s->xdev.chunk_first, chunk_first, s->stream);
+    if (rc != CFR_OK) return rc;
     HIP_TRY(hipStreamSynchronize(s->stream), "launch shape synchronise");
     if (s->exec != nullptr) (void)hipGraphExecDestroy(s->exec);
     if (s->graph != nullptr) (void)hipGraphDestroy(s->graph);

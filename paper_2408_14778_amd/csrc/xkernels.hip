@@ -65,70 +65,110 @@ __global__ void k_x_reach(int32_t lo, int32_t hi, int64_t N, const int32_t* __re
     reach[2 * N + x] = rc;
 }
 
-// Bottom-up of one level. Units [0, nh) are the level's infosets, [nh, nh + nc) its
-// chance nodes.
-template <int KMAX>
-__global__ void k_x_up(int32_t hlo, int32_t nh, int32_t clo, int32_t nc, int is_root_level,
-                       int64_t N, const int32_t* __restrict__ child_begin,
-                       const int32_t* __restrict__ child_stride,
-                       const int32_t* __restrict__ child_list,
-                       const int32_t* __restrict__ q_offset, const int8_t* __restrict__ iplayer,
-                       const int32_t* __restrict__ member_offset,
-                       const int32_t* __restrict__ members,
-                       const int32_t* __restrict__ chance_nodes,
-                       const int32_t* __restrict__ chance_base,
-                       const int32_t* __restrict__ chance_k, float* __restrict__ prob,
-                       float* __restrict__ value, const float* __restrict__ reach,
-                       float* __restrict__ R, float* __restrict__ S, int64_t* __restrict__ T,
-                       int variant, int linear) {
-    const int64_t u = gid();
-    if (u >= static_cast<int64_t>(nh) + nc) return;
-    if (u >= nh) {
-        const int32_t ci = clo + static_cast<int32_t>(u - nh);
+// Bottom-up of one level, member-parallel. Workgroup b < n_chunks takes chunk b: whole
+// infosets with at most CH members in total, one thread per member (or one infoset with more
+// members, each thread striding over them). Phase 1: each member's child values (gather by
+// stride), its value, its regret contributions cf * (w_a - v) and own reach, into LDS.
+// Phase 2: one thread per infoset sums its members' slots in member order (deterministic)
+// and applies the regret update, the average-strategy update and regret matching.
+// Workgroups past the chunks take the level's chance nodes, one thread each.
+template <int KMAX, int CH>
+__global__ void __launch_bounds__(CH) k_x_up_chunk(
+    int32_t chunk_lo, int32_t n_chunks, int32_t clo, int32_t nc, int64_t N,
+    const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ child_begin,
+    const int32_t* __restrict__ child_stride, const int32_t* __restrict__ child_list,
+    const int32_t* __restrict__ q_offset, const int8_t* __restrict__ iplayer,
+    const int32_t* __restrict__ member_offset, const int32_t* __restrict__ members,
+    const int32_t* __restrict__ chance_nodes, const int32_t* __restrict__ chance_base,
+    const int32_t* __restrict__ chance_k, float* __restrict__ prob, float* __restrict__ value,
+    const float* __restrict__ reach, float* __restrict__ R, float* __restrict__ S,
+    const int64_t* __restrict__ T, int variant, int linear) {
+    __shared__ float s_con[CH][KMAX];
+    __shared__ float s_own[CH];
+    __shared__ int32_t s_owner[CH];
+    const int tid = threadIdx.x;
+    const int32_t b = blockIdx.x;
+    if (b >= n_chunks) {
+        const int64_t i = static_cast<int64_t>(b - n_chunks) * CH + tid;
+        if (i >= nc) return;
+        const int32_t ci = clo + static_cast<int32_t>(i);
         const int32_t x = chance_nodes[ci];
         const int32_t base = chance_base[ci], k = chance_k[ci];
         float v = 0.0f;
         for (int32_t a = 0; a < k; ++a)
             v = fmaf(prob[base + a], value[child_of(child_begin, child_stride, child_list, x, a)], v);
         value[x] = v;
-        if (is_root_level) *T += 1;
         return;
     }
-    const int32_t h = hlo + static_cast<int32_t>(u);
+    const int32_t c = chunk_lo + b;
+    const int32_t h0 = chunk_first[c], h1 = chunk_first[c + 1];
+    const int32_t m0 = member_offset[h0], m1 = member_offset[h1];
+    const int32_t nm = m1 - m0;
+    const bool big = nm > CH;
+    if (!big) {
+        for (int32_t i = tid; i < h1 - h0; i += CH)
+            for (int32_t m = member_offset[h0 + i]; m < member_offset[h0 + i + 1]; ++m)
+                s_owner[m - m0] = i;
+        __syncthreads();
+    }
+    // phase 1
+    {
+        float con[KMAX];
+        float own = 0.0f;
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a) con[a] = 0.0f;
+        for (int32_t mi = tid; mi < nm; mi += CH) {
+            const int32_t h = big ? h0 : h0 + s_owner[mi];
+            const int player = iplayer[h];
+            const int32_t o = q_offset[h];
+            const int32_t k = q_offset[h + 1] - o;
+            const int32_t x = members[m0 + mi];
+            const int32_t st = child_stride[x];
+            const int32_t cb = child_begin[x];
+            float w[KMAX], sg[KMAX];
+            float v = 0.0f;
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a) {
+                if (a < k) {
+                    const int32_t ch = st != 0 ? cb + a * st : child_list[cb + a];
+                    w[a] = value[ch];
+                    sg[a] = prob[o + a];
+                    v = fmaf(sg[a], w[a], v);
+                } else {
+                    w[a] = 0.0f;
+                    sg[a] = 0.0f;
+                }
+            }
+            value[x] = v;
+            const float r1 = reach[x], r2 = reach[N + x], rc = reach[2 * N + x];
+            const float cf = (player == 1 ? r2 : r1) * rc;
+            own += player == 1 ? r1 : r2;
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a)
+                if (a < k) con[a] = fmaf(cf, w[a] - v, con[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a) s_con[tid][a] = con[a];
+        s_own[tid] = own;
+    }
+    __syncthreads();
+    // phase 2
+    const int32_t nh = h1 - h0;
+    if (tid >= nh) return;
+    const int32_t h = h0 + tid;
+    const int32_t slo = big ? 0 : member_offset[h] - m0;
+    const int32_t shi = big ? (nm < CH ? nm : CH) : member_offset[h + 1] - m0;
     const int player = iplayer[h];
     const int32_t o = q_offset[h];
     const int32_t k = q_offset[h + 1] - o;
-    float sigma[KMAX], racc[KMAX];
+    float racc[KMAX];
 #pragma unroll
-    for (int a = 0; a < KMAX; ++a) {
-        sigma[a] = a < k ? prob[o + a] : 0.0f;
-        racc[a] = 0.0f;
-    }
+    for (int a = 0; a < KMAX; ++a) racc[a] = 0.0f;
     float own = 0.0f;
-    const int32_t m0 = member_offset[h], m1 = member_offset[h + 1];
-    for (int32_t mi = m0; mi < m1; ++mi) {
-        const int32_t x = members[mi];
-        const int32_t st = child_stride[x];
-        const int32_t cb = child_begin[x];
-        float w[KMAX];
-        float v = 0.0f;
+    for (int32_t sl = slo; sl < shi; ++sl) {
 #pragma unroll
-        for (int a = 0; a < KMAX; ++a) {
-            if (a < k) {
-                const int32_t c = st != 0 ? cb + a * st : child_list[cb + a];
-                w[a] = value[c];
-                v = fmaf(sigma[a], w[a], v);
-            } else {
-                w[a] = 0.0f;
-            }
-        }
-        value[x] = v;
-        const float r1 = reach[x], r2 = reach[N + x], rc = reach[2 * N + x];
-        const float cf = (player == 1 ? r2 : r1) * rc;
-        own += player == 1 ? r1 : r2;
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a)
-            if (a < k) racc[a] = fmaf(cf, w[a] - v, racc[a]);
+        for (int a = 0; a < KMAX; ++a) racc[a] += s_con[sl][a];
+        own += s_own[sl];
     }
     const float sgn = player == 1 ? 1.0f : -1.0f;
     const float wt = linear ? static_cast<float>(*T + 1) : 1.0f;
@@ -136,11 +176,12 @@ __global__ void k_x_up(int32_t hlo, int32_t nh, int32_t clo, int32_t nc, int is_
 #pragma unroll
     for (int a = 0; a < KMAX; ++a) {
         if (a < k) {
+            const float sig = prob[o + a];
             float r = fmaf(sgn, racc[a], R[o + a]);
             if (variant == 1) r = fmaxf(r, 0.0f);
             R[o + a] = r;
-            S[o + a] = fmaf(wt * own, sigma[a], S[o + a]);
-            racc[a] = r;  // reuse as the new cumulative regret
+            S[o + a] = fmaf(wt * own, sig, S[o + a]);
+            racc[a] = r;
             pos_sum += fmaxf(r, 0.0f);
         }
     }
@@ -154,11 +195,8 @@ __global__ void k_x_up(int32_t hlo, int32_t nh, int32_t clo, int32_t nc, int is_
         for (int a = 0; a < KMAX; ++a)
             if (a < k) prob[o + a] = unif;
     }
-    if (is_root_level) *T += 1;
 }
 
-// Level 0 holds the root of every game of the plan (one for a single game, one per
-// subgame for a forest): their reach is 1.
 __global__ void k_x_reset_nodes(int64_t N, int32_t n_roots, const int8_t* __restrict__ meta,
                                 const float* __restrict__ payoff, float* __restrict__ value,
                                 float* __restrict__ reach) {
@@ -295,18 +333,26 @@ void launch_x_reset(const XDev& x, hipStream_t st) {
                        x.level_offset_host[1], x.meta, x.payoff, x.value, x.reach);
 }
 
-template <int KMAX>
-static void launch_up(const XDev& x, int32_t l, int variant, int linear, hipStream_t st) {
-    const int32_t hlo = x.h_level_offset_host[l], nh = x.h_level_offset_host[l + 1] - hlo;
+template <int KMAX, int CH>
+static void launch_up_chunk(const XDev& x, int32_t l, int variant, int linear, hipStream_t st) {
+    const int32_t klo = x.k_level_offset_host[l], nk = x.k_level_offset_host[l + 1] - klo;
     const int32_t clo = x.c_level_offset_host[l], nc = x.c_level_offset_host[l + 1] - clo;
-    if (nh + nc == 0) return;
-    const int64_t units = static_cast<int64_t>(nh) + nc;
-    const int threads = pick(x.up_block, units);
-    hipLaunchKernelGGL((k_x_up<KMAX>), dim3(blocks_of(units, threads)), dim3(threads), 0, st, hlo, nh, clo, nc, (l == 0 && x.level_offset_host[1] == 1) ? 1 : 0, x.N,
-                       x.child_begin,
-                       x.child_stride, x.child_list, x.q_offset, x.iplayer, x.member_offset,
-                       x.members, x.chance_nodes, x.chance_base, x.chance_k, x.prob, x.value,
-                       x.reach, x.R, x.S, x.T, variant, linear);
+    const int32_t grid = nk + (nc + CH - 1) / CH;
+    if (grid == 0) return;
+    hipLaunchKernelGGL((k_x_up_chunk<KMAX, CH>), dim3(grid), dim3(CH), 0, st, klo, nk, clo, nc, x.N,
+                       x.chunk_first, x.child_begin, x.child_stride, x.child_list, x.q_offset,
+                       x.iplayer, x.member_offset, x.members, x.chance_nodes, x.chance_base,
+                       x.chance_k, x.prob, x.value, x.reach, x.R, x.S, x.T, variant, linear);
+}
+
+template <int KMAX>
+static void launch_up_chunk_cap(const XDev& x, int32_t l, int variant, int linear, hipStream_t st) {
+    switch (x.chunk_cap_host != nullptr ? x.chunk_cap_host[l] : 256) {
+        case 64: launch_up_chunk<KMAX, 64>(x, l, variant, linear, st); break;
+        case 128: launch_up_chunk<KMAX, 128>(x, l, variant, linear, st); break;
+        case 512: launch_up_chunk<KMAX, 512>(x, l, variant, linear, st); break;
+        default: launch_up_chunk<KMAX, 256>(x, l, variant, linear, st); break;
+    }
 }
 
 void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st, LaunchTimer* timer) {
@@ -325,16 +371,13 @@ void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st, 
         const int32_t nunits = x.h_level_offset_host[l + 1] - x.h_level_offset_host[l] +
                                x.c_level_offset_host[l + 1] - x.c_level_offset_host[l];
         if (nunits == 0) continue;
-        pre(XK_UP, l, nunits);
-        if (x.max_actions <= 4) launch_up<4>(x, l, variant, linear, st);
-        else launch_up<16>(x, l, variant, linear, st);
+        pre(XK_UP, l, x.m_level_offset_host[l + 1] - x.m_level_offset_host[l]);
+        if (x.max_actions <= 4) launch_up_chunk_cap<4>(x, l, variant, linear, st);
+        else launch_up_chunk_cap<16>(x, l, variant, linear, st);
         post(XK_UP);
     }
-    // a single root ticks the iteration counter in its own unit; otherwise (a forest, or a
-    // lone terminal root) a one-thread launch does
-    const bool root_ticks = x.level_offset_host[1] == 1 &&
-                            x.h_level_offset_host[1] + x.c_level_offset_host[1] > 0;
-    if (!root_ticks) hipLaunchKernelGGL(k_x_tick, dim3(1), dim3(64), 0, st, x.T);
+    // the linear-averaging weight of every launch above read T: count the iteration last
+    hipLaunchKernelGGL(k_x_tick, dim3(1), dim3(64), 0, st, x.T);
 }
 
 void launch_x_best_response(const XDev& x, const float* avgprob, int player, hipStream_t st) {

@@ -21,8 +21,11 @@ int shape_bucket(int64_t units);
 struct XDev {
     int64_t N, Hp, Qp, Q0, M, L, C;
     int32_t D, max_actions;
-    const int32_t* up_block;     // host, kShapeBuckets entries (nullptr: 256 threads)
+    const int32_t* up_block;     // host, kShapeBuckets entries (unused by the chunked bottom-up)
     const int32_t* reach_block;  // host, kShapeBuckets entries (nullptr: 256 threads)
+    const int32_t* k_level_offset_host;  // D + 2: chunks of each level
+    const int32_t* chunk_cap_host;       // D + 1: members per chunk (= threads) of each level
+    const int32_t* m_level_offset_host;  // D + 2: first member of each level
     // host copies of the level tables (launch bounds)
     const int32_t* level_offset_host;
     const int32_t* h_level_offset_host;
@@ -42,6 +45,7 @@ struct XDev {
     int32_t* chance_nodes;
     int32_t* chance_base;  // index into prob of the chance node's action 0
     int32_t* chance_k;
+    int32_t* chunk_first;  // chunks + 1 (capacity Hp + D + 2)
     int32_t* q_input;
     float* payoff;
     // state (exec order)

@@ -236,7 +236,42 @@ int build_exec_plan(const Layout& L, ExecPlan& P, std::string& err) {
         }
     }
     P.L = static_cast<int64_t>(P.child_list.size());
+    build_chunks(P);
     return CFR_OK;
+}
+
+void build_chunks(const std::vector<int32_t>& hlo, const std::vector<int32_t>& mo,
+                  const int32_t* per_level, std::vector<int32_t>& chunk_first,
+                  std::vector<int32_t>& k_level_offset) {
+    const int32_t D = static_cast<int32_t>(hlo.size()) - 2;
+    chunk_first.clear();
+    k_level_offset.assign(D + 2, 0);
+    for (int32_t l = 0; l <= D; ++l) {
+        const int32_t cap = per_level != nullptr ? per_level[l] : kChunk;
+        k_level_offset[l] = static_cast<int32_t>(chunk_first.size());
+        int32_t h = hlo[l];
+        const int32_t hend = hlo[l + 1];
+        while (h < hend) {
+            chunk_first.push_back(h);
+            int32_t members = mo[h + 1] - mo[h];
+            int32_t count = 1;
+            ++h;
+            if (members > cap) continue;  // a large infoset alone
+            while (h < hend && count < cap) {
+                const int32_t m = mo[h + 1] - mo[h];
+                if (members + m > cap) break;
+                members += m;
+                ++count;
+                ++h;
+            }
+        }
+    }
+    k_level_offset[D + 1] = static_cast<int32_t>(chunk_first.size());
+    chunk_first.push_back(hlo[D + 1]);
+}
+
+void build_chunks(ExecPlan& P, const int32_t* per_level) {
+    build_chunks(P.h_level_offset, P.member_offset, per_level, P.chunk_first, P.k_level_offset);
 }
 
 int build_forest_plan(const std::vector<ExecPlan>& G, ExecPlan& F, std::string& err) {
@@ -389,6 +424,7 @@ int build_forest_plan(const std::vector<ExecPlan>& G, ExecPlan& F, std::string& 
         F.n_blocks += P.n_blocks;
         F.n_listed += P.n_listed;
     }
+    build_chunks(F);
     return CFR_OK;
 }
 

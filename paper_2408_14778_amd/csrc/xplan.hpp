@@ -24,6 +24,8 @@
 
 namespace cfr {
 
+constexpr int kChunk = 256;  // members per bottom-up workgroup (= threads per workgroup)
+
 struct ExecPlan {
     int64_t N = 0, Hp = 0, Qp = 0, Q0 = 0, M = 0, L = 0, C = 0;
     int32_t D = 0;
@@ -52,6 +54,11 @@ struct ExecPlan {
     std::vector<int32_t> chance_base;    // per chance node: index into [sigma | sigma_0] of action 0
     std::vector<int32_t> chance_k;       // per chance node: number of actions
     std::vector<float> chance_prob;      // sigma_0, Q0 entries (the tail of the probability array)
+    // bottom-up work chunks: runs of whole infosets of one level with at most kChunk members
+    // (an infoset with more members is a chunk of its own); chunk c covers infosets
+    // chunk_first[c] .. chunk_first[c + 1] - 1; chunks of level l are k_level_offset[l] ..
+    std::vector<int32_t> chunk_first;    // n_chunks + 1 (last entry = Hp)
+    std::vector<int32_t> k_level_offset; // D + 2
     // pair maps
     std::vector<int32_t> q_input;        // exec pair -> input pair
     int64_t n_blocks = 0;
@@ -66,5 +73,12 @@ int build_exec_plan(const Layout& L, ExecPlan& P, std::string& err);
 // numbered per level across games; q_input maps a forest pair to its position in the
 // concatenation of the games' input pair orders (game 0's pairs first).
 int build_forest_plan(const std::vector<ExecPlan>& games, ExecPlan& F, std::string& err);
+
+// Fills chunk_first / k_level_offset from h_level_offset and member_offset; level l packs at
+// most members_per_chunk[l] members per chunk (default kChunk for every level).
+void build_chunks(ExecPlan& P, const int32_t* members_per_chunk = nullptr);
+void build_chunks(const std::vector<int32_t>& h_level_offset,
+                  const std::vector<int32_t>& member_offset, const int32_t* members_per_chunk,
+                  std::vector<int32_t>& chunk_first, std::vector<int32_t>& k_level_offset);
 
 }  // namespace cfr

@@ -30,6 +30,15 @@ def test_every_declared_symbol_is_exported():
         assert n in _native.SIGNATURES, f"{n} has no binding"
 
 
+def test_warmstart_symbols_are_exported():
+    header = open(os.path.join(ROOT, "include", "cfr_warmstart.h")).read()
+    names = set(re.findall(r"^\s*(?:int|int64_t)\s+(cfr_\w+)\s*\(", header, re.M))
+    assert len(names) >= 11
+    lib = _lib()
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
 def test_plan_sizes():
     from paper_2408_14778_amd import plan
     p = plan(games.kuhn_like(3, "joint"))
