@@ -53,7 +53,7 @@ def level_counts(lay: dict) -> list:
         pl = player[a:b]
         dec = pl >= 0
         out.append({
-            "nodes": b - a, "decision": int(dec.sum()), "player": int((pl >= 1).sum()),
+            "nodes": int(b - a), "decision": int(dec.sum()), "player": int((pl >= 1).sum()),
             "chance": int((pl == 0).sum()),
             "player_children": int(nch[a:b][pl >= 1].sum()),
             "chance_children": int(nch[a:b][pl == 0].sum()),
@@ -63,40 +63,40 @@ def level_counts(lay: dict) -> list:
     return out
 
 
-def algorithmic_bytes(lay: dict, kernel: str, counts: list) -> float:
-    """Bytes one average launch of `kernel` must move (each distinct datum once).
-
-    block_reach (level l, one thread per node): node kind 1 B per node; per decision node
-    the parent index 4, edge index 4, edge probability 4 and its reach write 12; the
-    parents' reach 12 per distinct parent.
-    block_up (level l, one thread per infoset or chance node): per infoset its pair offset
-    4, player 1 and member offset 4; per pair sigma 4, R read+write 8, S read+write 8 and
-    the next sigma 4; per member its index 4, child begin 4, child stride 4, reach 12, value
-    write 4 and one value 4 per child; per chance node its index, base and count 12, value
-    write 4 and per child a listed index 4, probability 4 and value 4.
-    value_level / reach_level / infoset_update: the breadth-first node engine's kernels,
-    counted the same way (its regret and player-reach accumulation add 8 B per player child
-    and 8 B per player node).
+def algorithmic_bytes(kernel: str, counts: list) -> float:
+    """Bytes `kernel` must move per iteration under the two-sweep streaming model (fp32 values,
+    int32 indices; N_int = internal nodes, chance included; only internal nodes need reach):
+    top-down, per internal non-root node, parent index and edge label 8, parent reach 8 and
+    its own reach 8 (24 B); bottom-up, per node read as a child its value 12 with its
+    structure, per internal node its value write and the acting player's reach 8, per pair
+    36 (R and S read and written, the instantaneous regret, sigma read and written, sigma
+    gathers) and per infoset 8. A kernel's launches over one iteration move the sum of the
+    levels they process; the per-launch figure is that sum divided by the launches.
+    block_reach / reach_level: top-down; block_up: bottom-up (values, regrets and the
+    infoset update fused); value_level and infoset_update: the node engine's split of the
+    bottom-up terms.
     """
     D = len(counts) - 1
-    if kernel in ("block_reach", "reach_level"):
-        tot = sum(c["nodes"] + c["decision"] * 24 + c["parents"] * 12 for c in counts[1:D])
-        return tot / max(D - 1, 1)
-    if kernel == "block_up":
-        levels = [c for c in counts if c["infosets"] + c["chance"] > 0]
-        tot = sum(c["infosets"] * 9 + c["q"] * 24 + c["player"] * 28 + c["player_children"] * 4
-                  + c["chance"] * 16 + c["chance_children"] * 12 for c in levels)
-        return tot / max(len(levels), 1)
-    if kernel == "value_level":
-        tot = sum(c["nodes"] + c["decision"] * 8 + c["player"] * (12 + 4 + 8)
-                  + (c["player_children"] + c["chance_children"]) * 12
-                  + c["player_children"] * 8 for c in counts[:D])
-        return tot / max(D, 1)
-    if kernel == "infoset_update":
-        Qp = sum(c["q"] for c in counts)
-        Hp = sum(c["infosets"] for c in counts)
-        return Qp * 32 + Hp * 12
-    return 0.0
+    reach = sum(24 * c["decision"] for c in counts[1:D])
+    values = sum(12 * counts[l + 1]["nodes"] + 8 * counts[l]["decision"] for l in range(D))
+    infoset = sum(36 * c["q"] + 8 * c["infosets"] for c in counts)
+    return float({"block_reach": reach, "reach_level": reach, "block_up": values + infoset,
+                  "value_level": values, "infoset_update": infoset}.get(kernel, 0.0))
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None
+    when the kernels have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_large_game.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, rec["kernel_source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["kernel_source_sha256"]:
+            return None
+    return rec.get(kernel, {}).get("bytes_per_launch")
 
 
 def cpu_baseline(seconds_cap: float = 30.0) -> dict:
@@ -132,8 +132,8 @@ def main() -> int:
     ap.add_argument("--no-exploitability", action="store_true")
     ap.add_argument("--engine", choices=["auto", "node"], default="auto")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first copy 1 GiB device-to-device 3 times (a known-size kernel for "
-                         "scaling hardware byte counters)")
+                    help="first run a plain elementwise copy of 1 GiB (dst = src * 1) 3 times: a "
+                         "kernel of known size for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -151,10 +151,10 @@ def main() -> int:
         src = torch.ones(2**28, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)   # 1 GiB read + 1 GiB written per launch
         torch.cuda.synchronize()
         del src, dst
-        log("copy calibration: 3 x 1 GiB device-to-device copies done")
+        log("copy calibration: 3 x (1 GiB read + 1 GiB written) elementwise copies done")
     t0 = time.perf_counter()
     g = games.large_game()
     log(f"game built: {g.n_nodes} nodes in {time.perf_counter() - t0:.1f}s")
@@ -184,8 +184,9 @@ def main() -> int:
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
     avg_s = total_ms / launches * 1e-3
-    bytes_per_launch = algorithmic_bytes(lay, dom, counts)
+    bytes_per_launch = algorithmic_bytes(dom, counts) * args.timed_kernel_steps / launches
     achieved = bytes_per_launch / avg_s / 1e9
+    iter_bytes = float(sum(algorithmic_bytes(k, counts) for k in ("block_reach", "block_up")))
     kernels = {k: {"launches": n, "avg_us": ms / n * 1e3,
                    "share": ms / sum(v[1] for v in kt.values())} for k, (n, ms) in kt.items()}
     log(f"kernels: {json.dumps(kernels)}")
@@ -209,8 +210,10 @@ def main() -> int:
                    "depth": s.info["depth"],
                    "engine": ["node", "public-block"][s.info["engine"]]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
+                     "iteration_bytes": iter_bytes,
+                     "iteration_gbs": iter_bytes / (ms_per_step * 1e-3) / 1e9},
         "kernels": kernels,
     }
     if not args.no_exploitability:

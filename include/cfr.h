@@ -130,15 +130,27 @@ int cfr_iterate_profile(cfr_solver* s, int32_t n, double* launch_ms, int32_t* la
                         int32_t* launch_level, int64_t* launch_units, int32_t max_launches,
                         int32_t* n_launches);
 
-/* Launch shapes of the public-block engine. A top-down launch of u nodes uses
- * reach_threads[b] threads per workgroup (multiples of 64 in [64, 1024]); the bottom-up launch
- * of a level with u infoset members packs whole infosets into chunks of at most up_threads[b]
- * members, one workgroup of that many threads per chunk (64, 128, 256 or 512); b = min(floor(
- * log2 u), n_buckets - 1). n_buckets = 0 restores the defaults (256). Re-captures the iteration
- * graph; the results do not depend on the shape. Used by the autotuner; CFR_EINVAL for the node
- * engine. */
-int cfr_set_launch_shape(cfr_solver* s, const int32_t* up_threads, const int32_t* reach_threads,
-                         int32_t n_buckets);
+/* Launch shapes of the public-block engine, per bucket b = min(floor(log2 u), 31) of a
+ * launch's work items u (top-down: the level's nodes; bottom-up: the level's infoset members).
+ * A top-down launch uses reach_threads[b] threads per workgroup (a multiple of 64 in
+ * [64, 1024]), each thread taking reach_nodes[b] nodes (1, 2 or 4). The bottom-up launch packs
+ * whole infosets into chunks of at most up_threads[b] * up_members[b] members, one workgroup of
+ * up_threads[b] threads (64, 128, 256 or 512) per chunk, each thread taking up_members[b]
+ * members (1 or 2). The results do not depend on the shape (each infoset sums its members'
+ * contributions in member order), except for an infoset larger than a chunk. */
+typedef struct cfr_launch_shape {
+    int32_t up_threads[32];
+    int32_t up_members[32];
+    int32_t reach_threads[32];
+    int32_t reach_nodes[32];
+} cfr_launch_shape;
+
+/* Fills `out` with the library's default shapes. */
+void cfr_default_launch_shape(cfr_launch_shape* out);
+
+/* Sets the launch shapes (NULL: the defaults) and re-captures the iteration graph.
+ * CFR_EINVAL for a value outside the ranges above, or for the node engine. */
+int cfr_set_launch_shape(cfr_solver* s, const cfr_launch_shape* shape);
 
 /* Average strategy sigma-bar = S / sum_a S per infoset, uniform where that sum is 0
  * (Eq. average_strategy_profile), written to out[q] for the n_q pairs in input order.

@@ -68,6 +68,12 @@ class CfrPlanInfo(ctypes.Structure):
     ]
 
 
+class CfrLaunchShape(ctypes.Structure):
+    """cfr_launch_shape: per log2 bucket of work items (32 buckets)."""
+    _fields_ = [("up_threads", ctypes.c_int32 * 32), ("up_members", ctypes.c_int32 * 32),
+                ("reach_threads", ctypes.c_int32 * 32), ("reach_nodes", ctypes.c_int32 * 32)]
+
+
 # name -> (restype, argtypes); exactly the entry points declared in include/cfr.h
 SIGNATURES = {
     "cfr_plan": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.POINTER(CfrConfig),
@@ -81,7 +87,8 @@ SIGNATURES = {
     "cfr_kernel_name": (ctypes.c_char_p, [ctypes.c_int32]),
     "cfr_iterate_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, _i32p, _i32p,
                                            _i64p, ctypes.c_int32, _i32p]),
-    "cfr_set_launch_shape": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, ctypes.c_int32]),
+    "cfr_default_launch_shape": (None, [ctypes.POINTER(CfrLaunchShape)]),
+    "cfr_set_launch_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CfrLaunchShape)]),
     "cfr_average_strategy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_int]),
     "cfr_current_strategy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,

@@ -26,9 +26,11 @@ struct cfr_solver {
     int32_t n_games = 1;       // > 1: a batch (forest); canonical exports are unavailable
     bool canonical = true;     // the canonical layout arrays are on the device
     std::vector<int32_t> x_level_offset, x_h_level_offset, x_c_level_offset;
-    std::vector<int32_t> up_block, reach_block;  // launch shapes (empty: defaults)
+    cfr_launch_shape shape{};                    // launch shapes per bucket
+    std::vector<int32_t> reach_threads, reach_npt;  // views of `shape` for the kernels
     std::vector<int32_t> x_member_offset;        // host copy (chunk tables)
-    std::vector<int32_t> x_k_level_offset, chunk_cap, x_m_level_offset;
+    std::vector<int32_t> x_k_level_offset, x_m_level_offset;
+    std::vector<int32_t> up_threads, chunk_cap, chance_glog;  // per level
     int variant = CFR_VANILLA;
     int linear = 0;
     bool use_graph = true;
@@ -131,9 +133,11 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
     d.reach = c.take<float>(3 * N);
     d.T = c.take<int64_t>(1);
     d.avgprob = c.take<float>(Qp + Q0);
-    d.br_reach = c.take<float>(N);
-    d.br_value = c.take<float>(N);
-    d.best = c.take<int32_t>(Hp);
+    if (z.engine == ENGINE_NODE) {
+        d.br_reach = c.take<float>(N);
+        d.br_value = c.take<float>(N);
+        d.best = c.take<int32_t>(Hp);
+    }
     d.stage = c.take<float>(2 * Qp);
     d.out2 = c.take<double>(2 * static_cast<int64_t>(z.n_games));
     d.sq_offset = d.q_offset;
@@ -159,7 +163,12 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
         x.chance_nodes = c.take<int32_t>(z.C);
         x.chance_base = c.take<int32_t>(z.C);
         x.chance_k = c.take<int32_t>(z.C);
+        x.mem_q = c.take<int32_t>(M);
+        x.mem_kp = c.take<int8_t>(M);
+        x.mem_cb = c.take<int32_t>(M);
+        x.mem_st = c.take<int32_t>(M);
         x.chunk_first = c.take<int32_t>(Hp + D + 2);
+        x.chunk_m = c.take<int32_t>(Hp + D + 2);
         x.q_input = c.take<int32_t>(Qp);
         x.payoff = c.take<float>(N);
         x.prob = d.prob;
@@ -168,8 +177,8 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
         x.value = d.value;
         x.reach = d.reach;
         x.T = d.T;
-        x.br_reach = d.br_reach;
-        x.br_value = d.br_value;
+        x.br_reach = c.take<float>(2 * N);
+        x.br_value = c.take<float>(2 * N);
         x.out2 = d.out2;
         d.sq_offset = x.q_offset;
         d.sq_input = x.q_input;
@@ -251,35 +260,99 @@ int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out)
 
 namespace {
 
+// Per-level bottom-up shapes from the bucket tables (the fused first levels take one chunk of
+// up to kFuseThreads members), then the chunk tables, uploaded.
+int apply_shapes(cfr_solver* s, hipStream_t st) {
+    cfr::XDev& x = s->xdev;
+    const int32_t D = x.D;
+    s->reach_threads.assign(s->shape.reach_threads, s->shape.reach_threads + cfr::kShapeBuckets);
+    s->reach_npt.assign(s->shape.reach_nodes, s->shape.reach_nodes + cfr::kShapeBuckets);
+    x.reach_block = s->reach_threads.data();
+    x.reach_npt = s->reach_npt.data();
+    s->up_threads.assign(D + 1, 256);
+    s->chunk_cap.assign(D + 1, 256);
+    for (int32_t l = 0; l <= D; ++l) {
+        if (l < x.fused_up) {
+            s->up_threads[l] = cfr::kFuseThreads;
+            s->chunk_cap[l] = cfr::kFuseThreads;
+            continue;
+        }
+        const int b = cfr::shape_bucket(s->x_m_level_offset[l + 1] - s->x_m_level_offset[l]);
+        s->up_threads[l] = s->shape.up_threads[b];
+        s->chunk_cap[l] = s->shape.up_threads[b] * s->shape.up_members[b];
+    }
+    x.up_threads_host = s->up_threads.data();
+    x.chunk_cap_host = s->chunk_cap.data();
+    std::vector<int32_t> chunk_first, chunk_m;
+    cfr::build_chunks(s->x_h_level_offset, s->x_member_offset, s->chunk_cap.data(), chunk_first,
+                      s->x_k_level_offset);
+    chunk_m.resize(chunk_first.size());
+    for (size_t c = 0; c < chunk_first.size(); ++c) chunk_m[c] = s->x_member_offset[chunk_first[c]];
+    x.k_level_offset_host = s->x_k_level_offset.data();
+    int rc;
+    if ((rc = upload(x.chunk_first, chunk_first, st)) || (rc = upload(x.chunk_m, chunk_m, st)))
+        return rc;
+    // the host vectors go out of scope
+    HIP_TRY(hipStreamSynchronize(st), "chunk table upload");
+    return CFR_OK;
+}
+
 // Copies the block plan to the device and fills the solver's exec view.
 int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     cfr::XDev& x = s->xdev;
     int rc;
+    // member-major operands of the bottom-up pass
+    std::vector<int32_t> mem_q(P.M), mem_cb(P.M), mem_st(P.M);
+    std::vector<int8_t> mem_kp(P.M);
+    for (int64_t h = 0; h < P.Hp; ++h) {
+        const int32_t k = P.q_offset[h + 1] - P.q_offset[h];
+        const int8_t kp = static_cast<int8_t>(k | (P.infoset_player[h] == 2 ? 64 : 0));
+        for (int32_t m = P.member_offset[h]; m < P.member_offset[h + 1]; ++m) {
+            mem_q[m] = P.q_offset[h];
+            mem_kp[m] = kp;
+            mem_cb[m] = P.child_begin[P.members[m]];
+            mem_st[m] = P.child_stride[P.members[m]];
+        }
+    }
     if ((rc = upload(x.parent, P.parent, st)) || (rc = upload(x.edge, P.edge, st)) ||
         (rc = upload(x.meta, P.meta, st)) || (rc = upload(x.child_begin, P.child_begin, st)) ||
         (rc = upload(x.child_stride, P.child_stride, st)) ||
         (rc = upload(x.child_list, P.child_list, st)) || (rc = upload(x.canon_of, P.canon_of, st)) ||
         (rc = upload(x.q_offset, P.q_offset, st)) || (rc = upload(x.iplayer, P.infoset_player, st)) ||
         (rc = upload(x.member_offset, P.member_offset, st)) ||
-        (rc = upload(x.members, P.members, st)) || (rc = upload(x.chance_nodes, P.chance_nodes, st)) ||
+        (rc = upload(x.members, P.members, st)) || (rc = upload(x.mem_q, mem_q, st)) ||
+        (rc = upload(x.mem_kp, mem_kp, st)) || (rc = upload(x.mem_cb, mem_cb, st)) ||
+        (rc = upload(x.mem_st, mem_st, st)) || (rc = upload(x.chance_nodes, P.chance_nodes, st)) ||
+        (rc = upload(x.chance_base, P.chance_base, st)) || (rc = upload(x.chance_k, P.chance_k, st)) ||
         (rc = upload(x.q_input, P.q_input, st)) || (rc = upload(x.payoff, P.payoff, st)))
         return rc;
+    HIP_TRY(hipStreamSynchronize(st), "plan upload");
     s->x_level_offset = P.level_offset;
     s->x_h_level_offset = P.h_level_offset;
     s->x_c_level_offset = P.c_level_offset;
     s->x_member_offset = P.member_offset;
-    s->x_k_level_offset = P.k_level_offset;
-    s->chunk_cap.assign(P.D + 1, cfr::kChunk);
     s->x_m_level_offset.resize(P.D + 2);
     for (int32_t l = 0; l <= P.D + 1; ++l) s->x_m_level_offset[l] = P.member_offset[P.h_level_offset[l]];
+    // lanes per chance node: the level's largest fan-out rounded up to a power of two, <= 64
+    s->chance_glog.assign(P.D + 1, 0);
+    for (int32_t l = 0; l <= P.D; ++l) {
+        int32_t kmax = 1;
+        for (int32_t c = P.c_level_offset[l]; c < P.c_level_offset[l + 1]; ++c)
+            kmax = std::max(kmax, P.chance_k[c]);
+        int g = 0;
+        while (g < 6 && (1 << g) < kmax) ++g;
+        s->chance_glog[l] = g;
+    }
     x.m_level_offset_host = s->x_m_level_offset.data();
     x.level_offset_host = s->x_level_offset.data();
     x.h_level_offset_host = s->x_h_level_offset.data();
     x.c_level_offset_host = s->x_c_level_offset.data();
-    x.k_level_offset_host = s->x_k_level_offset.data();
-    x.chunk_cap_host = s->chunk_cap.data();
-    if ((rc = upload(x.chunk_first, P.chunk_first, st))) return rc;
-    return CFR_OK;
+    x.chance_glog_host = s->chance_glog.data();
+    x.fused_reach = cfr::fusable_reach_levels(x.level_offset_host, P.D);
+    x.fused_up = cfr::fusable_up_levels(x.m_level_offset_host, x.h_level_offset_host,
+                                        x.c_level_offset_host, x.chance_glog_host, P.D,
+                                        x.max_actions);
+    return apply_shapes(s, st);
 }
 
 }  // namespace
@@ -357,8 +430,8 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         return rc;
     }
     if (s->engine == ENGINE_BLOCK) {
-        if ((rc = upload_plan(s, P, st)) || (rc = upload(s->xdev.chance_base, P.chance_base, st)) ||
-            (rc = upload(s->xdev.chance_k, P.chance_k, st))) {
+        cfr_default_launch_shape(&s->shape);
+        if ((rc = upload_plan(s, P, st))) {
             delete s;
             return rc;
         }
@@ -506,46 +579,37 @@ int cfr_iterate_profile(cfr_solver* s, int32_t n, double* launch_ms, int32_t* la
     return CFR_OK;
 }
 
-int cfr_set_launch_shape(cfr_solver* s, const int32_t* up_threads, const int32_t* reach_threads,
-                         int32_t n_buckets) {
-    if (s == nullptr || n_buckets < 0 || n_buckets > cfr::kShapeBuckets)
-        return set_err(CFR_EINVAL, "bad argument");
-    if (s->engine != ENGINE_BLOCK) return set_err(CFR_EINVAL, "launch shapes apply to the block engine");
-    auto fill = [&](const int32_t* src, std::vector<int32_t>& dst, bool chunk) -> bool {
-        dst.assign(cfr::kShapeBuckets, 256);
-        if (src == nullptr) return true;
-        for (int32_t b = 0; b < cfr::kShapeBuckets; ++b) {
-            const int32_t t = src[std::min(b, n_buckets - 1)];
-            const bool ok = chunk ? (t == 64 || t == 128 || t == 256 || t == 512)
-                                  : (t >= 64 && t <= 1024 && (t % 64) == 0);
-            if (!ok) return false;
-            dst[b] = t;
-        }
-        return true;
-    };
-    std::vector<int32_t> up, reach;
-    if (n_buckets > 0 && (!fill(up_threads, up, true) || !fill(reach_threads, reach, false)))
-        return set_err(CFR_EINVAL,
-                       "bottom-up sizes must be 64, 128, 256 or 512; top-down sizes multiples of 64 "
-                       "in [64, 1024]");
-    s->up_block = up;
-    s->reach_block = reach;
-    s->xdev.up_block = s->up_block.empty() ? nullptr : s->up_block.data();
-    s->xdev.reach_block = s->reach_block.empty() ? nullptr : s->reach_block.data();
-    // members per bottom-up workgroup, per level, from the level's member count
-    const int32_t D = s->xdev.D;
-    for (int32_t l = 0; l <= D; ++l) {
-        const int64_t members = s->x_m_level_offset[l + 1] - s->x_m_level_offset[l];
-        s->chunk_cap[l] = up.empty() ? cfr::kChunk : up[cfr::shape_bucket(members)];
+void cfr_default_launch_shape(cfr_launch_shape* out) {
+    if (out == nullptr) return;
+    for (int b = 0; b < cfr::kShapeBuckets; ++b) {
+        out->up_threads[b] = 256;
+        out->up_members[b] = b >= 14 ? 2 : 1;
+        out->reach_threads[b] = 256;
+        out->reach_nodes[b] = b >= 16 ? 2 : 1;
     }
-    std::vector<int32_t> chunk_first;
-    cfr::build_chunks(s->x_h_level_offset, s->x_member_offset, s->chunk_cap.data(), chunk_first,
-                      s->x_k_level_offset);
-    s->xdev.k_level_offset_host = s->x_k_level_offset.data();
+}
+
+int cfr_set_launch_shape(cfr_solver* s, const cfr_launch_shape* shape) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (s->engine != ENGINE_BLOCK) return set_err(CFR_EINVAL, "launch shapes apply to the block engine");
+    cfr_launch_shape sh;
+    if (shape != nullptr) sh = *shape;
+    else cfr_default_launch_shape(&sh);
+    for (int b = 0; b < cfr::kShapeBuckets; ++b) {
+        const int32_t ut = sh.up_threads[b], um = sh.up_members[b];
+        const int32_t rt = sh.reach_threads[b], rn = sh.reach_nodes[b];
+        if (!(ut == 64 || ut == 128 || ut == 256 || ut == 512) || !(um == 1 || um == 2) ||
+            !(rt >= 64 && rt <= 1024 && rt % 64 == 0) || !(rn == 1 || rn == 2 || rn == 4))
+            return set_err(CFR_EINVAL,
+                           "bucket " + std::to_string(b) +
+                               ": bottom-up threads must be 64, 128, 256 or 512 with 1 or 2 "
+                               "members each; top-down threads a multiple of 64 in [64, 1024] "
+                               "with 1, 2 or 4 nodes each");
+    }
     HIP_TRY(hipStreamSynchronize(s->stream), "launch shape synchronise");
-    int rc = upload(s->xdev.chunk_first, chunk_first, s->stream);
+    s->shape = sh;
+    const int rc = apply_shapes(s, s->stream);
     if (rc != CFR_OK) return rc;
-    HIP_TRY(hipStreamSynchronize(s->stream), "launch shape synchronise");
     if (s->exec != nullptr) (void)hipGraphExecDestroy(s->exec);
     if (s->graph != nullptr) (void)hipGraphDestroy(s->graph);
     s->exec = nullptr;
@@ -588,10 +652,10 @@ int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]) {
     if (s->n_games != 1) return set_err(CFR_EINVAL, "a batch reports cfr_exploitability_batch");
     if (!s->level_pure) return set_err(CFR_ELEVEL, "an infoset spans several levels");
     cfr::launch_average(s->dev, s->stream);
-    for (int player = 1; player <= 2; ++player) {
-        if (s->engine == ENGINE_BLOCK)
-            cfr::launch_x_best_response(s->xdev, s->dev.avgprob, player, s->stream);
-        else
+    if (s->engine == ENGINE_BLOCK) {
+        cfr::launch_x_best_response(s->xdev, s->dev.avgprob, s->stream);
+    } else {
+        for (int player = 1; player <= 2; ++player)
             cfr::launch_best_response(s->dev, s->level_offset.data(), s->infoset_level_offset.data(),
                                       player, s->stream);
     }
@@ -868,8 +932,8 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     hipStream_t st = s->stream;
     std::vector<float> prob_tail(F.Qp + F.Q0, 0.0f);
     std::copy(F.chance_prob.begin(), F.chance_prob.end(), prob_tail.begin() + F.Qp);
-    if ((rc = upload_plan(s, F, st)) || (rc = upload(s->xdev.chance_base, F.chance_base, st)) ||
-        (rc = upload(s->xdev.chance_k, F.chance_k, st)) || (rc = upload(d.prob, prob_tail, st))) {
+    cfr_default_launch_shape(&s->shape);
+    if ((rc = upload_plan(s, F, st)) || (rc = upload(d.prob, prob_tail, st))) {
         delete s;
         return rc;
     }
@@ -897,8 +961,7 @@ int cfr_exploitability_batch(cfr_solver* s, double* expl, double* br_values, int
     if (n_games != s->n_games) return set_err(CFR_EINVAL, "n_games does not match the batch");
     if (s->engine != ENGINE_BLOCK) return set_err(CFR_EINVAL, "not a batch solver");
     cfr::launch_average(s->dev, s->stream);
-    for (int player = 1; player <= 2; ++player)
-        cfr::launch_x_best_response(s->xdev, s->dev.avgprob, player, s->stream);
+    cfr::launch_x_best_response(s->xdev, s->dev.avgprob, s->stream);
     int rc = check_hip("best response launch");
     if (rc != CFR_OK) return rc;
     std::vector<double> br(2 * static_cast<size_t>(n_games));

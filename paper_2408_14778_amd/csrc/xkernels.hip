@@ -2,15 +2,21 @@
 //
 // An iteration (Section 3.2) is one top-down launch per level for the reach
 // probabilities (Eq. excepted_reach_probabilities_matrix_recurrence and its own-reach
-// twin) and one bottom-up launch per level that, per unit of work, finishes a whole
-// infoset: its members' expected payoffs (Eq. expected_payoffs_matrix_recurrence), the
+// twin) and one bottom-up launch per level that, per chunk of whole infosets, finishes
+// each infoset: its members' expected payoffs (Eq. expected_payoffs_matrix_recurrence), the
 // instantaneous counterfactual regrets in their multiplied-out form (Eq.
 // instantaneous_counterfactual_regret), the player reach of Eq. (player_reach_probability),
 // and the cumulative regret / average / regret-matching update (Eqs.
 // average_counterfactual_regrets_vector, average_strategy_profile_vector,
-// next_strategy_profile). All members of an infoset sit in one public block, so the unit
-// reads a compact, coalesced slice; nothing is accumulated with atomics and the result
-// does not depend on scheduling. Chance nodes are units of their own.
+// next_strategy_profile). All members of an infoset sit in one public block, so a chunk
+// reads a compact slice; nothing is accumulated with atomics and the result does not depend
+// on scheduling or on the launch shape. Chance nodes are reduced by lane groups. The first,
+// tiny levels of each direction run in one workgroup with barriers between levels.
+//
+// The passes are bound by HBM traffic and by the latency of dependent loads (the level
+// structure forces node -> child -> value chains), so the kernels keep those chains short
+// (member-major copies of the per-member operands, pair operands loaded before they are
+// needed) and give each thread several independent nodes or members.
 #include <hip/hip_runtime.h>
 
 #include "xkernels.hpp"
@@ -23,16 +29,23 @@ constexpr int kBlock = 256;
 
 inline unsigned blocks_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
-inline int pick(const int32_t* table, int64_t units) {
-    return table != nullptr ? table[shape_bucket(units)] : kBlock;
-}
-
 inline unsigned blocks_of(int64_t n, int threads) {
     return static_cast<unsigned>((n + threads - 1) / threads);
 }
 
 __device__ __forceinline__ int64_t gid() {
     return static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+}
+
+// The hardware hands workgroup b to XCD b % 8 (each XCD has its own L2). Renumber so that each
+// XCD takes one contiguous run of tiles: neighbouring tiles share cache lines (a parent block,
+// the edges of a child range), and that sharing then stays inside one L2.
+__device__ __forceinline__ uint32_t xcd_tile() {
+    constexpr uint32_t kXcds = 8;
+    const uint32_t g = gridDim.x, b = blockIdx.x;
+    const uint32_t q = g / kXcds, r = g % kXcds;
+    const uint32_t xcd = b % kXcds, j = b / kXcds;
+    return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + j;
 }
 
 __device__ __forceinline__ int32_t child_of(const int32_t* __restrict__ child_begin,
@@ -44,157 +57,368 @@ __device__ __forceinline__ int32_t child_of(const int32_t* __restrict__ child_be
     return st != 0 ? cb + a * st : child_list[cb + a];
 }
 
-// Reach of one level: the factor of whoever acted into the node (meta bits 2-3) is
-// multiplied by the edge probability (sigma or sigma_0).
-__global__ void k_x_reach(int32_t lo, int32_t hi, int64_t N, const int32_t* __restrict__ parent,
-                          const int32_t* __restrict__ edge, const int8_t* __restrict__ meta,
-                          const float* __restrict__ prob, float* __restrict__ reach) {
-    const int64_t x = lo + gid();
-    if (x >= hi) return;
-    const int m = meta[x];
-    if ((m & 3) == 0) return;  // terminal: no reach needed
-    const int actor = m >> 2;  // 1 chance, 2 player 1, 3 player 2
-    const int32_t p = parent[x];
-    const float s = prob[edge[x]];
-    float r1 = reach[p], r2 = reach[N + p], rc = reach[2 * N + p];
-    if (actor == 2) r1 *= s;
-    else if (actor == 3) r2 *= s;
-    else rc *= s;
-    reach[x] = r1;
-    reach[N + x] = r2;
-    reach[2 * N + x] = rc;
+// ---- top-down (reach)
+
+// Reach of NPT nodes x = first + u * stride: the factor of whoever acted into the node (meta
+// bits 2-3) is multiplied by the edge probability (sigma or sigma_0). Terminal nodes need no
+// reach. All loads of the NPT nodes are issued before any of them is used.
+template <int NPT>
+__device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64_t hi, int64_t N,
+                                            const int32_t* __restrict__ parent,
+                                            const int32_t* __restrict__ edge,
+                                            const int8_t* __restrict__ meta,
+                                            const float* __restrict__ prob,
+                                            float* __restrict__ reach) {
+    int64_t xs[NPT];
+    int kind[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        xs[u] = first + u * stride;
+        kind[u] = xs[u] < hi ? meta[xs[u]] : 0;
+    }
+    int32_t p[NPT], e[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        p[u] = 0;
+        e[u] = 0;
+        if (kind[u] & 3) {
+            p[u] = parent[xs[u]];
+            e[u] = edge[xs[u]];
+        }
+    }
+    float r1[NPT], r2[NPT], rc[NPT], s[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        r1[u] = r2[u] = rc[u] = s[u] = 0.0f;
+        if (kind[u] & 3) {
+            r1[u] = reach[p[u]];
+            r2[u] = reach[N + p[u]];
+            rc[u] = reach[2 * N + p[u]];
+            s[u] = prob[e[u]];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        if ((kind[u] & 3) == 0) continue;
+        const int actor = kind[u] >> 2;  // 1 chance, 2 player 1, 3 player 2
+        if (actor == 2) r1[u] *= s[u];
+        else if (actor == 3) r2[u] *= s[u];
+        else rc[u] *= s[u];
+        reach[xs[u]] = r1[u];
+        reach[N + xs[u]] = r2[u];
+        reach[2 * N + xs[u]] = rc[u];
+    }
 }
 
-// Bottom-up of one level, member-parallel. Workgroup b < n_chunks takes chunk b: whole
-// infosets with at most CH members in total, one thread per member (or one infoset with more
-// members, each thread striding over them). Phase 1: each member's child values (gather by
-// stride), its value, its regret contributions cf * (w_a - v) and own reach, into LDS.
-// Phase 2: one thread per infoset sums its members' slots in member order (deterministic)
-// and applies the regret update, the average-strategy update and regret matching.
-// Workgroups past the chunks take the level's chance nodes, one thread each.
-template <int KMAX, int CH>
-__global__ void __launch_bounds__(CH) k_x_up_chunk(
-    int32_t chunk_lo, int32_t n_chunks, int32_t clo, int32_t nc, int64_t N,
-    const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ child_begin,
-    const int32_t* __restrict__ child_stride, const int32_t* __restrict__ child_list,
-    const int32_t* __restrict__ q_offset, const int8_t* __restrict__ iplayer,
-    const int32_t* __restrict__ member_offset, const int32_t* __restrict__ members,
-    const int32_t* __restrict__ chance_nodes, const int32_t* __restrict__ chance_base,
-    const int32_t* __restrict__ chance_k, float* __restrict__ prob, float* __restrict__ value,
-    const float* __restrict__ reach, float* __restrict__ R, float* __restrict__ S,
-    const int64_t* __restrict__ T, int variant, int linear) {
-    __shared__ float s_con[CH][KMAX];
-    __shared__ float s_own[CH];
-    __shared__ int32_t s_owner[CH];
-    const int tid = threadIdx.x;
-    const int32_t b = blockIdx.x;
-    if (b >= n_chunks) {
-        const int64_t i = static_cast<int64_t>(b - n_chunks) * CH + tid;
-        if (i >= nc) return;
-        const int32_t ci = clo + static_cast<int32_t>(i);
-        const int32_t x = chance_nodes[ci];
-        const int32_t base = chance_base[ci], k = chance_k[ci];
-        float v = 0.0f;
-        for (int32_t a = 0; a < k; ++a)
-            v = fmaf(prob[base + a], value[child_of(child_begin, child_stride, child_list, x, a)], v);
-        value[x] = v;
-        return;
-    }
-    const int32_t c = chunk_lo + b;
-    const int32_t h0 = chunk_first[c], h1 = chunk_first[c + 1];
-    const int32_t m0 = member_offset[h0], m1 = member_offset[h1];
-    const int32_t nm = m1 - m0;
-    const bool big = nm > CH;
-    if (!big) {
-        for (int32_t i = tid; i < h1 - h0; i += CH)
-            for (int32_t m = member_offset[h0 + i]; m < member_offset[h0 + i + 1]; ++m)
-                s_owner[m - m0] = i;
+// One level: workgroup b takes nodes lo + b * blockDim * NPT + [0, blockDim * NPT), each
+// thread NPT of them blockDim apart (every load coalesced across the wavefront).
+template <int NPT>
+__global__ void __launch_bounds__(1024) k_x_reach(int32_t lo, int32_t hi, int64_t N,
+                                                  const int32_t* __restrict__ parent,
+                                                  const int32_t* __restrict__ edge,
+                                                  const int8_t* __restrict__ meta,
+                                                  const float* __restrict__ prob,
+                                                  float* __restrict__ reach) {
+    const int64_t first = lo + static_cast<int64_t>(xcd_tile()) * blockDim.x * NPT + threadIdx.x;
+    reach_nodes<NPT>(first, blockDim.x, hi, N, parent, edge, meta, prob, reach);
+}
+
+// The levels one single-workgroup kernel takes, in the order it takes them; entry i covers
+// nodes (top-down) or chunks (bottom-up) lo[i] .. hi[i] - 1 and chance nodes clo[i] .. chi[i] - 1.
+struct LevelTable {
+    int32_t n;
+    int32_t lo[kFuseMax], hi[kFuseMax];
+    int32_t clo[kFuseMax], chi[kFuseMax];
+    int32_t glog[kFuseMax];  // log2 lanes per chance node (bottom-up)
+};
+
+// The first top-down levels in one workgroup: a barrier between levels instead of a launch.
+__global__ void __launch_bounds__(kFuseThreads) k_x_reach_top(LevelTable t, int64_t N,
+                                                              const int32_t* __restrict__ parent,
+                                                              const int32_t* __restrict__ edge,
+                                                              const int8_t* __restrict__ meta,
+                                                              const float* __restrict__ prob,
+                                                              float* __restrict__ reach) {
+    for (int32_t i = 0; i < t.n; ++i) {
+        reach_nodes<2>(t.lo[i] + threadIdx.x, kFuseThreads, t.hi[i], N, parent, edge, meta, prob,
+                       reach);
         __syncthreads();
     }
-    // phase 1
-    {
-        float con[KMAX];
-        float own = 0.0f;
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a) con[a] = 0.0f;
-        for (int32_t mi = tid; mi < nm; mi += CH) {
-            const int32_t h = big ? h0 : h0 + s_owner[mi];
-            const int player = iplayer[h];
-            const int32_t o = q_offset[h];
-            const int32_t k = q_offset[h + 1] - o;
-            const int32_t x = members[m0 + mi];
-            const int32_t st = child_stride[x];
-            const int32_t cb = child_begin[x];
-            float w[KMAX], sg[KMAX];
-            float v = 0.0f;
-#pragma unroll
-            for (int a = 0; a < KMAX; ++a) {
-                if (a < k) {
-                    const int32_t ch = st != 0 ? cb + a * st : child_list[cb + a];
-                    w[a] = value[ch];
-                    sg[a] = prob[o + a];
-                    v = fmaf(sg[a], w[a], v);
-                } else {
-                    w[a] = 0.0f;
-                    sg[a] = 0.0f;
-                }
-            }
-            value[x] = v;
-            const float r1 = reach[x], r2 = reach[N + x], rc = reach[2 * N + x];
-            const float cf = (player == 1 ? r2 : r1) * rc;
-            own += player == 1 ? r1 : r2;
-#pragma unroll
-            for (int a = 0; a < KMAX; ++a)
-                if (a < k) con[a] = fmaf(cf, w[a] - v, con[a]);
-        }
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a) s_con[tid][a] = con[a];
-        s_own[tid] = own;
+}
+
+// ---- bottom-up (values, regrets, average, regret matching)
+
+struct UpArgs {
+    int64_t N;
+    const int32_t* chunk_first;
+    const int32_t* chunk_m;
+    const int32_t* child_begin;
+    const int32_t* child_stride;
+    const int32_t* child_list;
+    const int32_t* q_offset;
+    const int8_t* iplayer;
+    const int32_t* member_offset;
+    const int32_t* members;
+    const int32_t* mem_q;
+    const int8_t* mem_kp;
+    const int32_t* mem_cb;
+    const int32_t* mem_st;
+    const int32_t* chance_nodes;
+    const int32_t* chance_base;
+    const int32_t* chance_k;
+    float* prob;
+    float* value;
+    const float* reach;
+    float* R;
+    float* S;
+    int64_t* T;
+    int variant;
+    int linear;
+};
+
+// Chance node ci (if ok) on a group of 2^glog lanes: lane l sums children l, l + 2^glog, ...,
+// then a butterfly over the group (a fixed order). Every lane of the wavefront must call it
+// with the same glog.
+__device__ __forceinline__ void chance_group(const UpArgs& a, int32_t ci, bool ok, int lane,
+                                             int glog) {
+    float v = 0.0f;
+    int32_t x = 0;
+    if (ok) {
+        x = a.chance_nodes[ci];
+        const int32_t base = a.chance_base[ci], k = a.chance_k[ci];
+        const int32_t cb = a.child_begin[x], st = a.child_stride[x];
+        for (int32_t c = lane; c < k; c += 1 << glog)
+            v = fmaf(a.prob[base + c], a.value[st != 0 ? cb + c * st : a.child_list[cb + c]], v);
     }
-    __syncthreads();
-    // phase 2
-    const int32_t nh = h1 - h0;
-    if (tid >= nh) return;
-    const int32_t h = h0 + tid;
-    const int32_t slo = big ? 0 : member_offset[h] - m0;
-    const int32_t shi = big ? (nm < CH ? nm : CH) : member_offset[h + 1] - m0;
-    const int player = iplayer[h];
-    const int32_t o = q_offset[h];
-    const int32_t k = q_offset[h + 1] - o;
+    for (int off = (1 << glog) >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (ok && lane == 0) a.value[x] = v;
+}
+
+// Phase 2 of a chunk for one infoset h (pair operands pr = R, ps = S, pp = sigma already
+// loaded): sums its members' LDS slots slo .. shi - 1 in member order, then the regret update
+// (vanilla, or CFR+ clipped), the average-strategy update S += w pi-bar sigma and regret
+// matching into sigma.
+template <int KMAX>
+__device__ __forceinline__ void update_infoset(const UpArgs& a, int32_t o, int32_t k, int player,
+                                               int32_t slo, int32_t shi, const float* pr,
+                                               const float* ps, const float* pp,
+                                               float (*s_con)[KMAX], const float* s_own) {
     float racc[KMAX];
 #pragma unroll
-    for (int a = 0; a < KMAX; ++a) racc[a] = 0.0f;
+    for (int j = 0; j < KMAX; ++j) racc[j] = 0.0f;
     float own = 0.0f;
+#pragma unroll 1
     for (int32_t sl = slo; sl < shi; ++sl) {
 #pragma unroll
-        for (int a = 0; a < KMAX; ++a) racc[a] += s_con[sl][a];
+        for (int j = 0; j < KMAX; ++j) racc[j] += s_con[sl][j];
         own += s_own[sl];
     }
     const float sgn = player == 1 ? 1.0f : -1.0f;
-    const float wt = linear ? static_cast<float>(*T + 1) : 1.0f;
+    const float wt = a.linear ? static_cast<float>(*a.T + 1) : 1.0f;
     float pos_sum = 0.0f;
 #pragma unroll
-    for (int a = 0; a < KMAX; ++a) {
-        if (a < k) {
-            const float sig = prob[o + a];
-            float r = fmaf(sgn, racc[a], R[o + a]);
-            if (variant == 1) r = fmaxf(r, 0.0f);
-            R[o + a] = r;
-            S[o + a] = fmaf(wt * own, sig, S[o + a]);
-            racc[a] = r;
+    for (int j = 0; j < KMAX; ++j) {
+        if (j < k) {
+            float r = fmaf(sgn, racc[j], pr[j]);
+            if (a.variant == 1) r = fmaxf(r, 0.0f);
+            a.R[o + j] = r;
+            a.S[o + j] = fmaf(wt * own, pp[j], ps[j]);
+            racc[j] = r;
             pos_sum += fmaxf(r, 0.0f);
         }
     }
     if (pos_sum > 0.0f) {
 #pragma unroll
-        for (int a = 0; a < KMAX; ++a)
-            if (a < k) prob[o + a] = fmaxf(racc[a], 0.0f) / pos_sum;
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) a.prob[o + j] = fmaxf(racc[j], 0.0f) / pos_sum;
     } else {
         const float unif = 1.0f / static_cast<float>(k);
 #pragma unroll
-        for (int a = 0; a < KMAX; ++a)
-            if (a < k) prob[o + a] = unif;
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) a.prob[o + j] = unif;
     }
+}
+
+template <int KMAX>
+__device__ __forceinline__ void load_pairs(const UpArgs& a, int32_t o, int32_t k, float* pr,
+                                           float* ps, float* pp) {
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        pr[j] = ps[j] = pp[j] = 0.0f;
+        if (j < k) {
+            pr[j] = a.R[o + j];
+            ps[j] = a.S[o + j];
+            pp[j] = a.prob[o + j];
+        }
+    }
+}
+
+// One chunk: whole infosets of one level with at most CH * MPT members in total (or one
+// larger infoset). Phase 1, MPT members per thread, all their loads issued first: child
+// values (gather by stride), the member's value, its regret contributions cf * (w_a - v) and
+// its own reach, into the member's LDS slot. Phase 2, one thread per infoset (a chunk of
+// single-member infosets has up to CH * MPT of them: threads stride): sums its members'
+// slots in member order (deterministic, independent of the shape), then update_infoset. The
+// pair operands of each thread's first infoset are loaded before phase 1. An infoset with
+// more members than the chunk holds is accumulated per thread (CH slots). Every thread of the
+// workgroup must call it; it holds one barrier.
+template <int KMAX, int CH, int MPT>
+__device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_con)[KMAX],
+                                         float* s_own, int tid) {
+    constexpr int CAP = CH * MPT;
+    constexpr bool kPrefetch = KMAX <= 4;
+    const int32_t h0 = a.chunk_first[c], h1 = a.chunk_first[c + 1];
+    const int32_t m0 = a.chunk_m[c], m1 = a.chunk_m[c + 1];
+    const int32_t nm = m1 - m0, nh = h1 - h0;
+    const bool big = nm > CAP;
+    int32_t o = 0, k = 0;
+    float pr[KMAX], ps[KMAX], pp[KMAX];
+    if (tid < nh) {
+        o = a.q_offset[h0 + tid];
+        k = a.q_offset[h0 + tid + 1] - o;
+        if (kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
+    }
+    if (!big) {
+        int32_t x[MPT], q[MPT], cb[MPT], st[MPT], kp[MPT];
+#pragma unroll
+        for (int u = 0; u < MPT; ++u) {
+            const int32_t mi = tid + u * CH;
+            x[u] = q[u] = cb[u] = st[u] = kp[u] = 0;
+            if (mi < nm) {
+                const int32_t m = m0 + mi;
+                x[u] = a.members[m];
+                q[u] = a.mem_q[m];
+                kp[u] = a.mem_kp[m];
+                cb[u] = a.mem_cb[m];
+                st[u] = a.mem_st[m];
+            }
+        }
+        float w[MPT][KMAX], sg[MPT][KMAX], r1[MPT], r2[MPT], rc[MPT];
+#pragma unroll
+        for (int u = 0; u < MPT; ++u) {
+            r1[u] = r2[u] = rc[u] = 0.0f;
+            const int kk = kp[u] & 31;
+            if (kk > 0) {
+                r1[u] = a.reach[x[u]];
+                r2[u] = a.reach[a.N + x[u]];
+                rc[u] = a.reach[2 * a.N + x[u]];
+            }
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) {
+                w[u][j] = sg[u][j] = 0.0f;
+                if (j < kk) {
+                    const int32_t ch = st[u] != 0 ? cb[u] + j * st[u] : a.child_list[cb[u] + j];
+                    w[u][j] = a.value[ch];
+                    sg[u][j] = a.prob[q[u] + j];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < MPT; ++u) {
+            const int32_t mi = tid + u * CH;
+            if (mi >= nm) continue;
+            float v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) v = fmaf(sg[u][j], w[u][j], v);
+            a.value[x[u]] = v;
+            const bool p2 = (kp[u] & 64) != 0;
+            const float cf = (p2 ? r1[u] : r2[u]) * rc[u];
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) s_con[mi][j] = cf * (w[u][j] - v);
+            s_own[mi] = p2 ? r2[u] : r1[u];
+        }
+    } else {
+        float con[KMAX];
+        float own = 0.0f;
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) con[j] = 0.0f;
+#pragma unroll 1
+        for (int32_t mi = tid; mi < nm; mi += CH) {
+            const int32_t m = m0 + mi;
+            const int32_t xm = a.members[m], qm = a.mem_q[m], cbm = a.mem_cb[m], stm = a.mem_st[m];
+            const int kpm = a.mem_kp[m];
+            const int kk = kpm & 31;
+            float w[KMAX];
+            float v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) {
+                w[j] = 0.0f;
+                if (j < kk) {
+                    w[j] = a.value[stm != 0 ? cbm + j * stm : a.child_list[cbm + j]];
+                    v = fmaf(a.prob[qm + j], w[j], v);
+                }
+            }
+            a.value[xm] = v;
+            const float r1 = a.reach[xm], r2 = a.reach[a.N + xm], rc = a.reach[2 * a.N + xm];
+            const bool p2 = (kpm & 64) != 0;
+            const float cf = (p2 ? r1 : r2) * rc;
+            own += p2 ? r2 : r1;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < kk) con[j] = fmaf(cf, w[j] - v, con[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) s_con[tid][j] = con[j];
+        s_own[tid] = own;
+    }
+    __syncthreads();
+    if (big) {
+        if (tid == 0) {
+            if (!kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
+            update_infoset<KMAX>(a, o, k, a.iplayer[h0], 0, nm < CH ? nm : CH, pr, ps, pp, s_con,
+                                 s_own);
+        }
+        return;
+    }
+    // nh <= nm <= CH * MPT: each thread has at most MPT infosets
+#pragma unroll
+    for (int u = 0; u < MPT; ++u) {
+        const int32_t li = tid + u * CH;
+        if (li >= nh) break;
+        const int32_t h = h0 + li;
+        if (u > 0) {
+            o = a.q_offset[h];
+            k = a.q_offset[h + 1] - o;
+        }
+        if (u > 0 || !kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
+        update_infoset<KMAX>(a, o, k, a.iplayer[h], a.member_offset[h] - m0,
+                             a.member_offset[h + 1] - m0, pr, ps, pp, s_con, s_own);
+    }
+}
+
+// Bottom-up of one level: workgroups [0, nk) take the level's chunks, the rest its chance
+// nodes, CH >> glog of them per workgroup.
+template <int KMAX, int CH, int MPT>
+__global__ void __launch_bounds__(CH) k_x_up_level(UpArgs a, int32_t klo, int32_t nk, int32_t clo,
+                                                   int32_t nc, int glog) {
+    __shared__ float s_con[CH * MPT][KMAX];
+    __shared__ float s_own[CH * MPT];
+    const int32_t b = static_cast<int32_t>(xcd_tile());
+    if (b < nk) {
+        up_chunk<KMAX, CH, MPT>(a, klo + b, s_con, s_own, threadIdx.x);
+        return;
+    }
+    const int32_t i = (b - nk) * (CH >> glog) + static_cast<int32_t>(threadIdx.x >> glog);
+    chance_group(a, clo + i, i < nc, threadIdx.x & ((1 << glog) - 1), glog);
+}
+
+// The shallowest levels, deepest first, in one workgroup (each level's chance nodes fit one
+// pass of the workgroup); then the iteration is counted (every read of T came before).
+__global__ void __launch_bounds__(kFuseThreads) k_x_up_top(UpArgs a, LevelTable t) {
+    __shared__ float s_con[kFuseThreads][4];
+    __shared__ float s_own[kFuseThreads];
+    const int tid = threadIdx.x;
+    for (int32_t i = 0; i < t.n; ++i) {
+        const int g = t.glog[i];
+        const int32_t ci = t.clo[i] + (tid >> g);
+        chance_group(a, ci, ci < t.chi[i], tid & ((1 << g) - 1), g);
+        for (int32_t c = t.lo[i]; c < t.hi[i]; ++c) {
+            up_chunk<4, kFuseThreads, 1>(a, c, s_con, s_own, tid);
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *a.T += 1;
 }
 
 __global__ void k_x_reset_nodes(int64_t N, int32_t n_roots, const int8_t* __restrict__ meta,
@@ -210,87 +434,225 @@ __global__ void k_x_reset_nodes(int64_t N, int32_t n_roots, const int8_t* __rest
     }
 }
 
-// ---- best response over the plan (Section 2.2)
+// ---- best response over the plan (Section 2.2), both players in one sweep
+//
+// Planes: br_reach[p N + x] = pi_{-i}(x) for i = p + 1 (chance and the other player's average
+// strategy); br_value[p N + x] = the value of x to player i when i best responds. Terminal
+// entries of br_value (+u_1, -u_1) and the roots' reach are written when the solver is built
+// and never again.
 
-__global__ void k_x_br_init(int64_t N, int32_t n_roots, const int8_t* __restrict__ meta,
-                            const float* __restrict__ payoff, float sgn,
-                            float* __restrict__ br_value, float* __restrict__ br_reach) {
+__global__ void k_x_br_setup(int64_t N, int32_t n_roots, const int8_t* __restrict__ meta,
+                             const float* __restrict__ payoff, float* __restrict__ br_value,
+                             float* __restrict__ br_reach) {
     const int64_t x = gid();
     if (x >= N) return;
-    br_value[x] = (meta[x] & 3) == 0 ? sgn * payoff[x] : 0.0f;
-    if (x < n_roots) br_reach[x] = 1.0f;
+    if ((meta[x] & 3) == 0) {
+        br_value[x] = payoff[x];
+        br_value[N + x] = -payoff[x];
+    }
+    if (x < n_roots) {
+        br_reach[x] = 1.0f;
+        br_reach[N + x] = 1.0f;
+    }
 }
 
-// pi_{-i}: chance and opponent edge probabilities only.
-__global__ void k_x_br_reach(int32_t lo, int32_t hi, int player, const int32_t* __restrict__ parent,
+// pi_{-1} takes chance and player-2 edges, pi_{-2} chance and player-1 edges (sigma-bar).
+__global__ void k_x_br_reach(int32_t lo, int32_t hi, int64_t N, const int32_t* __restrict__ parent,
                              const int32_t* __restrict__ edge, const int8_t* __restrict__ meta,
                              const float* __restrict__ avgprob, float* __restrict__ br_reach) {
-    const int64_t x = lo + gid();
-    if (x >= hi) return;
-    const int m = meta[x];
-    if ((m & 3) == 0) return;
-    const int actor = (m >> 2) - 1;  // 0 chance, 1, 2
-    const float f = actor == player ? 1.0f : avgprob[edge[x]];
-    br_reach[x] = br_reach[parent[x]] * f;
+    constexpr int NPT = 2;
+    const int64_t first = lo + static_cast<int64_t>(blockIdx.x) * blockDim.x * NPT + threadIdx.x;
+    int64_t xs[NPT];
+    int kind[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        xs[u] = first + u * static_cast<int64_t>(blockDim.x);
+        kind[u] = xs[u] < hi ? meta[xs[u]] : 0;
+    }
+    int32_t p[NPT], e[NPT];
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        p[u] = e[u] = 0;
+        if (kind[u] & 3) {
+            p[u] = parent[xs[u]];
+            e[u] = edge[xs[u]];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        if ((kind[u] & 3) == 0) continue;
+        const int actor = kind[u] >> 2;  // 1 chance, 2 player 1, 3 player 2
+        const float s = avgprob[e[u]];
+        float r0 = br_reach[p[u]], r1 = br_reach[N + p[u]];
+        if (actor != 2) r0 *= s;  // chance or player 2 moved: pi_{-1}
+        if (actor != 3) r1 *= s;  // chance or player 1 moved: pi_{-2}
+        br_reach[xs[u]] = r0;
+        br_reach[N + xs[u]] = r1;
+    }
 }
 
-// Responder's infosets: a* = argmax_a sum_m pi_{-i}(m) V(child(m, a)) (lowest index on ties)
-// and V(m) = V(child(m, a*)); other infosets and chance nodes take expectations.
-__global__ void k_x_br_up(int32_t hlo, int32_t nh, int32_t clo, int32_t nc, int player,
-                          const int32_t* __restrict__ child_begin,
-                          const int32_t* __restrict__ child_stride,
-                          const int32_t* __restrict__ child_list,
-                          const int32_t* __restrict__ q_offset, const int8_t* __restrict__ iplayer,
-                          const int32_t* __restrict__ member_offset,
-                          const int32_t* __restrict__ members,
-                          const int32_t* __restrict__ chance_nodes,
-                          const int32_t* __restrict__ chance_base,
-                          const int32_t* __restrict__ chance_k, const float* __restrict__ avgprob,
-                          const float* __restrict__ br_reach, float* __restrict__ br_value) {
-    const int64_t u = gid();
-    if (u >= static_cast<int64_t>(nh) + nc) return;
-    if (u >= nh) {
-        const int32_t ci = clo + static_cast<int32_t>(u - nh);
-        const int32_t x = chance_nodes[ci];
-        const int32_t base = chance_base[ci], k = chance_k[ci];
-        float v = 0.0f;
-        for (int32_t a = 0; a < k; ++a)
-            v = fmaf(avgprob[base + a],
-                     br_value[child_of(child_begin, child_stride, child_list, x, a)], v);
-        br_value[x] = v;
+struct BrArgs {
+    int64_t N;
+    const int32_t* chunk_first;
+    const int32_t* chunk_m;
+    const int32_t* member_offset;
+    const int32_t* members;
+    const int32_t* mem_q;
+    const int8_t* mem_kp;
+    const int32_t* mem_cb;
+    const int32_t* mem_st;
+    const int32_t* child_begin;
+    const int32_t* child_stride;
+    const int32_t* child_list;
+    const int32_t* chance_nodes;
+    const int32_t* chance_base;
+    const int32_t* chance_k;
+    const float* avgprob;
+    const float* br_reach;
+    float* br_value;
+};
+
+// One level. Chunks (one thread per member): the acting player i's plane takes, per infoset,
+// a* = argmax_a sum_m pi_{-i}(m) V_i(child(m, a)) (member order, lowest index on ties) and
+// V_i(m) = V_i(child(m, a*)); the other player's plane takes the expectation under sigma-bar.
+// Chance nodes (groups of 2^glog lanes) take expectations in both planes.
+template <int KMAX, int CH>
+__global__ void __launch_bounds__(CH) k_x_br_level(BrArgs a, int32_t klo, int32_t nk, int32_t clo,
+                                                   int32_t nc, int glog) {
+    __shared__ float s_con[CH][KMAX];
+    __shared__ int32_t s_sel[CH];
+    const int tid = threadIdx.x;
+    const int64_t N = a.N;
+    if (static_cast<int32_t>(blockIdx.x) >= nk) {
+        const int32_t i = (blockIdx.x - nk) * (CH >> glog) + (tid >> glog);
+        const int lane = tid & ((1 << glog) - 1);
+        const bool ok = i < nc;
+        float v0 = 0.0f, v1 = 0.0f;
+        int32_t x = 0;
+        if (ok) {
+            x = a.chance_nodes[clo + i];
+            const int32_t base = a.chance_base[clo + i], k = a.chance_k[clo + i];
+            const int32_t cb = a.child_begin[x], st = a.child_stride[x];
+            for (int32_t c = lane; c < k; c += 1 << glog) {
+                const int32_t ch = st != 0 ? cb + c * st : a.child_list[cb + c];
+                const float pr = a.avgprob[base + c];
+                v0 = fmaf(pr, a.br_value[ch], v0);
+                v1 = fmaf(pr, a.br_value[N + ch], v1);
+            }
+        }
+        for (int off = (1 << glog) >> 1; off > 0; off >>= 1) {
+            v0 += __shfl_xor(v0, off, 64);
+            v1 += __shfl_xor(v1, off, 64);
+        }
+        if (ok && lane == 0) {
+            a.br_value[x] = v0;
+            a.br_value[N + x] = v1;
+        }
         return;
     }
-    const int32_t h = hlo + static_cast<int32_t>(u);
-    const int32_t o = q_offset[h];
-    const int32_t k = q_offset[h + 1] - o;
-    const int32_t m0 = member_offset[h], m1 = member_offset[h + 1];
-    if (iplayer[h] == player) {
-        int32_t best = 0;
-        float best_v = 0.0f;
-        for (int32_t a = 0; a < k; ++a) {
-            float tot = 0.0f;
-            for (int32_t mi = m0; mi < m1; ++mi) {
-                const int32_t x = members[mi];
-                tot = fmaf(br_reach[x],
-                           br_value[child_of(child_begin, child_stride, child_list, x, a)], tot);
+    const int32_t c = klo + blockIdx.x;
+    const int32_t h0 = a.chunk_first[c], h1 = a.chunk_first[c + 1];
+    const int32_t m0 = a.chunk_m[c], m1 = a.chunk_m[c + 1];
+    const int32_t nm = m1 - m0;
+    const bool big = nm > CH;
+    float wr[KMAX];
+    int32_t x = 0, resp = 0;
+    if (!big) {
+        const bool ok = tid < nm;
+        float con[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) wr[j] = con[j] = 0.0f;
+        if (ok) {
+            const int32_t m = m0 + tid;
+            x = a.members[m];
+            const int32_t q = a.mem_q[m], cb = a.mem_cb[m], st = a.mem_st[m];
+            const int kp = a.mem_kp[m];
+            const int k = kp & 31;
+            resp = (kp & 64) ? 1 : 0;
+            const float pr = a.br_reach[resp * N + x];
+            float vo = 0.0f;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) {
+                if (j < k) {
+                    const int32_t ch = st != 0 ? cb + j * st : a.child_list[cb + j];
+                    wr[j] = a.br_value[resp * N + ch];
+                    vo = fmaf(a.avgprob[q + j], a.br_value[(1 - resp) * N + ch], vo);
+                    con[j] = pr * wr[j];
+                }
             }
-            if (a == 0 || tot > best_v) {
-                best_v = tot;
-                best = a;
+            a.br_value[(1 - resp) * N + x] = vo;
+        }
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) s_con[tid][j] = con[j];
+    } else {
+        float con[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) con[j] = 0.0f;
+        for (int32_t mi = tid; mi < nm; mi += CH) {
+            const int32_t m = m0 + mi;
+            const int32_t xm = a.members[m], q = a.mem_q[m], cb = a.mem_cb[m], st = a.mem_st[m];
+            const int kp = a.mem_kp[m];
+            const int k = kp & 31;
+            const int rp = (kp & 64) ? 1 : 0;
+            const float pr = a.br_reach[rp * N + xm];
+            float vo = 0.0f;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) {
+                if (j < k) {
+                    const int32_t ch = st != 0 ? cb + j * st : a.child_list[cb + j];
+                    con[j] = fmaf(pr, a.br_value[rp * N + ch], con[j]);
+                    vo = fmaf(a.avgprob[q + j], a.br_value[(1 - rp) * N + ch], vo);
+                }
+            }
+            a.br_value[(1 - rp) * N + xm] = vo;
+        }
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) s_con[tid][j] = con[j];
+    }
+    __syncthreads();
+    if (tid < h1 - h0) {
+        const int32_t h = h0 + tid;
+        const int32_t slo = big ? 0 : a.member_offset[h] - m0;
+        const int32_t shi = big ? (nm < CH ? nm : CH) : a.member_offset[h + 1] - m0;
+        const int k = a.mem_kp[a.member_offset[h]] & 31;
+        float tot[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) tot[j] = 0.0f;
+        for (int32_t sl = slo; sl < shi; ++sl) {
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j) tot[j] += s_con[sl][j];
+        }
+        int32_t best = 0;
+        float best_v = tot[0];
+#pragma unroll
+        for (int j = 1; j < KMAX; ++j) {
+            if (j < k && tot[j] > best_v) {
+                best_v = tot[j];
+                best = j;
             }
         }
-        for (int32_t mi = m0; mi < m1; ++mi) {
-            const int32_t x = members[mi];
-            br_value[x] = br_value[child_of(child_begin, child_stride, child_list, x, best)];
+        if (big) s_sel[0] = best;
+        else
+            for (int32_t sl = slo; sl < shi; ++sl) s_sel[sl] = best;
+    }
+    __syncthreads();
+    if (!big) {
+        if (tid < nm) {
+            const int32_t b = s_sel[tid];
+            float v = wr[0];
+#pragma unroll
+            for (int j = 1; j < KMAX; ++j)
+                if (j == b) v = wr[j];
+            a.br_value[resp * N + x] = v;
         }
     } else {
-        for (int32_t mi = m0; mi < m1; ++mi) {
-            const int32_t x = members[mi];
-            float v = 0.0f;
-            for (int32_t a = 0; a < k; ++a)
-                v = fmaf(avgprob[o + a],
-                         br_value[child_of(child_begin, child_stride, child_list, x, a)], v);
-            br_value[x] = v;
+        const int32_t b = s_sel[0];
+        for (int32_t mi = tid; mi < nm; mi += CH) {
+            const int32_t m = m0 + mi;
+            const int32_t xm = a.members[m], cb = a.mem_cb[m], st = a.mem_st[m];
+            const int rp = (a.mem_kp[m] & 64) ? 1 : 0;
+            const int32_t ch = st != 0 ? cb + b * st : a.child_list[cb + b];
+            a.br_value[rp * N + xm] = a.br_value[rp * N + ch];
         }
     }
 }
@@ -299,11 +661,13 @@ __global__ void k_x_tick(int64_t* T) {
     if (gid() == 0) *T += 1;
 }
 
-// Best-response value of every root (level 0, in game order) into out[g * 2 + player - 1].
-__global__ void k_x_store_roots(int32_t n_roots, int player, const float* __restrict__ br_value,
+// Best-response values of every root (level 0, in game order): out[2 g + p] = plane p.
+__global__ void k_x_store_roots(int32_t n_roots, int64_t N, const float* __restrict__ br_value,
                                 double* out) {
     const int64_t g = gid();
-    if (g < n_roots) out[2 * g + player - 1] = static_cast<double>(br_value[g]);
+    if (g >= n_roots) return;
+    out[2 * g] = static_cast<double>(br_value[g]);
+    out[2 * g + 1] = static_cast<double>(br_value[N + g]);
 }
 
 __global__ void k_x_permute_values(int64_t N, const int32_t* __restrict__ canon_of,
@@ -331,76 +695,228 @@ const char* xkernel_kind_name(int kind) {
 void launch_x_reset(const XDev& x, hipStream_t st) {
     hipLaunchKernelGGL(k_x_reset_nodes, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N,
                        x.level_offset_host[1], x.meta, x.payoff, x.value, x.reach);
+    hipLaunchKernelGGL(k_x_br_setup, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N,
+                       x.level_offset_host[1], x.meta, x.payoff, x.br_value, x.br_reach);
 }
 
-template <int KMAX, int CH>
-static void launch_up_chunk(const XDev& x, int32_t l, int variant, int linear, hipStream_t st) {
+namespace {
+
+UpArgs up_args(const XDev& x, int variant, int linear) {
+    UpArgs a;
+    a.N = x.N;
+    a.chunk_first = x.chunk_first;
+    a.chunk_m = x.chunk_m;
+    a.child_begin = x.child_begin;
+    a.child_stride = x.child_stride;
+    a.child_list = x.child_list;
+    a.q_offset = x.q_offset;
+    a.iplayer = x.iplayer;
+    a.member_offset = x.member_offset;
+    a.members = x.members;
+    a.mem_q = x.mem_q;
+    a.mem_kp = x.mem_kp;
+    a.mem_cb = x.mem_cb;
+    a.mem_st = x.mem_st;
+    a.chance_nodes = x.chance_nodes;
+    a.chance_base = x.chance_base;
+    a.chance_k = x.chance_k;
+    a.prob = x.prob;
+    a.value = x.value;
+    a.reach = x.reach;
+    a.R = x.R;
+    a.S = x.S;
+    a.T = x.T;
+    a.variant = variant;
+    a.linear = linear;
+    return a;
+}
+
+template <int KMAX, int CH, int MPT>
+void launch_up_level(const XDev& x, const UpArgs& a, int32_t l, hipStream_t st) {
     const int32_t klo = x.k_level_offset_host[l], nk = x.k_level_offset_host[l + 1] - klo;
     const int32_t clo = x.c_level_offset_host[l], nc = x.c_level_offset_host[l + 1] - clo;
-    const int32_t grid = nk + (nc + CH - 1) / CH;
+    const int glog = x.chance_glog_host[l];
+    const int32_t per = CH >> glog;
+    const int32_t grid = nk + (nc + per - 1) / per;
     if (grid == 0) return;
-    hipLaunchKernelGGL((k_x_up_chunk<KMAX, CH>), dim3(grid), dim3(CH), 0, st, klo, nk, clo, nc, x.N,
-                       x.chunk_first, x.child_begin, x.child_stride, x.child_list, x.q_offset,
-                       x.iplayer, x.member_offset, x.members, x.chance_nodes, x.chance_base,
-                       x.chance_k, x.prob, x.value, x.reach, x.R, x.S, x.T, variant, linear);
+    hipLaunchKernelGGL((k_x_up_level<KMAX, CH, MPT>), dim3(grid), dim3(CH), 0, st, a, klo, nk, clo,
+                       nc, glog);
+}
+
+template <int KMAX, int MPT>
+void launch_up_threads(const XDev& x, const UpArgs& a, int32_t l, hipStream_t st) {
+    switch (x.up_threads_host[l]) {
+        case 64: launch_up_level<KMAX, 64, MPT>(x, a, l, st); break;
+        case 128: launch_up_level<KMAX, 128, MPT>(x, a, l, st); break;
+        case 512: launch_up_level<KMAX, 512, MPT>(x, a, l, st); break;
+        default: launch_up_level<KMAX, 256, MPT>(x, a, l, st); break;
+    }
 }
 
 template <int KMAX>
-static void launch_up_chunk_cap(const XDev& x, int32_t l, int variant, int linear, hipStream_t st) {
-    switch (x.chunk_cap_host != nullptr ? x.chunk_cap_host[l] : 256) {
-        case 64: launch_up_chunk<KMAX, 64>(x, l, variant, linear, st); break;
-        case 128: launch_up_chunk<KMAX, 128>(x, l, variant, linear, st); break;
-        case 512: launch_up_chunk<KMAX, 512>(x, l, variant, linear, st); break;
-        default: launch_up_chunk<KMAX, 256>(x, l, variant, linear, st); break;
+void launch_up(const XDev& x, const UpArgs& a, int32_t l, hipStream_t st) {
+    if (x.chunk_cap_host[l] > x.up_threads_host[l]) launch_up_threads<KMAX, 2>(x, a, l, st);
+    else launch_up_threads<KMAX, 1>(x, a, l, st);
+}
+
+void launch_reach_level(const XDev& x, int32_t lo, int32_t hi, hipStream_t st) {
+    const int64_t units = hi - lo;
+    const int b = shape_bucket(units);
+    const int threads = x.reach_block != nullptr ? x.reach_block[b] : kBlock;
+    const int npt = x.reach_npt != nullptr ? x.reach_npt[b] : 1;
+    const unsigned grid = blocks_of(units, threads * npt);
+    switch (npt) {
+        case 2:
+            hipLaunchKernelGGL(k_x_reach<2>, dim3(grid), dim3(threads), 0, st, lo, hi, x.N, x.parent,
+                               x.edge, x.meta, x.prob, x.reach);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_x_reach<4>, dim3(grid), dim3(threads), 0, st, lo, hi, x.N, x.parent,
+                               x.edge, x.meta, x.prob, x.reach);
+            break;
+        default:
+            hipLaunchKernelGGL(k_x_reach<1>, dim3(grid), dim3(threads), 0, st, lo, hi, x.N, x.parent,
+                               x.edge, x.meta, x.prob, x.reach);
+            break;
     }
+}
+
+}  // namespace
+
+int32_t fusable_reach_levels(const int32_t* level_offset, int32_t D) {
+    int32_t k = 0;
+    while (1 + k < D && k < kFuseMax && level_offset[k + 2] - level_offset[k + 1] <= 2 * kFuseThreads)
+        ++k;
+    return k;
+}
+
+int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_offset,
+                          const int32_t* c_level_offset, const int32_t* chance_glog, int32_t D,
+                          int32_t max_actions) {
+    if (max_actions > 4) return 0;
+    int32_t k = 0;
+    while (k <= D && k < kFuseMax && m_level_offset[k + 1] - m_level_offset[k] <= kFuseThreads &&
+           h_level_offset[k + 1] - h_level_offset[k] <= kFuseThreads &&
+           (static_cast<int64_t>(c_level_offset[k + 1] - c_level_offset[k]) << chance_glog[k]) <=
+               kFuseThreads)
+        ++k;
+    return k;
 }
 
 void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st, LaunchTimer* timer) {
     auto pre = [&](int k, int l, int64_t n) { if (timer) timer->before(k, l, n, st); };
     auto post = [&](int k) { if (timer) timer->after(k, st); };
     const int32_t* lo = x.level_offset_host;
-    for (int32_t l = 1; l < x.D; ++l) {
-        const int64_t units = lo[l + 1] - lo[l];
-        const int threads = pick(x.reach_block, units);
-        pre(XK_REACH, l, units);
-        hipLaunchKernelGGL(k_x_reach, dim3(blocks_of(units, threads)), dim3(threads), 0, st, lo[l],
-                           lo[l + 1], x.N, x.parent, x.edge, x.meta, x.prob, x.reach);
+    // top-down: the first small levels in one workgroup, then a launch per level
+    const int32_t fr = x.fused_reach;
+    if (fr > 0) {
+        LevelTable t{};
+        t.n = fr;
+        for (int32_t i = 0; i < fr; ++i) {  // entry i is level 1 + i
+            t.lo[i] = lo[1 + i];
+            t.hi[i] = lo[2 + i];
+        }
+        pre(XK_REACH, -1, lo[1 + fr] - lo[1]);
+        hipLaunchKernelGGL(k_x_reach_top, dim3(1), dim3(kFuseThreads), 0, st, t, x.N, x.parent,
+                           x.edge, x.meta, x.prob, x.reach);
         post(XK_REACH);
     }
-    for (int32_t l = x.D; l >= 0; --l) {
+    for (int32_t l = 1 + fr; l < x.D; ++l) {
+        pre(XK_REACH, l, lo[l + 1] - lo[l]);
+        launch_reach_level(x, lo[l], lo[l + 1], st);
+        post(XK_REACH);
+    }
+    // bottom-up: a launch per deep level, then the shallow levels in one workgroup
+    const UpArgs a = up_args(x, variant, linear);
+    const int32_t fu = x.fused_up;
+    for (int32_t l = x.D; l >= fu; --l) {
         const int32_t nunits = x.h_level_offset_host[l + 1] - x.h_level_offset_host[l] +
                                x.c_level_offset_host[l + 1] - x.c_level_offset_host[l];
         if (nunits == 0) continue;
         pre(XK_UP, l, x.m_level_offset_host[l + 1] - x.m_level_offset_host[l]);
-        if (x.max_actions <= 4) launch_up_chunk_cap<4>(x, l, variant, linear, st);
-        else launch_up_chunk_cap<16>(x, l, variant, linear, st);
+        if (x.max_actions <= 4) launch_up<4>(x, a, l, st);
+        else launch_up<16>(x, a, l, st);
         post(XK_UP);
     }
-    // the linear-averaging weight of every launch above read T: count the iteration last
-    hipLaunchKernelGGL(k_x_tick, dim3(1), dim3(64), 0, st, x.T);
+    if (fu > 0) {
+        LevelTable t{};
+        t.n = fu;
+        for (int32_t i = 0; i < fu; ++i) {  // entry i is level fu - 1 - i
+            const int32_t l = fu - 1 - i;
+            t.lo[i] = x.k_level_offset_host[l];
+            t.hi[i] = x.k_level_offset_host[l + 1];
+            t.clo[i] = x.c_level_offset_host[l];
+            t.chi[i] = x.c_level_offset_host[l + 1];
+            t.glog[i] = x.chance_glog_host[l];
+        }
+        pre(XK_UP, -1, x.m_level_offset_host[fu] - x.m_level_offset_host[0]);
+        hipLaunchKernelGGL(k_x_up_top, dim3(1), dim3(kFuseThreads), 0, st, a, t);
+        post(XK_UP);
+    } else {
+        // the linear-averaging weight of every launch above read T: count the iteration last
+        hipLaunchKernelGGL(k_x_tick, dim3(1), dim3(64), 0, st, x.T);
+    }
 }
 
-void launch_x_best_response(const XDev& x, const float* avgprob, int player, hipStream_t st) {
-    const float sgn = player == 1 ? 1.0f : -1.0f;
-    hipLaunchKernelGGL(k_x_br_init, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N,
-                       x.level_offset_host[1], x.meta, x.payoff, sgn, x.br_value, x.br_reach);
+namespace {
+
+template <int KMAX, int CH>
+void launch_br_level(const XDev& x, const BrArgs& a, int32_t l, hipStream_t st) {
+    const int32_t klo = x.k_level_offset_host[l], nk = x.k_level_offset_host[l + 1] - klo;
+    const int32_t clo = x.c_level_offset_host[l], nc = x.c_level_offset_host[l + 1] - clo;
+    const int glog = x.chance_glog_host[l];
+    const int32_t per = CH >> glog;
+    const int32_t grid = nk + (nc + per - 1) / per;
+    if (grid == 0) return;
+    hipLaunchKernelGGL((k_x_br_level<KMAX, CH>), dim3(grid), dim3(CH), 0, st, a, klo, nk, clo, nc,
+                       glog);
+}
+
+template <int KMAX>
+void launch_br_cap(const XDev& x, const BrArgs& a, int32_t l, hipStream_t st) {
+    switch (x.chunk_cap_host[l]) {  // one thread per member of a chunk
+        case 64: launch_br_level<KMAX, 64>(x, a, l, st); break;
+        case 128: launch_br_level<KMAX, 128>(x, a, l, st); break;
+        case 256: launch_br_level<KMAX, 256>(x, a, l, st); break;
+        case 512: launch_br_level<KMAX, 512>(x, a, l, st); break;
+        default: launch_br_level<KMAX, 1024>(x, a, l, st); break;
+    }
+}
+
+}  // namespace
+
+void launch_x_best_response(const XDev& x, const float* avgprob, hipStream_t st) {
     const int32_t* lo = x.level_offset_host;
     for (int32_t l = 1; l < x.D; ++l)
-        hipLaunchKernelGGL(k_x_br_reach, dim3(blocks_for(lo[l + 1] - lo[l])), dim3(kBlock), 0, st,
-                           lo[l], lo[l + 1], player, x.parent, x.edge, x.meta, avgprob, x.br_reach);
+        hipLaunchKernelGGL(k_x_br_reach, dim3(blocks_of(lo[l + 1] - lo[l], 2 * kBlock)), dim3(kBlock),
+                           0, st, lo[l], lo[l + 1], x.N, x.parent, x.edge, x.meta, avgprob,
+                           x.br_reach);
+    BrArgs a;
+    a.N = x.N;
+    a.chunk_first = x.chunk_first;
+    a.chunk_m = x.chunk_m;
+    a.member_offset = x.member_offset;
+    a.members = x.members;
+    a.mem_q = x.mem_q;
+    a.mem_kp = x.mem_kp;
+    a.mem_cb = x.mem_cb;
+    a.mem_st = x.mem_st;
+    a.child_begin = x.child_begin;
+    a.child_stride = x.child_stride;
+    a.child_list = x.child_list;
+    a.chance_nodes = x.chance_nodes;
+    a.chance_base = x.chance_base;
+    a.chance_k = x.chance_k;
+    a.avgprob = avgprob;
+    a.br_reach = x.br_reach;
+    a.br_value = x.br_value;
     for (int32_t l = x.D; l >= 0; --l) {
-        const int32_t hlo = x.h_level_offset_host[l], nh = x.h_level_offset_host[l + 1] - hlo;
-        const int32_t clo = x.c_level_offset_host[l], nc = x.c_level_offset_host[l + 1] - clo;
-        if (nh + nc == 0) continue;
-        hipLaunchKernelGGL(k_x_br_up, dim3(blocks_for(static_cast<int64_t>(nh) + nc)), dim3(kBlock),
-                           0, st, hlo, nh, clo, nc, player, x.child_begin, x.child_stride,
-                           x.child_list, x.q_offset, x.iplayer, x.member_offset, x.members,
-                           x.chance_nodes, x.chance_base, x.chance_k, avgprob, x.br_reach,
-                           x.br_value);
+        if (x.max_actions <= 4) launch_br_cap<4>(x, a, l, st);
+        else launch_br_cap<16>(x, a, l, st);
     }
-    const int32_t n_roots = x.level_offset_host[1];
-    hipLaunchKernelGGL(k_x_store_roots, dim3(blocks_for(n_roots)), dim3(kBlock), 0, st, n_roots,
-                       player, x.br_value, x.out2);
+    const int32_t n_roots = lo[1];
+    hipLaunchKernelGGL(k_x_store_roots, dim3(blocks_for(n_roots)), dim3(kBlock), 0, st, n_roots, x.N,
+                       x.br_value, x.out2);
 }
 
 void launch_x_values_to_canonical(const XDev& x, float* dst, hipStream_t st) {

@@ -13,23 +13,35 @@ namespace cfr {
 enum XKernelKind { XK_REACH = K_NUM_KINDS, XK_UP = K_NUM_KINDS + 1 };
 const char* xkernel_kind_name(int kind);
 
-// Launch shapes: threads per workgroup for a launch of `units` work items is
-// table[bucket(units)], bucket = floor(log2(units)) clamped to [0, kShapeBuckets).
+// Launch shapes are chosen per log2 bucket of a launch's work items:
+// bucket = floor(log2(units)) clamped to [0, kShapeBuckets).
 constexpr int kShapeBuckets = 32;
 int shape_bucket(int64_t units);
+
+// Levels handled together by the single-workgroup kernels of the first levels.
+constexpr int kFuseMax = 8;
+constexpr int kFuseThreads = 1024;
 
 struct XDev {
     int64_t N, Hp, Qp, Q0, M, L, C;
     int32_t D, max_actions;
-    const int32_t* up_block;     // host, kShapeBuckets entries (unused by the chunked bottom-up)
-    const int32_t* reach_block;  // host, kShapeBuckets entries (nullptr: 256 threads)
+    // launch shapes (host): top-down threads and nodes per thread per bucket of level size
+    const int32_t* reach_block;  // kShapeBuckets entries (nullptr: 256)
+    const int32_t* reach_npt;    // kShapeBuckets entries (nullptr: 1)
+    // bottom-up shapes (host), per level: threads per workgroup and members per chunk
+    // (threads x members per thread)
+    const int32_t* up_threads_host;      // D + 1
+    const int32_t* chunk_cap_host;       // D + 1
     const int32_t* k_level_offset_host;  // D + 2: chunks of each level
-    const int32_t* chunk_cap_host;       // D + 1: members per chunk (= threads) of each level
     const int32_t* m_level_offset_host;  // D + 2: first member of each level
+    const int32_t* chance_glog_host;     // D + 1: log2 of lanes per chance node
     // host copies of the level tables (launch bounds)
     const int32_t* level_offset_host;
     const int32_t* h_level_offset_host;
     const int32_t* c_level_offset_host;
+    // the first levels run in one workgroup: top-down levels 1 .. fused_reach and
+    // bottom-up levels fused_up - 1 .. 0 (0: none)
+    int32_t fused_reach, fused_up;
     // plan arrays (exec order)
     int32_t* parent;
     int32_t* edge;
@@ -42,10 +54,17 @@ struct XDev {
     int8_t* iplayer;
     int32_t* member_offset;
     int32_t* members;
+    // member-major copies (member m of the level-ordered member list): its infoset's first
+    // pair, k | (player 2 ? 64 : 0), and its node's child begin and stride
+    int32_t* mem_q;
+    int8_t* mem_kp;
+    int32_t* mem_cb;
+    int32_t* mem_st;
     int32_t* chance_nodes;
     int32_t* chance_base;  // index into prob of the chance node's action 0
     int32_t* chance_k;
     int32_t* chunk_first;  // chunks + 1 (capacity Hp + D + 2)
+    int32_t* chunk_m;      // first member of each chunk, chunks + 1
     int32_t* q_input;
     float* payoff;
     // state (exec order)
@@ -55,15 +74,23 @@ struct XDev {
     float* value;    // N (terminals hold the payoff)
     float* reach;    // 3N planes
     int64_t* T;
-    float* br_reach;
-    float* br_value;
+    float* br_reach;  // 2N: pi_{-1}, pi_{-2}
+    float* br_value;  // 2N: values under player 1's, player 2's best response
     double* out2;
 };
+
+// How many first levels the single-workgroup kernels take (from the plan's level tables).
+int32_t fusable_reach_levels(const int32_t* level_offset, int32_t D);
+int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_offset,
+                          const int32_t* c_level_offset, const int32_t* chance_glog, int32_t D,
+                          int32_t max_actions);
 
 void launch_x_reset(const XDev& x, hipStream_t st);
 void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st,
                         LaunchTimer* timer = nullptr);
-void launch_x_best_response(const XDev& x, const float* avgprob, int player, hipStream_t st);
+// Best responses of both players to sigma-bar (avgprob: exec pairs, then sigma_0); the root
+// values land in out2[2 g], out2[2 g + 1].
+void launch_x_best_response(const XDev& x, const float* avgprob, hipStream_t st);
 void launch_x_values_to_canonical(const XDev& x, float* dst, hipStream_t st);
 void launch_x_reach_to_canonical(const XDev& x, float* dst, hipStream_t st);
 

@@ -109,6 +109,13 @@ def host_layout(game, names=None) -> dict:
         lib.cfr_host_layout_destroy(h)
 
 
+def default_launch_shape(lib=None) -> "N.CfrLaunchShape":
+    """The library's default launch shapes (a cfr_launch_shape)."""
+    sh = N.CfrLaunchShape()
+    (lib or N.load()).cfr_default_launch_shape(ctypes.byref(sh))
+    return sh
+
+
 class Solver:
     """CFR (vanilla or CFR+) over one game, resident on one GPU."""
 
@@ -173,17 +180,24 @@ class Solver:
         return [{"kernel": self._lib.cfr_kernel_name(int(kind[i])).decode(), "level": int(level[i]),
                  "units": int(units[i]), "ms": float(ms[i]) / n} for i in range(min(nl.value, cap))]
 
-    def set_launch_shape(self, up_threads=None, reach_threads=None) -> None:
-        """Threads per workgroup per log2 bucket of work items (None: default 256)."""
-        if up_threads is None and reach_threads is None:
-            N.check(self._lib.cfr_set_launch_shape(self._h, None, None, 0))
+    def set_launch_shape(self, up_threads=None, reach_threads=None, up_members=None,
+                         reach_nodes=None) -> None:
+        """Launch shapes per log2 bucket of work items: bottom-up threads per workgroup and
+        members per thread, top-down threads per workgroup and nodes per thread (a scalar or
+        a list of up to 32 buckets, the last entry repeated). Arguments left None keep the
+        library default; all None restores every default."""
+        if all(v is None for v in (up_threads, reach_threads, up_members, reach_nodes)):
+            N.check(self._lib.cfr_set_launch_shape(self._h, None))
             return
-        up = np.ascontiguousarray(up_threads if up_threads is not None else [256] * 32, np.int32)
-        re = np.ascontiguousarray(reach_threads if reach_threads is not None else [256] * 32,
-                                  np.int32)
-        n = min(len(up), len(re))
-        N.check(self._lib.cfr_set_launch_shape(self._h, _ptr(up, ctypes.c_int32),
-                                               _ptr(re, ctypes.c_int32), n))
+        sh = default_launch_shape(self._lib)
+        for name, val in (("up_threads", up_threads), ("up_members", up_members),
+                          ("reach_threads", reach_threads), ("reach_nodes", reach_nodes)):
+            if val is None:
+                continue
+            vals = [int(val)] * 32 if np.isscalar(val) else [int(v) for v in val]
+            vals = (vals + [vals[-1]] * 32)[:32]
+            getattr(sh, name)[:] = vals
+        N.check(self._lib.cfr_set_launch_shape(self._h, ctypes.byref(sh)))
 
     def synchronize(self) -> None:
         self.stream.synchronize()

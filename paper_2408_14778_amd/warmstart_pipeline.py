@@ -1,6 +1,6 @@
 """Training and evaluation of the learned warm start on the batched subgame family.
 
-    python -m paper_2408_14778_amd.warmstart_pipeline --train-games 4096 --out-weights W.npy
+    python -m paper_2408_14778_amd.warmstart_pipeline --train-games 20000 --out-weights W.npy
 
 1. Data: seeded subgames (training seeds from 10,000 up, disjoint from the evaluation seeds
    100-611) are solved in batches by GPU CFR+; each infoset's target is the average strategy
@@ -42,6 +42,10 @@ def _subgame(seed):
 def build_games(seeds, workers: int = 16):
     with Pool(workers) as pool:
         return pool.map(_subgame, list(seeds), chunksize=4)
+
+
+def _batches(total: int, size: int, first_seed: int):
+    return [range(first_seed + s, first_seed + min(total, s + size)) for s in range(0, total, size)]
 
 
 def solve_targets(game_list, iterations: int, per_game: int, rng) -> dict:
@@ -101,6 +105,8 @@ def run_to_target(solver, target: float, check_every: int, max_iters: int, done:
         worst = float(np.max(solver.exploitability()["expl"]))
         if worst <= target:
             break
+        if (it // check_every) % 50 == 0:
+            log(f"  iteration {it}: max exploitability {worst:.3e}")
     torch.cuda.synchronize()
     return it, worst
 
@@ -136,7 +142,7 @@ def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: i
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train-games", type=int, default=4096)
+    ap.add_argument("--train-games", type=int, default=20000)
     ap.add_argument("--batch-games", type=int, default=512)
     ap.add_argument("--solve-iters", type=int, default=300)
     ap.add_argument("--per-game", type=int, default=256)
@@ -149,6 +155,8 @@ def main() -> int:
     ap.add_argument("--out-json", default=None)
     args = ap.parse_args()
     sys.path.insert(0, ROOT)
+    # the worker processes are forked before this process touches the GPU
+    pool = Pool(args.workers)
     import torch
     from . import warmstart as ws
 
@@ -156,31 +164,48 @@ def main() -> int:
     rng = np.random.default_rng(0)
     parts = []
     t0 = time.time()
-    for start in range(0, args.train_games, args.batch_games):
-        seeds = range(10000 + start, 10000 + min(args.train_games, start + args.batch_games))
-        gl = build_games(seeds, args.workers)
+    batches = _batches(args.train_games, args.batch_games, 10000)
+    n_games = 0
+    # the host builds batch i + 1 while the GPU solves batch i
+    pending = pool.map_async(_subgame, list(batches[0]), chunksize=4)
+    for i, seeds in enumerate(batches):
+        gl = pending.get()
+        if i + 1 < len(batches):
+            pending = pool.map_async(_subgame, list(batches[i + 1]), chunksize=4)
+        else:
+            pending = pool.map_async(_subgame, list(range(100, 100 + args.eval_games)), chunksize=4)
         d = solve_targets(gl, args.solve_iters, args.per_game, rng)
         log(f"solved training seeds {seeds.start}-{seeds.stop - 1}: {len(d['desc'])} samples, "
             f"median expl {np.median(d['expl']):.2e} ({time.time() - t0:.0f}s)")
         d["desc"] = d["desc"].copy()
-        d["desc"][:, 15] += sum(len(p["beliefs"]) for p in parts)  # global game index
+        d["desc"][:, 15] += n_games  # global game index into the stacked beliefs
+        n_games += len(gl)
         parts.append(d)
         del gl
     data = {"desc": np.concatenate([p["desc"] for p in parts]),
             "beliefs": np.concatenate([p["beliefs"] for p in parts]),
             "target": np.concatenate([p["target"] for p in parts]),
             "mask": np.concatenate([p["mask"] for p in parts])}
+    del parts
     net = ws.WarmStartNet(max_batch=4096, seed=1)
+    t1 = time.time()
     losses = train(net, data, args.epochs, 4096, args.lr)
+    log(f"trained on {len(data['desc'])} samples in {time.time() - t1:.1f}s")
     os.makedirs(os.path.dirname(args.out_weights), exist_ok=True)
     np.save(args.out_weights, net.params())
     log(f"weights written to {args.out_weights}")
-    gl = build_games(range(100, 100 + args.eval_games), args.workers)
-    res = evaluate(gl, net, args.weight)
+    gl = pending.get()
+    pool.close()
+    infer = ws.WarmStartNet(max_batch=65536)
+    infer.set_params(net.params())
+    res = evaluate(gl, infer, args.weight)
     res.update({"train_games": args.train_games, "solve_iters": args.solve_iters,
                 "samples": int(len(data["desc"])), "losses": losses, "weight": args.weight,
                 "eval_games": args.eval_games})
     log(json.dumps(res))
+    side = os.path.splitext(args.out_weights)[0] + ".json"
+    with open(side, "w") as f:
+        json.dump({"weight": args.weight, "shape": list(net.shape), "results": res}, f, indent=1)
     if args.out_json:
         with open(args.out_json, "w") as f:
             json.dump(res, f, indent=1)

@@ -21,13 +21,22 @@ def _lib():
 
 def test_every_declared_symbol_is_exported():
     header = open(os.path.join(ROOT, "include", "cfr.h")).read()
-    names = set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(cfr_\w+)\s*\(", header, re.M))
-    assert len(names) >= 24
+    names = set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(cfr_\w+)\s*\(", header,
+                           re.M))
+    assert len(names) >= 25
     lib = _lib()
     from paper_2408_14778_amd import _native
     for n in sorted(names):
         assert hasattr(lib, n), n
         assert n in _native.SIGNATURES, f"{n} has no binding"
+
+
+def test_default_launch_shape():
+    from paper_2408_14778_amd.solver import default_launch_shape
+    sh = default_launch_shape()
+    for name, allowed in (("up_threads", {64, 128, 256, 512}), ("up_members", {1, 2}),
+                          ("reach_threads", set(range(64, 1025, 64))), ("reach_nodes", {1, 2, 4})):
+        assert set(getattr(sh, name)) <= allowed, name
 
 
 def test_warmstart_symbols_are_exported():

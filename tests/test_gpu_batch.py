@@ -108,12 +108,12 @@ def test_launch_shapes_do_not_change_results():
     ref = BatchSolver(gl, "cfr+", tuned=False)
     ref.iterate(9)
     _, R0, S0 = ref.get_state()
-    for threads in (64, 128, 512):
+    for ut, um, rt, rn in ((64, 1, 64, 1), (128, 2, 256, 4), (512, 2, 1024, 2), (256, 1, 512, 4)):
         b = BatchSolver(gl, "cfr+", tuned=False)
-        b.set_launch_shape([threads] * 32, [threads] * 32)
+        b.set_launch_shape(up_threads=ut, up_members=um, reach_threads=rt, reach_nodes=rn)
         b.iterate(9)
         _, R, S = b.get_state()
-        assert np.array_equal(R, R0) and np.array_equal(S, S0), threads
+        assert np.array_equal(R, R0) and np.array_equal(S, S0), (ut, um, rt, rn)
 
 
 def test_autotuner_measures_and_chooses():
@@ -122,11 +122,68 @@ def test_autotuner_measures_and_chooses():
     b = BatchSolver(gl, "cfr+", tuned=False)
     b.iterate(2)
     T0, R0, S0 = b.get_state()
-    m = autotune.measure(b, candidates=(64, 256), iters=2)
+    m = autotune.measure(b, iters=2, up=((64, 1), (256, 2)), reach=((256, 1), (128, 4)))
     T1, R1, S1 = b.get_state()
     assert T1 == T0 and np.array_equal(R1, R0)      # state restored
     assert "block_up" in m and "block_reach" in m
     table = autotune.choose(m)
     assert len(table["up_threads"]) == 32 and set(table["up_threads"]) <= {64, 256}
+    assert {(t, m) for t, m in zip(table["up_threads"], table["up_members"])} <= {(64, 1), (256, 2)}
+    assert {(t, n) for t, n in zip(table["reach_threads"], table["reach_nodes"])} <= {(256, 1),
+                                                                                      (128, 4)}
     autotune.apply(b, table)
     b.iterate(1)
+
+
+@pytest.fixture(scope="module")
+def full_batch():
+    """The batched workload at full size: 512 subgames, seeds 100-611."""
+    return [games.subgame(s) for s in range(100, 612)]
+
+
+def test_full_batch_sampled_games_match_single_and_oracle(full_batch):
+    """One CFR+ iteration of the 512-subgame forest from seeded states, checked game by game on a
+    sample (smallest, largest, two seeded picks) against solving the game alone, and the
+    smallest against the FP64 oracle."""
+    from paper_2408_14778_amd import BatchSolver, Solver
+    gl = full_batch
+    sizes = np.array([g.n_nodes for g in gl])
+    assert sizes.sum() > 5e7
+    states = [games.random_state(g, seed=1000 + i, nonnegative=True) for i, g in enumerate(gl)]
+    T = 37
+    b = BatchSolver(gl, "cfr+")
+    b.set_state(T, np.concatenate([st[1] for st in states]), np.concatenate([st[2] for st in states]))
+    b.iterate(1)
+    _, Rb, Sb = b.get_state()
+    Rs_b, Ss_b = b.split(Rb), b.split(Sb)
+    pick = sorted({int(sizes.argmin()), int(sizes.argmax())} |
+                  set(np.random.default_rng(5).choice(len(gl), 2, replace=False).tolist()))
+    for i in pick:
+        s = Solver(gl[i], "cfr+")
+        s.set_state(T, states[i][1], states[i][2])
+        s.iterate(1)
+        _, Rs, Ss = s.get_state()
+        s.close()
+        assert _rel(Rs_b[i], Rs) <= 1e-6 and _rel(Ss_b[i], Ss) <= 1e-6, i
+    i = int(sizes.argmin())
+    t = Tree(gl[i])
+    new, _ = cfr.iterate(t, cfr.State(T, [float(x) for x in states[i][1]],
+                                      [float(x) for x in states[i][2]]), "cfr+")
+    assert _rel(Rs_b[i], new.R) <= 1e-6 and _rel(Ss_b[i], new.S) <= 1e-6
+    # every game's state is finite and CFR+ regrets stay nonnegative
+    assert np.all(np.isfinite(Rb)) and np.all(Rb >= 0) and np.all(np.isfinite(Sb))
+
+
+def test_full_batch_exploitability_matches_single(full_batch):
+    from paper_2408_14778_amd import BatchSolver, Solver
+    gl = full_batch
+    b = BatchSolver(gl, "cfr+")
+    b.iterate(30)
+    e = b.exploitability()["expl"]
+    assert e.shape == (512,) and np.all(e >= -1e-6)
+    for i in np.random.default_rng(9).choice(len(gl), 3, replace=False):
+        s = Solver(gl[int(i)], "cfr+")
+        s.iterate(30)
+        es = s.exploitability()["expl"]
+        s.close()
+        assert abs(e[int(i)] - es) <= 1e-5 * max(1.0, abs(es)), int(i)
