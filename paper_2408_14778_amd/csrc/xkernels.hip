@@ -271,11 +271,15 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
     const int32_t m0 = a.chunk_m[c], m1 = a.chunk_m[c + 1];
     const int32_t nm = m1 - m0, nh = h1 - h0;
     const bool big = nm > CAP;
-    int32_t o = 0, k = 0;
+    int32_t o = 0, k = 0, slo = 0, shi = 0;
+    int player = 1;
     float pr[KMAX], ps[KMAX], pp[KMAX];
     if (tid < nh) {
         o = a.q_offset[h0 + tid];
         k = a.q_offset[h0 + tid + 1] - o;
+        slo = a.member_offset[h0 + tid] - m0;
+        shi = a.member_offset[h0 + tid + 1] - m0;
+        player = a.iplayer[h0 + tid];
         if (kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
     }
     if (!big) {
@@ -365,7 +369,7 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
     if (big) {
         if (tid == 0) {
             if (!kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
-            update_infoset<KMAX>(a, o, k, a.iplayer[h0], 0, nm < CH ? nm : CH, pr, ps, pp, s_con,
+            update_infoset<KMAX>(a, o, k, player, 0, nm < CH ? nm : CH, pr, ps, pp, s_con,
                                  s_own);
         }
         return;
@@ -376,13 +380,15 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
         const int32_t li = tid + u * CH;
         if (li >= nh) break;
         const int32_t h = h0 + li;
-        if (u > 0) {
+        if (u > 0) {  // the first infoset's operands were loaded before phase 1
             o = a.q_offset[h];
             k = a.q_offset[h + 1] - o;
+            slo = a.member_offset[h] - m0;
+            shi = a.member_offset[h + 1] - m0;
+            player = a.iplayer[h];
         }
         if (u > 0 || !kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
-        update_infoset<KMAX>(a, o, k, a.iplayer[h], a.member_offset[h] - m0,
-                             a.member_offset[h + 1] - m0, pr, ps, pp, s_con, s_own);
+        update_infoset<KMAX>(a, o, k, player, slo, shi, pr, ps, pp, s_con, s_own);
     }
 }
 

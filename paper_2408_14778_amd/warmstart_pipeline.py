@@ -7,10 +7,13 @@
    GPU CFR+ reaches after K iterations, over its legal action slots.
 2. Training: minibatch Adam on the masked softmax cross-entropy, all on the GPU with the
    library's BF16-MFMA kernels (features, forward, backward, optimiser).
-3. Evaluation: on the held-out batch, plain CFR+ from zero regrets against the warm start,
-   both checked with the best-response pass every `check_every` iterations until the largest
-   exploitability in the batch is at most the target; wall time includes the network's
-   inference and the warm start's own checks.
+3. Weight: the warm-start weight (how strongly the initial regrets commit to the network's
+   strategy) is chosen on validation seeds 9000.. by mean iterations to the target.
+4. Evaluation: on the held-out batch, plain CFR+ from zero regrets against the warm start,
+   both checked with the best-response pass every `check_every` iterations; a game is solved
+   at its first check with exploitability at most the target, and the batch when every game
+   is. Wall time includes the network's inference and the warm start's own checks; per-game
+   iteration counts are compared pairwise.
 """
 from __future__ import annotations
 
@@ -24,6 +27,7 @@ from multiprocessing import Pool
 import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+VAL_SEED = 9000   # validation seeds 9000.. (training 10000.., evaluation 100-611)
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning",
                             "warmstart_gfx950.npy")
 
@@ -94,35 +98,63 @@ def train(net, data: dict, epochs: int, batch: int, lr: float, seed: int = 0) ->
     return losses
 
 
-def run_to_target(solver, target: float, check_every: int, max_iters: int, done: int = 0):
-    """Iterate with best-response checks until max exploitability <= target."""
+def run_to_target(solver, target: float, check_every: int, max_iters: int, done: int = 0,
+                  t0: float = None):
+    """Iterate with best-response checks every `check_every` iterations. A game is solved at
+    the first check where its exploitability is at most `target` (a batched solver keeps that
+    game's average strategy from then on); returns, per game, the iteration and the wall time
+    (from t0) at which it was solved (-1 / inf if it never was) and the exploitability then."""
     import torch
+    t0 = time.perf_counter() if t0 is None else t0
+    n = solver.n_games
+    solved_it = np.full(n, -1, dtype=np.int64)
+    solved_s = np.full(n, np.inf)
+    solved_e = np.full(n, np.nan)
     it = done
-    worst = float("inf")
     while it < max_iters:
         solver.iterate(check_every)
         it += check_every
-        worst = float(np.max(solver.exploitability()["expl"]))
-        if worst <= target:
+        e = solver.exploitability()["expl"]
+        now = time.perf_counter() - t0
+        new = (solved_it < 0) & (e <= target)
+        solved_it[new], solved_s[new], solved_e[new] = it, now, e[new]
+        if np.all(solved_it >= 0):
             break
         if (it // check_every) % 50 == 0:
-            log(f"  iteration {it}: max exploitability {worst:.3e}")
+            log(f"  iteration {it}: {int(np.sum(solved_it >= 0))}/{n} solved, "
+                f"max exploitability {float(np.max(e)):.3e}")
     torch.cuda.synchronize()
-    return it, worst
+    return solved_it, solved_s, solved_e
+
+
+def _arm(solved_it, solved_s) -> dict:
+    ok = solved_it >= 0
+    ts = np.sort(solved_s)
+    return {"iterations": int(solved_it.max()) if ok.all() else -1,
+            "seconds": float(solved_s.max()),
+            "solved": int(ok.sum()),
+            "seconds_until_solved_fraction": {
+                str(f): float(ts[max(0, int(np.ceil(f * len(ts))) - 1)])
+                for f in (0.5, 0.9, 0.99, 1.0)},
+            "per_game_iterations": {"mean": float(solved_it[ok].mean()),
+                                    "median": float(np.median(solved_it[ok])),
+                                    "p90": float(np.percentile(solved_it[ok], 90)),
+                                    "max": int(solved_it[ok].max())}}
 
 
 def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: int = 10,
-             max_iters: int = 4000) -> dict:
+             max_iters: int = 20000) -> dict:
+    """Plain zero-start CFR+ against the warm start on the same batch: wall time until every
+    game is solved (the batch's time to the target), and per game the iterations to it."""
     import torch
     from . import warmstart as ws
     from .solver import BatchSolver
     out = {}
-    # plain CFR+ from zero regrets
     b = BatchSolver(game_list, "cfr+")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, worst = run_to_target(b, target, check_every, max_iters)
-    out["plain"] = {"iterations": iters, "seconds": time.perf_counter() - t0, "max_expl": worst}
+    p_it, p_s, _ = run_to_target(b, target, check_every, max_iters, t0=t0)
+    out["plain"] = _arm(p_it, p_s)
     b.close()
     del b
     # warm start (one zero-start iteration, network inference, fallback check, then CFR+)
@@ -130,13 +162,21 @@ def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: i
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = ws.warm_start(b, net, game_list, weight)
-    iters, worst = run_to_target(b, target, check_every, max_iters, done=2)
-    out["warm"] = {"iterations": iters, "seconds": time.perf_counter() - t0, "max_expl": worst,
-                   "warm_start_seconds": info["seconds"],
-                   "fallback_games": info["fallback_games"],
-                   "first_expl_zero": float(np.max(info["expl_zero_start"])),
-                   "first_expl_warm": float(np.max(info["expl_warm_start"]))}
+    w_it, w_s, _ = run_to_target(b, target, check_every, max_iters, done=2, t0=t0)
+    out["warm"] = _arm(w_it, w_s)
+    out["warm"].update({"warm_start_seconds": info["seconds"],
+                        "fallback_games": info["fallback_games"],
+                        "first_expl_zero_max": float(np.max(info["expl_zero_start"])),
+                        "first_expl_warm_max": float(np.max(info["expl_warm_start"]))})
     b.close()
+    both = (p_it >= 0) & (w_it >= 0)
+    ratio = w_it[both] / np.maximum(p_it[both], 1)
+    out["paired"] = {"games": int(both.sum()),
+                     "warm_faster": int(np.sum(w_it[both] < p_it[both])),
+                     "warm_slower": int(np.sum(w_it[both] > p_it[both])),
+                     "geomean_iteration_ratio": float(np.exp(np.mean(np.log(ratio)))),
+                     "mean_iterations_plain": float(p_it[both].mean()),
+                     "mean_iterations_warm": float(w_it[both].mean())}
     return out
 
 
@@ -144,11 +184,13 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-games", type=int, default=20000)
     ap.add_argument("--batch-games", type=int, default=512)
-    ap.add_argument("--solve-iters", type=int, default=300)
+    ap.add_argument("--solve-iters", type=int, default=1000)
     ap.add_argument("--per-game", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--weight", type=float, default=10.0)
+    ap.add_argument("--weights", default="3,10,30,100",
+                    help="warm-start weights tried on the validation games; the best is used")
+    ap.add_argument("--val-games", type=int, default=128)
     ap.add_argument("--eval-games", type=int, default=512)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out-weights", default=WEIGHTS_PATH)
@@ -173,7 +215,8 @@ def main() -> int:
         if i + 1 < len(batches):
             pending = pool.map_async(_subgame, list(batches[i + 1]), chunksize=4)
         else:
-            pending = pool.map_async(_subgame, list(range(100, 100 + args.eval_games)), chunksize=4)
+            pending = pool.map_async(_subgame, list(range(VAL_SEED, VAL_SEED + args.val_games)),
+                                     chunksize=4)
         d = solve_targets(gl, args.solve_iters, args.per_game, rng)
         log(f"solved training seeds {seeds.start}-{seeds.stop - 1}: {len(d['desc'])} samples, "
             f"median expl {np.median(d['expl']):.2e} ({time.time() - t0:.0f}s)")
@@ -194,18 +237,36 @@ def main() -> int:
     os.makedirs(os.path.dirname(args.out_weights), exist_ok=True)
     np.save(args.out_weights, net.params())
     log(f"weights written to {args.out_weights}")
-    gl = pending.get()
-    pool.close()
     infer = ws.WarmStartNet(max_batch=65536)
     infer.set_params(net.params())
-    res = evaluate(gl, infer, args.weight)
+    # the weight is chosen on validation games (seeds disjoint from training and evaluation)
+    val = pending.get()
+    pending = pool.map_async(_subgame, list(range(100, 100 + args.eval_games)), chunksize=4)
+    sweep = {}
+    for w in [float(v) for v in args.weights.split(",")]:
+        r = evaluate(val, infer, w)
+        sweep[w] = r
+        log(f"validation weight {w}: plain {r['plain']['seconds']:.3f}s, mean "
+            f"{r['paired']['mean_iterations_plain']:.0f} it; warm {r['warm']['seconds']:.3f}s, "
+            f"mean {r['paired']['mean_iterations_warm']:.0f} it")
+    # chosen by the mean per-game iterations to the target (less noisy than the slowest game)
+    weight = min(sweep, key=lambda w: sweep[w]["paired"]["mean_iterations_warm"])
+    del val
+    gl = pending.get()
+    pool.close()
+    res = evaluate(gl, infer, weight)
     res.update({"train_games": args.train_games, "solve_iters": args.solve_iters,
-                "samples": int(len(data["desc"])), "losses": losses, "weight": args.weight,
-                "eval_games": args.eval_games})
+                "samples": int(len(data["desc"])), "losses": losses, "weight": weight,
+                "eval_games": args.eval_games, "eval_seeds": [100, 99 + args.eval_games],
+                "validation": {str(w): {"plain_s": r["plain"]["seconds"],
+                                        "warm_s": r["warm"]["seconds"],
+                                        "plain_mean_it": r["paired"]["mean_iterations_plain"],
+                                        "warm_mean_it": r["paired"]["mean_iterations_warm"]}
+                               for w, r in sweep.items()}})
     log(json.dumps(res))
     side = os.path.splitext(args.out_weights)[0] + ".json"
     with open(side, "w") as f:
-        json.dump({"weight": args.weight, "shape": list(net.shape), "results": res}, f, indent=1)
+        json.dump({"weight": weight, "shape": list(net.shape), "results": res}, f, indent=1)
     if args.out_json:
         with open(args.out_json, "w") as f:
             json.dump(res, f, indent=1)
