@@ -27,10 +27,12 @@ struct cfr_solver {
     bool canonical = true;     // the canonical layout arrays are on the device
     std::vector<int32_t> x_level_offset, x_h_level_offset, x_c_level_offset;
     cfr_launch_shape shape{};                    // launch shapes per bucket
-    std::vector<int32_t> reach_threads, reach_npt;  // views of `shape` for the kernels
     std::vector<int32_t> x_member_offset;        // host copy (chunk tables)
     std::vector<int32_t> x_k_level_offset, x_m_level_offset;
     std::vector<int32_t> up_threads, chunk_cap, chance_glog;  // per level
+    std::vector<int8_t> x_meta;                                 // host copy (top-down tiles)
+    std::vector<int32_t> reach_threads_l, reach_npt_l, t_level_offset;
+    std::vector<int64_t> reach_units;  // decision nodes per level
     int variant = CFR_VANILLA;
     int linear = 0;
     bool use_graph = true;
@@ -89,6 +91,7 @@ struct Carve {
 // Sizes the device arrays depend on.
 struct Sizes {
     int64_t N = 0, Hp = 0, Qp = 0, H0 = 0, Q0 = 0, M = 0, C = 0, L = 0;
+    int64_t terminals = 0;
     int32_t D = 0, max_actions = 0;
     int engine = ENGINE_NODE;
     bool canonical = true;   // false for a batch: only the execution plan is on the device
@@ -167,6 +170,8 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
         x.mem_kp = c.take<int8_t>(M);
         x.mem_cb = c.take<int32_t>(M);
         x.mem_st = c.take<int32_t>(M);
+        x.tile_lo = c.take<int32_t>(N - z.terminals);
+        x.tile_hi = c.take<int32_t>(N - z.terminals);
         x.chunk_first = c.take<int32_t>(Hp + D + 2);
         x.chunk_m = c.take<int32_t>(Hp + D + 2);
         x.q_input = c.take<int32_t>(Qp);
@@ -239,6 +244,7 @@ int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out)
     if (rc != CFR_OK) return set_err(rc, err);
     Sizes z;
     z.N = L.N; z.Hp = L.Hp; z.Qp = L.Qp; z.H0 = L.H0; z.Q0 = L.Q0; z.M = L.n_members;
+    z.terminals = L.n_terminals;
     z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
     z.engine = choose_engine(L.level_pure, L.max_actions, config ? config->flags : 0u);
     cfr::Dev d{};
@@ -265,10 +271,38 @@ namespace {
 int apply_shapes(cfr_solver* s, hipStream_t st) {
     cfr::XDev& x = s->xdev;
     const int32_t D = x.D;
-    s->reach_threads.assign(s->shape.reach_threads, s->shape.reach_threads + cfr::kShapeBuckets);
-    s->reach_npt.assign(s->shape.reach_nodes, s->shape.reach_nodes + cfr::kShapeBuckets);
-    x.reach_block = s->reach_threads.data();
-    x.reach_npt = s->reach_npt.data();
+    // top-down: per level, the shape of its decision-node count, and tiles that cover the runs
+    // of decision nodes (levels past the single-workgroup ones)
+    s->reach_threads_l.assign(D + 1, 256);
+    s->reach_npt_l.assign(D + 1, 1);
+    s->t_level_offset.assign(D + 2, 0);
+    std::vector<int32_t> tlo, thi;
+    for (int32_t l = 0; l <= D; ++l) {
+        s->t_level_offset[l] = static_cast<int32_t>(tlo.size());
+        if (l < 1 + x.fused_reach || l >= D) continue;
+        const int b = cfr::shape_bucket(s->reach_units[l]);
+        const int32_t threads = s->shape.reach_threads[b], npt = s->shape.reach_nodes[b];
+        s->reach_threads_l[l] = threads;
+        s->reach_npt_l[l] = npt;
+        const int32_t cap = threads * npt;
+        int32_t x0 = s->x_level_offset[l];
+        const int32_t x1 = s->x_level_offset[l + 1];
+        while (x0 < x1) {
+            while (x0 < x1 && (s->x_meta[x0] & 3) == 0) ++x0;
+            int32_t e = x0;
+            while (e < x1 && e - x0 < cap && (s->x_meta[e] & 3) != 0) ++e;
+            if (e > x0) {
+                tlo.push_back(x0);
+                thi.push_back(e);
+            }
+            x0 = e;
+        }
+    }
+    s->t_level_offset[D + 1] = static_cast<int32_t>(tlo.size());
+    x.reach_threads_host = s->reach_threads_l.data();
+    x.reach_npt_host = s->reach_npt_l.data();
+    x.t_level_offset_host = s->t_level_offset.data();
+    x.reach_units_host = s->reach_units.data();
     s->up_threads.assign(D + 1, 256);
     s->chunk_cap.assign(D + 1, 256);
     for (int32_t l = 0; l <= D; ++l) {
@@ -290,7 +324,8 @@ int apply_shapes(cfr_solver* s, hipStream_t st) {
     for (size_t c = 0; c < chunk_first.size(); ++c) chunk_m[c] = s->x_member_offset[chunk_first[c]];
     x.k_level_offset_host = s->x_k_level_offset.data();
     int rc;
-    if ((rc = upload(x.chunk_first, chunk_first, st)) || (rc = upload(x.chunk_m, chunk_m, st)))
+    if ((rc = upload(x.chunk_first, chunk_first, st)) || (rc = upload(x.chunk_m, chunk_m, st)) ||
+        (rc = upload(x.tile_lo, tlo, st)) || (rc = upload(x.tile_hi, thi, st)))
         return rc;
     // the host vectors go out of scope
     HIP_TRY(hipStreamSynchronize(st), "chunk table upload");
@@ -331,6 +366,11 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     s->x_h_level_offset = P.h_level_offset;
     s->x_c_level_offset = P.c_level_offset;
     s->x_member_offset = P.member_offset;
+    s->x_meta = P.meta;
+    s->reach_units.assign(P.D + 1, 0);
+    for (int32_t l = 0; l <= P.D; ++l)
+        for (int32_t v = P.level_offset[l]; v < P.level_offset[l + 1]; ++v)
+            s->reach_units[l] += (P.meta[v] & 3) != 0;
     s->x_m_level_offset.resize(P.D + 2);
     for (int32_t l = 0; l <= P.D + 1; ++l) s->x_m_level_offset[l] = P.member_offset[P.h_level_offset[l]];
     // lanes per chance node: the level's largest fan-out rounded up to a power of two, <= 64
@@ -373,6 +413,7 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     if (rc != CFR_OK) return set_err(rc, err);
     Sizes z;
     z.N = L.N; z.Hp = L.Hp; z.Qp = L.Qp; z.H0 = L.H0; z.Q0 = L.Q0; z.M = L.n_members;
+    z.terminals = L.n_terminals;
     z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
     z.engine = choose_engine(L.level_pure, L.max_actions, cfg.flags);
     cfr::ExecPlan P;
@@ -864,6 +905,7 @@ int cfr_plan_batch(const cfr_game* games, int32_t n_games, const cfr_config* con
         z.D = std::max(z.D, L.D);
         z.max_actions = std::max(z.max_actions, L.max_actions);
         terminals += L.n_terminals;
+        z.terminals += L.n_terminals;
     }
     cfr::Dev d{};
     cfr::XDev x{};
@@ -904,6 +946,7 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     plans.shrink_to_fit();
     Sizes z;
     z.N = F.N; z.Hp = F.Hp; z.Qp = F.Qp; z.Q0 = F.Q0; z.M = F.M; z.C = F.C; z.L = F.L; z.D = F.D;
+    for (int8_t m : F.meta) z.terminals += (m & 3) == 0;
     z.max_actions = max_actions;
     z.engine = ENGINE_BLOCK;
     z.canonical = false;

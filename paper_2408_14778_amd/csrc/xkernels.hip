@@ -110,17 +110,22 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
     }
 }
 
-// One level: workgroup b takes nodes lo + b * blockDim * NPT + [0, blockDim * NPT), each
-// thread NPT of them blockDim apart (every load coalesced across the wavefront).
+// One level: workgroup b takes tile t0 + b, a run of at most blockDim * NPT decision nodes
+// (terminal nodes, which need no reach, take no lanes); each thread takes NPT of them blockDim
+// apart (every load coalesced across the wavefront).
 template <int NPT>
-__global__ void __launch_bounds__(1024) k_x_reach(int32_t lo, int32_t hi, int64_t N,
+__global__ void __launch_bounds__(1024) k_x_reach(int32_t t0, int64_t N,
+                                                  const int32_t* __restrict__ tile_lo,
+                                                  const int32_t* __restrict__ tile_hi,
                                                   const int32_t* __restrict__ parent,
                                                   const int32_t* __restrict__ edge,
                                                   const int8_t* __restrict__ meta,
                                                   const float* __restrict__ prob,
                                                   float* __restrict__ reach) {
-    const int64_t first = lo + static_cast<int64_t>(xcd_tile()) * blockDim.x * NPT + threadIdx.x;
-    reach_nodes<NPT>(first, blockDim.x, hi, N, parent, edge, meta, prob, reach);
+    const int32_t t = t0 + static_cast<int32_t>(xcd_tile());
+    const int32_t lo = tile_lo[t], hi = tile_hi[t];
+    reach_nodes<NPT>(lo + static_cast<int64_t>(threadIdx.x), blockDim.x, hi, N, parent, edge, meta,
+                     prob, reach);
 }
 
 // The levels one single-workgroup kernel takes, in the order it takes them; entry i covers
@@ -765,24 +770,22 @@ void launch_up(const XDev& x, const UpArgs& a, int32_t l, hipStream_t st) {
     else launch_up_threads<KMAX, 1>(x, a, l, st);
 }
 
-void launch_reach_level(const XDev& x, int32_t lo, int32_t hi, hipStream_t st) {
-    const int64_t units = hi - lo;
-    const int b = shape_bucket(units);
-    const int threads = x.reach_block != nullptr ? x.reach_block[b] : kBlock;
-    const int npt = x.reach_npt != nullptr ? x.reach_npt[b] : 1;
-    const unsigned grid = blocks_of(units, threads * npt);
-    switch (npt) {
+void launch_reach_level(const XDev& x, int32_t l, hipStream_t st) {
+    const int32_t t0 = x.t_level_offset_host[l], nt = x.t_level_offset_host[l + 1] - t0;
+    if (nt == 0) return;
+    const int threads = x.reach_threads_host[l];
+    switch (x.reach_npt_host[l]) {
         case 2:
-            hipLaunchKernelGGL(k_x_reach<2>, dim3(grid), dim3(threads), 0, st, lo, hi, x.N, x.parent,
-                               x.edge, x.meta, x.prob, x.reach);
+            hipLaunchKernelGGL(k_x_reach<2>, dim3(nt), dim3(threads), 0, st, t0, x.N, x.tile_lo,
+                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach);
             break;
         case 4:
-            hipLaunchKernelGGL(k_x_reach<4>, dim3(grid), dim3(threads), 0, st, lo, hi, x.N, x.parent,
-                               x.edge, x.meta, x.prob, x.reach);
+            hipLaunchKernelGGL(k_x_reach<4>, dim3(nt), dim3(threads), 0, st, t0, x.N, x.tile_lo,
+                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach);
             break;
         default:
-            hipLaunchKernelGGL(k_x_reach<1>, dim3(grid), dim3(threads), 0, st, lo, hi, x.N, x.parent,
-                               x.edge, x.meta, x.prob, x.reach);
+            hipLaunchKernelGGL(k_x_reach<1>, dim3(nt), dim3(threads), 0, st, t0, x.N, x.tile_lo,
+                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach);
             break;
     }
 }
@@ -828,8 +831,9 @@ void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st, 
         post(XK_REACH);
     }
     for (int32_t l = 1 + fr; l < x.D; ++l) {
-        pre(XK_REACH, l, lo[l + 1] - lo[l]);
-        launch_reach_level(x, lo[l], lo[l + 1], st);
+        if (x.t_level_offset_host[l + 1] == x.t_level_offset_host[l]) continue;
+        pre(XK_REACH, l, x.reach_units_host[l]);
+        launch_reach_level(x, l, st);
         post(XK_REACH);
     }
     // bottom-up: a launch per deep level, then the shallow levels in one workgroup

@@ -25,9 +25,12 @@ constexpr int kFuseThreads = 1024;
 struct XDev {
     int64_t N, Hp, Qp, Q0, M, L, C;
     int32_t D, max_actions;
-    // launch shapes (host): top-down threads and nodes per thread per bucket of level size
-    const int32_t* reach_block;  // kShapeBuckets entries (nullptr: 256)
-    const int32_t* reach_npt;    // kShapeBuckets entries (nullptr: 1)
+    // top-down launches (host), per level: threads per workgroup, nodes per thread, and the
+    // level's tiles t_level_offset[l] .. t_level_offset[l + 1] - 1 (runs of decision nodes)
+    const int32_t* reach_threads_host;  // D + 1
+    const int32_t* reach_npt_host;      // D + 1
+    const int32_t* t_level_offset_host; // D + 2
+    const int64_t* reach_units_host;    // D + 1: decision nodes of each level
     // bottom-up shapes (host), per level: threads per workgroup and members per chunk
     // (threads x members per thread)
     const int32_t* up_threads_host;      // D + 1
@@ -63,6 +66,8 @@ struct XDev {
     int32_t* chance_nodes;
     int32_t* chance_base;  // index into prob of the chance node's action 0
     int32_t* chance_k;
+    int32_t* tile_lo;      // top-down tiles: nodes tile_lo[t] .. tile_hi[t] - 1, all decision
+    int32_t* tile_hi;      // nodes of one level (capacity: decision nodes)
     int32_t* chunk_first;  // chunks + 1 (capacity Hp + D + 2)
     int32_t* chunk_m;      // first member of each chunk, chunks + 1
     int32_t* q_input;
