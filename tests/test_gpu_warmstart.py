@@ -165,3 +165,26 @@ def test_warm_start_sets_scaled_regrets():
     np.testing.assert_allclose(R, expect, rtol=1e-5, atol=1e-7)
     sig = b.current_strategy()
     np.testing.assert_allclose(np.where(np.repeat(m, k) > 0, sig, pr), pr, atol=1e-5)
+
+
+def test_trained_network_reduces_iterations_to_target():
+    """The committed network (trained by warmstart_pipeline on seeds 10000-29999) against
+    zero-start CFR+ on 64 held-out subgames: iterations until each game's exploitability first
+    reaches 1e-3 (best-response check every 10 iterations)."""
+    import json
+    import os
+    from paper_2408_14778_amd import warmstart as ws
+    from paper_2408_14778_amd import warmstart_pipeline as wp
+    if not os.path.exists(wp.WEIGHTS_PATH):
+        pytest.skip("no trained weights (run paper_2408_14778_amd.warmstart_pipeline)")
+    with open(os.path.splitext(wp.WEIGHTS_PATH)[0] + ".json") as f:
+        weight = json.load(f)["weight"]
+    net = ws.WarmStartNet(max_batch=65536)
+    net.set_params(np.load(wp.WEIGHTS_PATH))
+    gl = [games.subgame(s) for s in range(100, 164)]
+    res = wp.evaluate(gl, net, weight, max_iters=8000)
+    paired = res["paired"]
+    assert paired["games"] >= 60
+    assert paired["mean_iterations_warm"] < 0.95 * paired["mean_iterations_plain"], paired
+    assert paired["geomean_iteration_ratio"] < 0.95, paired
+    assert res["warm"]["first_expl_warm_max"] < res["warm"]["first_expl_zero_max"]
