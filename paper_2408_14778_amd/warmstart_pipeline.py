@@ -180,6 +180,39 @@ def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: i
     return out
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16
+
+
+def mlp_throughput(infer, trainer, rows: int = 65536, batch: int = 4096, reps: int = 20) -> dict:
+    """Achieved TFLOP/s of the network's forward pass (`rows` infosets) and of one training step
+    (`batch` infosets: forward, backward, Adam), hipEvent-timed. Multiply-adds per row: forward
+    F H + H H + H A; training step 2 F H + 3 H H + 3 H A (no input gradient)."""
+    import torch
+    F, H, A = infer.shape
+    dev = infer.device
+    x = torch.randn(rows, F, device=dev).to(torch.bfloat16)
+    xb = x[:batch].contiguous()
+    t = torch.full((batch, A), 1.0 / A, device=dev)
+    m = torch.ones(batch, A, device=dev)
+    p0 = trainer.params()
+    out = {}
+    for name, fn, macs in (("forward", lambda: infer.forward(x), rows * (F * H + H * H + H * A)),
+                           ("train_step", lambda: trainer.train_step(xb, t, m, 0.0),
+                            batch * (2 * F * H + 3 * H * H + 3 * H * A))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = 2.0 * macs / (ms * 1e-3) / 1e12
+        out[name] = {"ms": ms, "tflops": tf, "frac_of_bf16_peak": tf / MFMA_BF16_PEAK_TFLOPS}
+    trainer.set_params(p0)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-games", type=int, default=20000)
@@ -255,6 +288,8 @@ def main() -> int:
     gl = pending.get()
     pool.close()
     res = evaluate(gl, infer, weight)
+    res["mlp"] = mlp_throughput(infer, net)
+    log(f"network throughput: {json.dumps(res['mlp'])}")
     res.update({"train_games": args.train_games, "solve_iters": args.solve_iters,
                 "samples": int(len(data["desc"])), "losses": losses, "weight": weight,
                 "eval_games": args.eval_games, "eval_seeds": [100, 99 + args.eval_games],

@@ -26,7 +26,7 @@ from oracle import br, cfr  # noqa: E402
 from oracle.tree import Tree  # noqa: E402
 
 ITERS = 1000
-SEEDS = [1, 2, 3, 4]
+SEEDS = list(range(1, 17))
 
 
 def run(args):
