@@ -32,23 +32,29 @@ inline unsigned blocks_for(int64_t n, int t) { return static_cast<unsigned>((n +
 // element e of lane l at row 8 * (e / 4) + 4 * (l / 32) + e % 4, column l % 32.
 // Epilogue: + bias[j] (if bias), then mode 0: store FP32; 1: relu, store BF16; 2: multiply by
 // (gate[i, j] > 0) (the ReLU derivative of the layer's output), store BF16.
+// Split K (weight gradients, where K is the batch): workgroup z of gridDim.z takes k in
+// [z kps, (z + 1) kps) and stores its FP32 partial tile to part[z][M][N]; k_sum_splits adds the
+// partials in z order (deterministic) and applies mode 0.
 __global__ void __launch_bounds__(64) k_gemm(int M, int N, int K, const __bf16* __restrict__ A,
                                              int64_t a_i, int64_t a_k,
                                              const __bf16* __restrict__ B, int64_t b_k,
                                              int64_t b_j, const float* __restrict__ bias, int mode,
                                              const __bf16* __restrict__ gate, float* __restrict__ Cf,
-                                             __bf16* __restrict__ Cb, int64_t ldc) {
+                                             __bf16* __restrict__ Cb, int64_t ldc, int kps,
+                                             float* __restrict__ part) {
     const int lane = threadIdx.x;
     const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
     const int r = lane & 31, half = lane >> 5;
     const int ai = m0 + r, bj = n0 + r;
+    const int kbeg = blockIdx.z * kps;
+    const int kend = min(K, kbeg + kps);
     floatx16 acc = {};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = kbeg; k0 < kend; k0 += 16) {
         bf16x8 fa, fb;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = k0 + 8 * half + j;
-            const bool kin = k < K;
+            const bool kin = k < kend;
             fa[j] = (kin && ai < M) ? A[ai * a_i + k * a_k] : static_cast<__bf16>(0.0f);
             fb[j] = (kin && bj < N) ? B[k * b_k + bj * b_j] : static_cast<__bf16>(0.0f);
         }
@@ -59,6 +65,10 @@ __global__ void __launch_bounds__(64) k_gemm(int M, int N, int K, const __bf16* 
         const int i = m0 + 8 * (e >> 2) + 4 * half + (e & 3);
         const int j = n0 + r;
         if (i >= M || j >= N) continue;
+        if (gridDim.z > 1) {
+            part[(static_cast<int64_t>(blockIdx.z) * M + i) * N + j] = acc[e];
+            continue;
+        }
         float v = acc[e];
         if (bias != nullptr) v += bias[j];
         const int64_t o = static_cast<int64_t>(i) * ldc + j;
@@ -110,13 +120,35 @@ __global__ void k_softmax_xent(int B, int A, const float* __restrict__ Z,
     if ((threadIdx.x & 63) == 0 && loss != nullptr) atomicAdd(loss, l);
 }
 
-// Column sums of a BF16 [rows x cols] matrix into FP32 (bias gradients): one thread per column.
-__global__ void k_colsum(int rows, int cols, const __bf16* __restrict__ G, float* __restrict__ out) {
-    const int64_t j = gid();
-    if (j >= cols) return;
+// Sums split partials part[z][M][N] over z in order into C (row stride ldc), one thread per
+// element.
+__global__ void k_sum_splits(int M, int N, int splits, const float* __restrict__ part,
+                             float* __restrict__ C, int64_t ldc) {
+    const int64_t t = gid();
+    if (t >= static_cast<int64_t>(M) * N) return;
+    const int64_t i = t / N, j = t % N;
     float s = 0.0f;
-    for (int i = 0; i < rows; ++i) s += static_cast<float>(G[static_cast<int64_t>(i) * cols + j]);
-    out[j] = s;
+    for (int z = 0; z < splits; ++z) s += part[(static_cast<int64_t>(z) * M + i) * N + j];
+    C[i * ldc + j] = s;
+}
+
+// Column sums of a BF16 [rows x cols] matrix (bias gradients), split over rows: workgroup
+// (x, y) takes 64 columns (one per lane, coalesced rows) and rows [y rps, (y + 1) rps), with
+// four interleaved accumulators combined in a fixed order, into part[y][cols].
+__global__ void __launch_bounds__(64) k_colsum_part(int rows, int cols, int rps,
+                                                    const __bf16* __restrict__ G,
+                                                    float* __restrict__ part) {
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= cols) return;
+    const int r0 = blockIdx.y * rps, r1 = min(rows, r0 + rps);
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int i = r0;
+    for (; i + 4 <= r1; i += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] += static_cast<float>(G[static_cast<int64_t>(i + u) * cols + j]);
+    }
+    for (; i < r1; ++i) s[0] += static_cast<float>(G[static_cast<int64_t>(i) * cols + j]);
+    part[static_cast<int64_t>(blockIdx.y) * cols + j] = (s[0] + s[1]) + (s[2] + s[3]);
 }
 
 // Adam on FP32 master parameters; refreshes the BF16 copy used by the GEMMs.
@@ -245,11 +277,21 @@ __global__ void k_warm_start(int64_t Hp, const int32_t* __restrict__ q_offset,
 
 void launch_gemm(int M, int N, int K, const void* A, int64_t a_i, int64_t a_k, const void* B,
                  int64_t b_k, int64_t b_j, const float* bias, int mode, const void* gate, float* Cf,
-                 void* Cb, int64_t ldc, hipStream_t st) {
-    dim3 grid((N + 31) / 32, (M + 31) / 32);
+                 void* Cb, int64_t ldc, hipStream_t st, float* part) {
+    // split K only for FP32 outputs without bias (weight gradients) when K is long
+    int splits = 1;
+    if (part != nullptr && mode == 0 && bias == nullptr && K >= 2 * kSplitK)
+        splits = min(kMaxSplits, K / kSplitK);
+    const int kps = ((K + splits - 1) / splits + 15) / 16 * 16;
+    splits = (K + kps - 1) / kps;
+    dim3 grid((N + 31) / 32, (M + 31) / 32, splits);
     hipLaunchKernelGGL(k_gemm, grid, dim3(64), 0, st, M, N, K, static_cast<const __bf16*>(A), a_i,
                        a_k, static_cast<const __bf16*>(B), b_k, b_j, bias, mode,
-                       static_cast<const __bf16*>(gate), Cf, static_cast<__bf16*>(Cb), ldc);
+                       static_cast<const __bf16*>(gate), Cf, static_cast<__bf16*>(Cb), ldc, kps,
+                       part);
+    if (splits > 1)
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for(int64_t{M} * N, 256)), dim3(256), 0, st, M,
+                           N, splits, part, Cf, ldc);
 }
 
 void launch_softmax_xent(int B, int A, const float* Z, const float* target, const float* mask,
@@ -258,9 +300,13 @@ void launch_softmax_xent(int B, int A, const float* Z, const float* target, cons
                        mask, static_cast<__bf16*>(dZ), loss);
 }
 
-void launch_colsum(int rows, int cols, const void* G, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_colsum, dim3(blocks_for(cols, 256)), dim3(256), 0, st, rows, cols,
-                       static_cast<const __bf16*>(G), out);
+void launch_colsum(int rows, int cols, const void* G, float* out, hipStream_t st, float* part) {
+    const int splits = max(1, min(kMaxSplits, rows / kSplitK));
+    const int rps = (rows + splits - 1) / splits;
+    hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, splits), dim3(64), 0, st, rows, cols,
+                       rps, static_cast<const __bf16*>(G), part);
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for(cols, 256)), dim3(256), 0, st, 1, cols, splits,
+                       part, out, int64_t{cols});
 }
 
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, void* wb, float lr,

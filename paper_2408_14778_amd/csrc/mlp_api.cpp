@@ -1,6 +1,7 @@
 // C ABI of the warm-start network (include/cfr_warmstart.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -22,6 +23,7 @@ struct cfr_mlp {
     // activations
     __bf16 *A1, *A2, *dZ3, *dZ2, *dZ1;
     float *Z3, *loss;
+    float* part;  // split-K partials: kMaxSplits * max(F, H) * max(H, A) floats
     int64_t step;
 };
 
@@ -62,6 +64,8 @@ size_t layout(cfr_mlp& n, void* base, int32_t F, int32_t H, int32_t A, int32_t m
     n.dZ3 = static_cast<__bf16*>(take(int64_t{maxB} * A * 2));
     n.Z3 = static_cast<float*>(take(int64_t{maxB} * A * 4));
     n.loss = static_cast<float*>(take(4));
+    n.part = static_cast<float*>(
+        take(int64_t{cfr::kMaxSplits} * std::max(F, H) * std::max(H, A) * 4));
     return (off + 255) & ~size_t{255};
 }
 
@@ -173,20 +177,20 @@ int cfr_mlp_train_step(cfr_mlp* n, const void* x, const float* target, const flo
     cfr::launch_softmax_xent(B, A, n->Z3, target, mask, n->dZ3, n->loss, n->st);
     // layer 3
     cfr::launch_gemm(H, A, B, n->A2, 1, H, n->dZ3, A, 1, nullptr, 0, nullptr, n->g + o[4], nullptr,
-                     A, n->st);
-    cfr::launch_colsum(B, A, n->dZ3, n->g + o[5], n->st);
+                     A, n->st, n->part);
+    cfr::launch_colsum(B, A, n->dZ3, n->g + o[5], n->st, n->part);
     cfr::launch_gemm(B, H, A, n->dZ3, A, 1, n->wb + o[4], 1, A, nullptr, 2, n->A2, nullptr, n->dZ2,
                      H, n->st);
     // layer 2
     cfr::launch_gemm(H, H, B, n->A1, 1, H, n->dZ2, H, 1, nullptr, 0, nullptr, n->g + o[2], nullptr,
-                     H, n->st);
-    cfr::launch_colsum(B, H, n->dZ2, n->g + o[3], n->st);
+                     H, n->st, n->part);
+    cfr::launch_colsum(B, H, n->dZ2, n->g + o[3], n->st, n->part);
     cfr::launch_gemm(B, H, H, n->dZ2, H, 1, n->wb + o[2], 1, H, nullptr, 2, n->A1, nullptr, n->dZ1,
                      H, n->st);
     // layer 1
     cfr::launch_gemm(F, H, B, x, 1, F, n->dZ1, H, 1, nullptr, 0, nullptr, n->g + o[0], nullptr, H,
-                     n->st);
-    cfr::launch_colsum(B, H, n->dZ1, n->g + o[1], n->st);
+                     n->st, n->part);
+    cfr::launch_colsum(B, H, n->dZ1, n->g + o[1], n->st, n->part);
     // Adam
     n->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;
