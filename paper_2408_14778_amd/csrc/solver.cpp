@@ -281,7 +281,9 @@ int apply_shapes(cfr_solver* s, hipStream_t st) {
         s->t_level_offset[l] = static_cast<int32_t>(tlo.size());
         if (l < 1 + x.fused_reach || l >= D) continue;
         const int b = cfr::shape_bucket(s->reach_units[l]);
-        const int32_t threads = s->shape.reach_threads[b], npt = s->shape.reach_nodes[b];
+        const bool path = l <= x.path_reach;  // one node per lane, fixed workgroup size
+        const int32_t threads = path ? cfr::kPathThreads : s->shape.reach_threads[b];
+        const int32_t npt = path ? 1 : s->shape.reach_nodes[b];
         s->reach_threads_l[l] = threads;
         s->reach_npt_l[l] = npt;
         const int32_t cap = threads * npt;
@@ -389,6 +391,7 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     x.c_level_offset_host = s->x_c_level_offset.data();
     x.chance_glog_host = s->chance_glog.data();
     x.fused_reach = cfr::fusable_reach_levels(x.level_offset_host, P.D);
+    x.path_reach = cfr::path_reach_levels(s->reach_units.data(), x.fused_reach, P.D);
     x.fused_up = cfr::fusable_up_levels(x.m_level_offset_host, x.h_level_offset_host,
                                         x.c_level_offset_host, x.chance_glog_host, P.D,
                                         x.max_actions);

@@ -128,6 +128,43 @@ __global__ void __launch_bounds__(1024) k_x_reach(int32_t t0, int64_t N,
                      prob, reach);
 }
 
+// Several small levels in one launch without a barrier between them: the node of each lane
+// (tiles as in k_x_reach, one node per lane) walks up through its ancestors to the first stored
+// level (nodes below `stop`), at most kPathDepth steps, collecting the edge probabilities and
+// actors, then multiplies them onto the ancestor's reach from the top down, in the order the
+// level-by-level pass uses.
+__global__ void __launch_bounds__(256) k_x_reach_path(int32_t t0, int32_t stop, int64_t N,
+                                                      const int32_t* __restrict__ tile_lo,
+                                                      const int32_t* __restrict__ tile_hi,
+                                                      const int32_t* __restrict__ parent,
+                                                      const int32_t* __restrict__ edge,
+                                                      const int8_t* __restrict__ meta,
+                                                      const float* __restrict__ prob,
+                                                      float* __restrict__ reach) {
+    const int32_t t = t0 + static_cast<int32_t>(xcd_tile());
+    const int32_t x = tile_lo[t] + static_cast<int32_t>(threadIdx.x);
+    if (x >= tile_hi[t] || (meta[x] & 3) == 0) return;
+    float s[kPathDepth];
+    int actor[kPathDepth];
+    int n = 0;
+    int32_t y = x;
+    while (y >= stop && n < kPathDepth) {
+        actor[n] = (meta[y] >> 2) & 3;
+        s[n] = prob[edge[y]];
+        y = parent[y];
+        ++n;
+    }
+    float r1 = reach[y], r2 = reach[N + y], rc = reach[2 * N + y];
+    for (int i = n - 1; i >= 0; --i) {
+        if (actor[i] == 2) r1 *= s[i];
+        else if (actor[i] == 3) r2 *= s[i];
+        else rc *= s[i];
+    }
+    reach[x] = r1;
+    reach[N + x] = r2;
+    reach[2 * N + x] = rc;
+}
+
 // The levels one single-workgroup kernel takes, in the order it takes them; entry i covers
 // nodes (top-down) or chunks (bottom-up) lo[i] .. hi[i] - 1 and chance nodes clo[i] .. chi[i] - 1.
 struct LevelTable {
@@ -799,6 +836,14 @@ int32_t fusable_reach_levels(const int32_t* level_offset, int32_t D) {
     return k;
 }
 
+int32_t path_reach_levels(const int64_t* units, int32_t fused, int32_t D) {
+    // levels fused + 1 .. l with at most kPathNodes decision nodes each and at most kPathDepth
+    // levels below the last stored one
+    int32_t l = fused;
+    while (l + 1 < D && l + 1 - fused <= kPathDepth && units[l + 1] <= kPathNodes) ++l;
+    return l;
+}
+
 int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_offset,
                           const int32_t* c_level_offset, const int32_t* chance_glog, int32_t D,
                           int32_t max_actions) {
@@ -830,7 +875,19 @@ void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st, 
                            x.edge, x.meta, x.prob, x.reach);
         post(XK_REACH);
     }
-    for (int32_t l = 1 + fr; l < x.D; ++l) {
+    const int32_t fp = x.path_reach;
+    if (fp > fr) {
+        const int32_t t0 = x.t_level_offset_host[1 + fr], nt = x.t_level_offset_host[fp + 1] - t0;
+        if (nt > 0) {
+            int64_t units = 0;
+            for (int32_t l = 1 + fr; l <= fp; ++l) units += x.reach_units_host[l];
+            pre(XK_REACH, -2, units);
+            hipLaunchKernelGGL(k_x_reach_path, dim3(nt), dim3(kPathThreads), 0, st, t0, lo[1 + fr],
+                               x.N, x.tile_lo, x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach);
+            post(XK_REACH);
+        }
+    }
+    for (int32_t l = 1 + (fp > fr ? fp : fr); l < x.D; ++l) {
         if (x.t_level_offset_host[l + 1] == x.t_level_offset_host[l]) continue;
         pre(XK_REACH, l, x.reach_units_host[l]);
         launch_reach_level(x, l, st);

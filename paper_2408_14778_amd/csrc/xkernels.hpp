@@ -21,6 +21,11 @@ int shape_bucket(int64_t units);
 // Levels handled together by the single-workgroup kernels of the first levels.
 constexpr int kFuseMax = 8;
 constexpr int kFuseThreads = 1024;
+// Top-down levels after those computed in one launch by walking up to the last stored level:
+// at most kPathDepth levels of at most kPathNodes decision nodes; tiles of kPathThreads nodes.
+constexpr int kPathDepth = 5;
+constexpr int64_t kPathNodes = 200000;
+constexpr int kPathThreads = 256;
 
 struct XDev {
     int64_t N, Hp, Qp, Q0, M, L, C;
@@ -45,6 +50,9 @@ struct XDev {
     // the first levels run in one workgroup: top-down levels 1 .. fused_reach and
     // bottom-up levels fused_up - 1 .. 0 (0: none)
     int32_t fused_reach, fused_up;
+    // top-down levels fused_reach + 1 .. path_reach run in one path launch (path_reach <=
+    // fused_reach: none)
+    int32_t path_reach;
     // plan arrays (exec order)
     int32_t* parent;
     int32_t* edge;
@@ -86,6 +94,7 @@ struct XDev {
 
 // How many first levels the single-workgroup kernels take (from the plan's level tables).
 int32_t fusable_reach_levels(const int32_t* level_offset, int32_t D);
+int32_t path_reach_levels(const int64_t* decision_nodes_per_level, int32_t fused, int32_t D);
 int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_offset,
                           const int32_t* c_level_offset, const int32_t* chance_glog, int32_t D,
                           int32_t max_actions);

@@ -166,6 +166,9 @@ def test_best_response_on_the_gpu_average(name, engine):
 
 @pytest.mark.parametrize("engine", ENGINES)
 def test_graph_replay_matches_direct_launches(engine):
+    """The block engine sums in a fixed order: graph replays and direct launches agree bit for
+    bit. The node engine accumulates with float atomics, whose order varies between runs, so
+    over 21 iterations the two agree to fp32 reordering only."""
     g = games.leduc_like(3, 2, deal="sequential")
     a = _solver(g, "cfr+", graph=True, engine=engine)
     b = _solver(g, "cfr+", graph=False, engine=engine)
@@ -175,7 +178,10 @@ def test_graph_replay_matches_direct_launches(engine):
         Ta, Ra, Sa = a.get_state()
         Tb, Rb, Sb = b.get_state()
         assert Ta == Tb
-        assert _rel(Ra, Rb) <= 1e-6 and _rel(Sa, Sb) <= 1e-6
+        if engine == "node":
+            assert _rel(Ra, Rb) <= 1e-5 and _rel(Sa, Sb) <= 1e-5
+        else:
+            assert np.array_equal(Ra, Rb) and np.array_equal(Sa, Sb)
 
 
 def test_average_strategy_to_device():
