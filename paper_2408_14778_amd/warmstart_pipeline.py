@@ -99,32 +99,53 @@ def train(net, data: dict, epochs: int, batch: int, lr: float, seed: int = 0) ->
 
 
 def run_to_target(solver, target: float, check_every: int, max_iters: int, done: int = 0,
-                  t0: float = None):
+                  t0: float = None, game_list=None, variant: str = "cfr+",
+                  compact: float = 0.05):
     """Iterate with best-response checks every `check_every` iterations. A game is solved at
     the first check where its exploitability is at most `target` (a batched solver keeps that
-    game's average strategy from then on); returns, per game, the iteration and the wall time
-    (from t0) at which it was solved (-1 / inf if it never was) and the exploitability then."""
+    game's average strategy from then on). With `game_list`, the batch is compacted: once the
+    unsolved games hold at most `compact` of the current forest's nodes, the forest is rebuilt
+    from them alone and their state (T, R, S) carried over, so the last, slow games do not keep
+    the whole batch iterating. Returns, per game, the iteration and the wall time (from t0) at
+    which it was solved (-1 / inf if it never was), the exploitability then, and the solver
+    left at the end (the caller closes it; `solver` itself is closed if it was replaced)."""
     import torch
+    from .solver import BatchSolver
     t0 = time.perf_counter() if t0 is None else t0
     n = solver.n_games
     solved_it = np.full(n, -1, dtype=np.int64)
     solved_s = np.full(n, np.inf)
     solved_e = np.full(n, np.nan)
+    idx = np.arange(n)  # original index of each game of the current solver
+    sizes = None if game_list is None else np.array([g.n_nodes for g in game_list])
     it = done
     while it < max_iters:
         solver.iterate(check_every)
         it += check_every
         e = solver.exploitability()["expl"]
         now = time.perf_counter() - t0
-        new = (solved_it < 0) & (e <= target)
-        solved_it[new], solved_s[new], solved_e[new] = it, now, e[new]
-        if np.all(solved_it >= 0):
+        new = (solved_it[idx] < 0) & (e <= target)
+        solved_it[idx[new]], solved_s[idx[new]], solved_e[idx[new]] = it, now, e[new]
+        active = solved_it[idx] < 0
+        if not active.any():
             break
         if (it // check_every) % 50 == 0:
-            log(f"  iteration {it}: {int(np.sum(solved_it >= 0))}/{n} solved, "
-                f"max exploitability {float(np.max(e)):.3e}")
+            log(f"  iteration {it}: {n - int(active.sum())}/{n} solved, "
+                f"max exploitability {float(np.max(e[active])):.3e}")
+        if sizes is not None and active.sum() < len(idx) and \
+                sizes[idx[active]].sum() <= compact * sizes[idx].sum():
+            T, R, S = solver.get_state()
+            keep = np.flatnonzero(active)
+            Rs, Ss = solver.split(R), solver.split(S)
+            smaller = BatchSolver([game_list[i] for i in idx[keep]], variant)
+            smaller.set_state(T, np.concatenate([Rs[k] for k in keep]),
+                              np.concatenate([Ss[k] for k in keep]))
+            solver.close()
+            solver, idx = smaller, idx[keep]
+            log(f"  iteration {it}: continuing with the {len(idx)} unsolved games "
+                f"({int(sizes[idx].sum())} nodes)")
     torch.cuda.synchronize()
-    return solved_it, solved_s, solved_e
+    return solved_it, solved_s, solved_e, solver
 
 
 def _arm(solved_it, solved_s) -> dict:
@@ -143,9 +164,10 @@ def _arm(solved_it, solved_s) -> dict:
 
 
 def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: int = 10,
-             max_iters: int = 20000) -> dict:
-    """Plain zero-start CFR+ against the warm start on the same batch: wall time until every
-    game is solved (the batch's time to the target), and per game the iterations to it."""
+             max_iters: int = 20000, compact: float = 0.05) -> dict:
+    """Plain zero-start CFR+ against the warm start on the same batch, both with the same
+    compaction rule: wall time until every game is solved (the batch's time to the target), and
+    per game the iterations to it."""
     import torch
     from . import warmstart as ws
     from .solver import BatchSolver
@@ -153,7 +175,8 @@ def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: i
     b = BatchSolver(game_list, "cfr+")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    p_it, p_s, _ = run_to_target(b, target, check_every, max_iters, t0=t0)
+    p_it, p_s, _, b = run_to_target(b, target, check_every, max_iters, t0=t0,
+                                    game_list=game_list, compact=compact)
     out["plain"] = _arm(p_it, p_s)
     b.close()
     del b
@@ -162,7 +185,8 @@ def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: i
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = ws.warm_start(b, net, game_list, weight)
-    w_it, w_s, _ = run_to_target(b, target, check_every, max_iters, done=2, t0=t0)
+    w_it, w_s, _, b = run_to_target(b, target, check_every, max_iters, done=2, t0=t0,
+                                    game_list=game_list, compact=compact)
     out["warm"] = _arm(w_it, w_s)
     out["warm"].update({"warm_start_seconds": info["seconds"],
                         "fallback_games": info["fallback_games"],
@@ -213,6 +237,28 @@ def mlp_throughput(infer, trainer, rows: int = 65536, batch: int = 4096, reps: i
     return out
 
 
+def eval_only(args) -> int:
+    pool = Pool(args.workers)  # forked before this process touches the GPU
+    pending = pool.map_async(_subgame, list(range(100, 100 + args.eval_games)), chunksize=4)
+    import torch
+    from . import warmstart as ws
+    torch.cuda.set_device(0)
+    with open(os.path.splitext(args.out_weights)[0] + ".json") as f:
+        weight = json.load(f)["weight"]
+    net = ws.WarmStartNet(max_batch=65536)
+    net.set_params(np.load(args.out_weights))
+    gl = pending.get()
+    pool.close()
+    res = evaluate(gl, net, weight)
+    res.update({"weight": weight, "eval_games": args.eval_games,
+                "eval_seeds": [100, 99 + args.eval_games]})
+    log(json.dumps(res))
+    if args.out_json:
+        with open(args.out_json, "w") as f:
+            json.dump(res, f, indent=1)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-games", type=int, default=20000)
@@ -228,7 +274,12 @@ def main() -> int:
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out-weights", default=WEIGHTS_PATH)
     ap.add_argument("--out-json", default=None)
+    ap.add_argument("--eval-only", action="store_true",
+                    help="evaluate the stored network (weights and chosen weight next to "
+                         "--out-weights) on the held-out games, without training")
     args = ap.parse_args()
+    if args.eval_only:
+        return eval_only(args)
     sys.path.insert(0, ROOT)
     # the worker processes are forked before this process touches the GPU
     pool = Pool(args.workers)
