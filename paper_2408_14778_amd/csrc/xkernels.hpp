@@ -19,7 +19,7 @@ constexpr int kShapeBuckets = 32;
 int shape_bucket(int64_t units);
 
 // Levels handled together by the single-workgroup kernels of the first levels.
-constexpr int kFuseMax = 8;
+constexpr int kFuseMax = 16;
 constexpr int kFuseThreads = 1024;
 // Top-down levels after those computed in one launch by walking up to the last stored level:
 // at most kPathDepth levels of at most kPathNodes decision nodes; tiles of kPathThreads nodes.
