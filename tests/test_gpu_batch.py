@@ -187,3 +187,22 @@ def test_full_batch_exploitability_matches_single(full_batch):
         es = s.exploitability()["expl"]
         s.close()
         assert abs(e[int(i)] - es) <= 1e-5 * max(1.0, abs(es)), int(i)
+
+
+def test_compaction_carries_the_state_over():
+    """Dropping solved subgames from the forest (rebuilt from the unsolved ones with their T, R,
+    S) continues each game's own trajectory: the iteration at which every game first reaches
+    the target matches the uncompacted run (chance-node sums may be reduced in another lane
+    order in the smaller forest, so a crossing may move by a check)."""
+    from paper_2408_14778_amd import BatchSolver
+    from paper_2408_14778_amd import warmstart_pipeline as wp
+    gl = [games.subgame(s) for s in range(100, 124)]
+    ref = BatchSolver(gl, "cfr+")
+    it0, _, _, ref = wp.run_to_target(ref, 3e-3, 10, 6000)
+    ref.close()
+    b = BatchSolver(gl, "cfr+")
+    it1, _, _, b = wp.run_to_target(b, 3e-3, 10, 6000, game_list=gl, compact=0.5)
+    assert b.n_games < len(gl)  # the forest was rebuilt at least once
+    b.close()
+    assert np.all(it0 > 0) and np.all(it1 > 0)
+    assert np.mean(it0 == it1) >= 0.9 and np.max(np.abs(it0 - it1)) <= 20, (it0, it1)
