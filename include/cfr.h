@@ -125,13 +125,16 @@ const char* cfr_kernel_name(int32_t kind);
 /* Like cfr_iterate_timed but per launch: after n iterations, for each of the *n_launches
  * launches of one iteration (in launch order, up to max_launches are written), the summed
  * event time over the n iterations, its kernel kind (cfr_kernel_name), the tree level it
- * processes (-1 if none) and its number of work items. Synchronises. */
+ * processes (-1: the single-workgroup launch of the first levels; -2: the launch that takes
+ * several small top-down levels at once) and its number of work items. Synchronises. */
 int cfr_iterate_profile(cfr_solver* s, int32_t n, double* launch_ms, int32_t* launch_kind,
                         int32_t* launch_level, int64_t* launch_units, int32_t max_launches,
                         int32_t* n_launches);
 
 /* Launch shapes of the public-block engine, per bucket b = min(floor(log2 u), 31) of a
- * launch's work items u (top-down: the level's nodes; bottom-up: the level's infoset members).
+ * launch's work items u (top-down: the level's decision nodes; bottom-up: the level's infoset
+ * members). The single-workgroup launches of the first levels and the multi-level top-down
+ * launch have fixed shapes.
  * A top-down launch uses reach_threads[b] threads per workgroup (a multiple of 64 in
  * [64, 1024]), each thread taking reach_nodes[b] nodes (1, 2 or 4). The bottom-up launch packs
  * whole infosets into chunks of at most up_threads[b] * up_members[b] members, one workgroup of
