@@ -228,6 +228,14 @@ int capture(cfr_solver* s) {
     return CFR_OK;
 }
 
+// Releases a solver that failed part-way through its build (graph objects included).
+void discard(cfr_solver* s) {
+    if (s == nullptr) return;
+    if (s->exec != nullptr) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph != nullptr) (void)hipGraphDestroy(s->graph);
+    delete s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -470,30 +478,30 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         (rc = upload(d.member_offset, L.member_offset, st)) ||
         (rc = upload(d.members, L.members, st)) || (rc = upload(d.q_input, L.q_input, st)) ||
         (rc = upload(d.payoff, L.payoff, st)) || (rc = upload(d.prob, prob_tail, st))) {
-        delete s;
+        discard(s);
         return rc;
     }
     if (s->engine == ENGINE_BLOCK) {
         cfr_default_launch_shape(&s->shape);
         if ((rc = upload_plan(s, P, st))) {
-            delete s;
+            discard(s);
             return rc;
         }
     }
     cfr::launch_reset(d, st, s->engine == ENGINE_NODE);
     if (s->engine == ENGINE_BLOCK) cfr::launch_x_reset(s->xdev, st);
     if ((rc = check_hip("reset")) != CFR_OK) {
-        delete s;
+        discard(s);
         return rc;
     }
     // host vectors are released when L and P go out of scope: wait for the copies first
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-        delete s;
+        discard(s);
         return hip_err(e, "build synchronise");
     }
     if (s->use_graph && (rc = capture(s)) != CFR_OK) {
-        delete s;
+        discard(s);
         return rc;
     }
     *out = s;
@@ -980,22 +988,22 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     std::copy(F.chance_prob.begin(), F.chance_prob.end(), prob_tail.begin() + F.Qp);
     cfr_default_launch_shape(&s->shape);
     if ((rc = upload_plan(s, F, st)) || (rc = upload(d.prob, prob_tail, st))) {
-        delete s;
+        discard(s);
         return rc;
     }
     cfr::launch_reset(d, st, false);
     cfr::launch_x_reset(s->xdev, st);
     if ((rc = check_hip("reset")) != CFR_OK) {
-        delete s;
+        discard(s);
         return rc;
     }
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-        delete s;
+        discard(s);
         return hip_err(e, "build synchronise");
     }
     if (s->use_graph && (rc = capture(s)) != CFR_OK) {
-        delete s;
+        discard(s);
         return rc;
     }
     *out = s;
