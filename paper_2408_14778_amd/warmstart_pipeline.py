@@ -263,9 +263,9 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-games", type=int, default=20000)
     ap.add_argument("--batch-games", type=int, default=512)
-    ap.add_argument("--solve-iters", type=int, default=1000)
+    ap.add_argument("--solve-iters", type=int, default=2000)
     ap.add_argument("--per-game", type=int, default=256)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--weights", default="3,10,30,100",
                     help="warm-start weights tried on the validation games; the best is used")
