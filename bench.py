@@ -99,23 +99,26 @@ def measured_traffic(kernel: str):
     return rec.get(kernel, {}).get("bytes_per_launch")
 
 
-def copy_bandwidth(mbytes: int = 256, reps: int = 20) -> float:
-    """GB/s of a plain elementwise copy (dst = src * 1) moving `mbytes` MB (read + write), timed
-    with hipEvents: the attainable bandwidth the roofline is read against."""
+def copy_bandwidth(mbytes: int = 1024, copies: int = 3, reps: int = 12) -> float:
+    """GB/s of a plain elementwise copy (dst = src * 1) moving `mbytes` MB per launch (half read,
+    half written), timed with hipEvents: the attainable bandwidth the roofline is read against.
+    Successive launches rotate over `copies` disjoint buffer pairs (3 GB in all by default), so no
+    launch finds its operands in the 256 MB last-level cache: the figure is an HBM figure."""
     import torch
     n = mbytes * 2**20 // 8
-    src = torch.ones(n, device="cuda")
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        torch.mul(src, 1.0, out=dst)
+    pairs = [(torch.ones(n, device="cuda"), torch.empty(n, device="cuda")) for _ in range(copies)]
+    for i in range(copies):
+        torch.mul(pairs[i][0], 1.0, out=pairs[i][1])
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(reps):
+    for r in range(reps):
+        src, dst = pairs[r % copies]
         torch.mul(src, 1.0, out=dst)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    del src, dst
+    del pairs
+    torch.cuda.empty_cache()
     return mbytes * 2**20 / (ms * 1e-3) / 1e9
 
 
@@ -270,14 +273,26 @@ def main() -> int:
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} done")
 
+    # the K timed iterations run as 10 consecutive groups (a synchronisation after each) so that
+    # the per-iteration time comes with its standard error over the groups
+    groups = [args.steps // 10 + (1 if i < args.steps % 10 else 0) for i in range(10)]
+    group_s = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.iterate(args.steps)
-    torch.cuda.synchronize()
+    for n in groups:
+        if n == 0:
+            continue
+        tg = time.perf_counter()
+        s.iterate(n)
+        torch.cuda.synchronize()
+        group_s.append(((time.perf_counter() - tg) / n))
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
+    per = np.array(group_s) * 1e3
+    sem_ms = float(per.std(ddof=1) / np.sqrt(len(per))) if len(per) > 1 else 0.0
     value = g.n_nodes * args.steps / dt
-    log(f"timed {args.steps} iterations: {ms_per_step:.4f} ms/iteration, {value:.4e} node-updates/s")
+    log(f"timed {args.steps} iterations: {ms_per_step:.4f} +- {sem_ms:.4f} ms/iteration (SEM over "
+        f"{len(per)} groups), {value:.4e} node-updates/s")
 
     # per-kernel durations, hipEvents around every launch on the solver's stream
     kt = s.iterate_timed(args.timed_kernel_steps)
@@ -304,6 +319,7 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_sem": sem_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -162,14 +162,12 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
         x.q_offset = c.take<int32_t>(Hp + 1);
         x.iplayer = c.take<int8_t>(Hp);
         x.member_offset = c.take<int32_t>(Hp + 1);
-        x.members = c.take<int32_t>(M);
         x.chance_nodes = c.take<int32_t>(z.C);
         x.chance_base = c.take<int32_t>(z.C);
         x.chance_k = c.take<int32_t>(z.C);
-        x.mem_q = c.take<int32_t>(M);
+        x.mem_rec = c.take<int4>(M);
         x.mem_kp = c.take<int8_t>(M);
-        x.mem_cb = c.take<int32_t>(M);
-        x.mem_st = c.take<int32_t>(M);
+        x.set_rec = c.take<int4>(Hp);
         x.tile_lo = c.take<int32_t>(N - z.terminals);
         x.tile_hi = c.take<int32_t>(N - z.terminals);
         x.chunk_first = c.take<int32_t>(Hp + D + 2);
@@ -346,17 +344,17 @@ int apply_shapes(cfr_solver* s, hipStream_t st) {
 int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     cfr::XDev& x = s->xdev;
     int rc;
-    // member-major operands of the bottom-up pass
-    std::vector<int32_t> mem_q(P.M), mem_cb(P.M), mem_st(P.M);
+    // member-major and infoset records of the bottom-up pass
+    std::vector<int4> mem_rec(P.M), set_rec(P.Hp);
     std::vector<int8_t> mem_kp(P.M);
     for (int64_t h = 0; h < P.Hp; ++h) {
         const int32_t k = P.q_offset[h + 1] - P.q_offset[h];
         const int8_t kp = static_cast<int8_t>(k | (P.infoset_player[h] == 2 ? 64 : 0));
+        set_rec[h] = make_int4(P.q_offset[h], P.member_offset[h], P.member_offset[h + 1], kp);
         for (int32_t m = P.member_offset[h]; m < P.member_offset[h + 1]; ++m) {
-            mem_q[m] = P.q_offset[h];
+            const int32_t xm = P.members[m];
+            mem_rec[m] = make_int4(xm, P.q_offset[h], P.child_begin[xm], P.child_stride[xm]);
             mem_kp[m] = kp;
-            mem_cb[m] = P.child_begin[P.members[m]];
-            mem_st[m] = P.child_stride[P.members[m]];
         }
     }
     if ((rc = upload(x.parent, P.parent, st)) || (rc = upload(x.edge, P.edge, st)) ||
@@ -365,9 +363,8 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
         (rc = upload(x.child_list, P.child_list, st)) || (rc = upload(x.canon_of, P.canon_of, st)) ||
         (rc = upload(x.q_offset, P.q_offset, st)) || (rc = upload(x.iplayer, P.infoset_player, st)) ||
         (rc = upload(x.member_offset, P.member_offset, st)) ||
-        (rc = upload(x.members, P.members, st)) || (rc = upload(x.mem_q, mem_q, st)) ||
-        (rc = upload(x.mem_kp, mem_kp, st)) || (rc = upload(x.mem_cb, mem_cb, st)) ||
-        (rc = upload(x.mem_st, mem_st, st)) || (rc = upload(x.chance_nodes, P.chance_nodes, st)) ||
+        (rc = upload(x.mem_rec, mem_rec, st)) || (rc = upload(x.mem_kp, mem_kp, st)) ||
+        (rc = upload(x.set_rec, set_rec, st)) || (rc = upload(x.chance_nodes, P.chance_nodes, st)) ||
         (rc = upload(x.chance_base, P.chance_base, st)) || (rc = upload(x.chance_k, P.chance_k, st)) ||
         (rc = upload(x.q_input, P.q_input, st)) || (rc = upload(x.payoff, P.payoff, st)))
         return rc;

@@ -61,7 +61,8 @@ __device__ __forceinline__ int32_t child_of(const int32_t* __restrict__ child_be
 
 // Reach of NPT nodes x = first + u * stride: the factor of whoever acted into the node (meta
 // bits 2-3) is multiplied by the edge probability (sigma or sigma_0). Terminal nodes need no
-// reach. All loads of the NPT nodes are issued before any of them is used.
+// reach. All loads of the NPT nodes are issued before any of them is used, and a node's parent
+// and edge are loaded together with its kind.
 template <int NPT>
 __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64_t hi, int64_t N,
                                             const int32_t* __restrict__ parent,
@@ -71,17 +72,14 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
                                             float* __restrict__ reach) {
     int64_t xs[NPT];
     int kind[NPT];
-#pragma unroll
-    for (int u = 0; u < NPT; ++u) {
-        xs[u] = first + u * stride;
-        kind[u] = xs[u] < hi ? meta[xs[u]] : 0;
-    }
     int32_t p[NPT], e[NPT];
 #pragma unroll
     for (int u = 0; u < NPT; ++u) {
-        p[u] = 0;
-        e[u] = 0;
-        if (kind[u] & 3) {
+        xs[u] = first + u * stride;
+        kind[u] = 0;
+        p[u] = e[u] = 0;
+        if (xs[u] < hi) {  // every node below the root has a parent and an edge
+            kind[u] = meta[xs[u]];
             p[u] = parent[xs[u]];
             e[u] = edge[xs[u]];
         }
@@ -197,14 +195,9 @@ struct UpArgs {
     const int32_t* child_begin;
     const int32_t* child_stride;
     const int32_t* child_list;
-    const int32_t* q_offset;
-    const int8_t* iplayer;
-    const int32_t* member_offset;
-    const int32_t* members;
-    const int32_t* mem_q;
+    const int4* mem_rec;
     const int8_t* mem_kp;
-    const int32_t* mem_cb;
-    const int32_t* mem_st;
+    const int4* set_rec;
     const int32_t* chance_nodes;
     const int32_t* chance_base;
     const int32_t* chance_k;
@@ -317,11 +310,12 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
     int player = 1;
     float pr[KMAX], ps[KMAX], pp[KMAX];
     if (tid < nh) {
-        o = a.q_offset[h0 + tid];
-        k = a.q_offset[h0 + tid + 1] - o;
-        slo = a.member_offset[h0 + tid] - m0;
-        shi = a.member_offset[h0 + tid + 1] - m0;
-        player = a.iplayer[h0 + tid];
+        const int4 hr = a.set_rec[h0 + tid];
+        o = hr.x;
+        slo = hr.y - m0;
+        shi = hr.z - m0;
+        k = hr.w & 31;
+        player = (hr.w & 64) ? 2 : 1;
         if (kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
     }
     if (!big) {
@@ -332,11 +326,12 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
             x[u] = q[u] = cb[u] = st[u] = kp[u] = 0;
             if (mi < nm) {
                 const int32_t m = m0 + mi;
-                x[u] = a.members[m];
-                q[u] = a.mem_q[m];
+                const int4 r = a.mem_rec[m];
+                x[u] = r.x;
+                q[u] = r.y;
+                cb[u] = r.z;
+                st[u] = r.w;
                 kp[u] = a.mem_kp[m];
-                cb[u] = a.mem_cb[m];
-                st[u] = a.mem_st[m];
             }
         }
         float w[MPT][KMAX], sg[MPT][KMAX], r1[MPT], r2[MPT], rc[MPT];
@@ -381,7 +376,8 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
 #pragma unroll 1
         for (int32_t mi = tid; mi < nm; mi += CH) {
             const int32_t m = m0 + mi;
-            const int32_t xm = a.members[m], qm = a.mem_q[m], cbm = a.mem_cb[m], stm = a.mem_st[m];
+            const int4 r = a.mem_rec[m];
+            const int32_t xm = r.x, qm = r.y, cbm = r.z, stm = r.w;
             const int kpm = a.mem_kp[m];
             const int kk = kpm & 31;
             float w[KMAX];
@@ -423,11 +419,12 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
         if (li >= nh) break;
         const int32_t h = h0 + li;
         if (u > 0) {  // the first infoset's operands were loaded before phase 1
-            o = a.q_offset[h];
-            k = a.q_offset[h + 1] - o;
-            slo = a.member_offset[h] - m0;
-            shi = a.member_offset[h + 1] - m0;
-            player = a.iplayer[h];
+            const int4 hr = a.set_rec[h];
+            o = hr.x;
+            slo = hr.y - m0;
+            shi = hr.z - m0;
+            k = hr.w & 31;
+            player = (hr.w & 64) ? 2 : 1;
         }
         if (u > 0 || !kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
         update_infoset<KMAX>(a, o, k, player, slo, shi, pr, ps, pp, s_con, s_own);
@@ -543,12 +540,9 @@ struct BrArgs {
     int64_t N;
     const int32_t* chunk_first;
     const int32_t* chunk_m;
-    const int32_t* member_offset;
-    const int32_t* members;
-    const int32_t* mem_q;
+    const int4* mem_rec;
     const int8_t* mem_kp;
-    const int32_t* mem_cb;
-    const int32_t* mem_st;
+    const int4* set_rec;
     const int32_t* child_begin;
     const int32_t* child_stride;
     const int32_t* child_list;
@@ -612,8 +606,9 @@ __global__ void __launch_bounds__(CH) k_x_br_level(BrArgs a, int32_t klo, int32_
         for (int j = 0; j < KMAX; ++j) wr[j] = con[j] = 0.0f;
         if (ok) {
             const int32_t m = m0 + tid;
-            x = a.members[m];
-            const int32_t q = a.mem_q[m], cb = a.mem_cb[m], st = a.mem_st[m];
+            const int4 r = a.mem_rec[m];
+            x = r.x;
+            const int32_t q = r.y, cb = r.z, st = r.w;
             const int kp = a.mem_kp[m];
             const int k = kp & 31;
             resp = (kp & 64) ? 1 : 0;
@@ -638,7 +633,8 @@ __global__ void __launch_bounds__(CH) k_x_br_level(BrArgs a, int32_t klo, int32_
         for (int j = 0; j < KMAX; ++j) con[j] = 0.0f;
         for (int32_t mi = tid; mi < nm; mi += CH) {
             const int32_t m = m0 + mi;
-            const int32_t xm = a.members[m], q = a.mem_q[m], cb = a.mem_cb[m], st = a.mem_st[m];
+            const int4 r = a.mem_rec[m];
+            const int32_t xm = r.x, q = r.y, cb = r.z, st = r.w;
             const int kp = a.mem_kp[m];
             const int k = kp & 31;
             const int rp = (kp & 64) ? 1 : 0;
@@ -659,10 +655,10 @@ __global__ void __launch_bounds__(CH) k_x_br_level(BrArgs a, int32_t klo, int32_
     }
     __syncthreads();
     if (tid < h1 - h0) {
-        const int32_t h = h0 + tid;
-        const int32_t slo = big ? 0 : a.member_offset[h] - m0;
-        const int32_t shi = big ? (nm < CH ? nm : CH) : a.member_offset[h + 1] - m0;
-        const int k = a.mem_kp[a.member_offset[h]] & 31;
+        const int4 hr = a.set_rec[h0 + tid];
+        const int32_t slo = big ? 0 : hr.y - m0;
+        const int32_t shi = big ? (nm < CH ? nm : CH) : hr.z - m0;
+        const int k = hr.w & 31;
         float tot[KMAX];
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) tot[j] = 0.0f;
@@ -697,7 +693,8 @@ __global__ void __launch_bounds__(CH) k_x_br_level(BrArgs a, int32_t klo, int32_
         const int32_t b = s_sel[0];
         for (int32_t mi = tid; mi < nm; mi += CH) {
             const int32_t m = m0 + mi;
-            const int32_t xm = a.members[m], cb = a.mem_cb[m], st = a.mem_st[m];
+            const int4 r = a.mem_rec[m];
+            const int32_t xm = r.x, cb = r.z, st = r.w;
             const int rp = (a.mem_kp[m] & 64) ? 1 : 0;
             const int32_t ch = st != 0 ? cb + b * st : a.child_list[cb + b];
             a.br_value[rp * N + xm] = a.br_value[rp * N + ch];
@@ -757,14 +754,9 @@ UpArgs up_args(const XDev& x, int variant, int linear) {
     a.child_begin = x.child_begin;
     a.child_stride = x.child_stride;
     a.child_list = x.child_list;
-    a.q_offset = x.q_offset;
-    a.iplayer = x.iplayer;
-    a.member_offset = x.member_offset;
-    a.members = x.members;
-    a.mem_q = x.mem_q;
+    a.mem_rec = x.mem_rec;
     a.mem_kp = x.mem_kp;
-    a.mem_cb = x.mem_cb;
-    a.mem_st = x.mem_st;
+    a.set_rec = x.set_rec;
     a.chance_nodes = x.chance_nodes;
     a.chance_base = x.chance_base;
     a.chance_k = x.chance_k;
@@ -962,12 +954,9 @@ void launch_x_best_response(const XDev& x, const float* avgprob, hipStream_t st)
     a.N = x.N;
     a.chunk_first = x.chunk_first;
     a.chunk_m = x.chunk_m;
-    a.member_offset = x.member_offset;
-    a.members = x.members;
-    a.mem_q = x.mem_q;
+    a.mem_rec = x.mem_rec;
     a.mem_kp = x.mem_kp;
-    a.mem_cb = x.mem_cb;
-    a.mem_st = x.mem_st;
+    a.set_rec = x.set_rec;
     a.child_begin = x.child_begin;
     a.child_stride = x.child_stride;
     a.child_list = x.child_list;

@@ -64,13 +64,13 @@ struct XDev {
     int32_t* q_offset;
     int8_t* iplayer;
     int32_t* member_offset;
-    int32_t* members;
-    // member-major copies (member m of the level-ordered member list): its infoset's first
-    // pair, k | (player 2 ? 64 : 0), and its node's child begin and stride
-    int32_t* mem_q;
+    // member-major records (member m of the level-ordered member list), one 16-byte load each:
+    // {node, its infoset's first pair, the node's child begin, its child stride}; and
+    // k | (player 2 ? 64 : 0)
+    int4* mem_rec;
     int8_t* mem_kp;
-    int32_t* mem_cb;
-    int32_t* mem_st;
+    // infoset records: {first pair, first member, end of members, k | (player 2 ? 64 : 0)}
+    int4* set_rec;
     int32_t* chance_nodes;
     int32_t* chance_base;  // index into prob of the chance node's action 0
     int32_t* chance_k;
