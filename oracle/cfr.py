@@ -1,4 +1,4 @@
-"""Recursive FP64 counterfactual regret minimisation (vanilla CFR and CFR+).
+"""Recursive FP64 counterfactual regret minimisation (vanilla CFR, CFR+ and discounted CFR).
 
 Test infrastructure (oracle): not part of the product path.
 
@@ -36,6 +36,18 @@ simultaneous schedule of Section 3.2):
 CFR+ is only cited by the paper; it is read here as regret matching on
 cumulative regrets clipped at zero after each update, linear averaging with no
 delay, the same simultaneous schedule and the same uniform fallback.
+
+Discounted CFR (DCFR with parameters alpha, beta, gamma) is the discounting of
+the cited weighting work, which the paper's discussion (Section 6) says enters
+only through the average-regret and average-strategy equations. Read here, for
+iteration t = T + 1 (1-based) and the same r~, pibar and sigma as above:
+   R(h,a) <- (R + r~) * t^alpha / (t^alpha + 1)   where R + r~ > 0,
+             (R + r~) * t^beta / (t^beta + 1)     elsewhere;
+   S(h,a) <- (S + pibar(h) * sigma(h,a)) * (t / (t + 1))^gamma.
+Each iteration's strategy then carries weight proportional to t^gamma in the
+normalised average, and with alpha = beta every iteration's regret carries a
+weight that grows as t^alpha; alpha = beta = gamma = 1 is linear CFR up to a
+positive scale, which the tests use as an independent pin.
 """
 from __future__ import annotations
 
@@ -43,7 +55,17 @@ from dataclasses import dataclass
 
 from .tree import Tree
 
-VANILLA, CFR_PLUS = "vanilla", "cfr+"
+VANILLA, CFR_PLUS, DCFR = "vanilla", "cfr+", "dcfr"
+# the weighting work's recommended parameters (alpha, beta, gamma)
+DCFR_DEFAULT = (1.5, 0.0, 2.0)
+
+
+def dcfr_factors(t: int, params=DCFR_DEFAULT):
+    """The discount factors of iteration t (1-based): on positive and on other cumulative
+    regrets, and on the cumulative strategy."""
+    alpha, beta, gamma = params
+    ta, tb = float(t) ** alpha, float(t) ** beta
+    return ta / (ta + 1.0), tb / (tb + 1.0), (t / (t + 1.0)) ** gamma
 
 
 @dataclass
@@ -88,9 +110,11 @@ def average_strategy(tree: Tree, S: list) -> list:
     return out
 
 
-def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = False):
+def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = False,
+            dcfr=DCFR_DEFAULT):
     """One CFR iteration. Returns (new_state, info); ``info`` holds sigma, r~,
-    pibar and, if ``record``, per-node expected payoff u1 and reaches."""
+    pibar and, if ``record``, per-node expected payoff u1 and reaches. ``dcfr`` holds
+    (alpha, beta, gamma) for the discounted variant."""
     sigma = current_strategy(tree, state.R)
     rt = [0.0] * tree.Q
     pibar = {h: 0.0 for h in tree.rational}
@@ -142,7 +166,9 @@ def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = Fal
 
     R = list(state.R)
     S = list(state.S)
-    w = 1.0 if variant == VANILLA else float(state.T + 1)
+    w = float(state.T + 1) if variant == CFR_PLUS else 1.0
+    if variant == DCFR:
+        d_pos, d_neg, d_avg = dcfr_factors(state.T + 1, dcfr)
     for h in tree.rational:
         o, k = qoff[h], tree.nact[h]
         for a in range(k):
@@ -151,9 +177,14 @@ def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = Fal
                 R[q] = R[q] + rt[q]
             elif variant == CFR_PLUS:
                 R[q] = max(R[q] + rt[q], 0.0)
+            elif variant == DCFR:
+                x = R[q] + rt[q]
+                R[q] = x * (d_pos if x > 0.0 else d_neg)
             else:
                 raise ValueError(variant)
             S[q] = S[q] + w * pibar[h] * sigma[q]
+            if variant == DCFR:
+                S[q] = S[q] * d_avg
     info = {"sigma": sigma, "rtilde": rt, "pibar": pibar, "root_value": root_value,
             "next_sigma": current_strategy(tree, R)}
     if record:
@@ -163,10 +194,10 @@ def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = Fal
 
 
 def solve(tree: Tree, iterations: int, variant: str = VANILLA, state: State | None = None,
-          callback=None) -> State:
+          callback=None, dcfr=DCFR_DEFAULT) -> State:
     st = state.copy() if state is not None else State.zeros(tree)
     for _ in range(iterations):
-        st, _info = iterate(tree, st, variant)
+        st, _info = iterate(tree, st, variant, dcfr=dcfr)
         if callback is not None:
             callback(st)
     return st

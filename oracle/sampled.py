@@ -76,7 +76,7 @@ class InfosetSampler:
             return float(self.g.payoff_u1[v])
         return sum(self.edge_prob(R, v, a) * self.value(R, c) for a, c in enumerate(kids))
 
-    def update(self, R, S, T: int, h: int, variant: str = "vanilla") -> dict:
+    def update(self, R, S, T: int, h: int, variant: str = "vanilla", dcfr=(1.5, 0.0, 2.0)) -> dict:
         i = int(self.player[h])
         k = int(self.nact[h])
         o = int(self.qoff[h])
@@ -94,13 +94,23 @@ class InfosetSampler:
             for a in range(k):
                 rt[a] += cf * sgn * (w[a] - u)
             pibar += p1 if i == 1 else p2
-        wt = 1.0 if variant == "vanilla" else float(T + 1)
+        wt = float(T + 1) if variant == "cfr+" else 1.0
+        if variant == "dcfr":  # the discount factors of iteration T + 1 (see oracle.cfr)
+            t = float(T + 1)
+            ta, tb = t ** dcfr[0], t ** dcfr[1]
+            d_pos, d_neg, d_avg = ta / (ta + 1.0), tb / (tb + 1.0), (t / (t + 1.0)) ** dcfr[2]
         Rn, Sn = [], []
         for a in range(k):
             r = float(R[o + a]) + rt[a]
-            if variant != "vanilla":
+            sn = float(S[o + a]) + wt * pibar * sigma[a]
+            if variant == "cfr+":
                 r = max(r, 0.0)
+            elif variant == "dcfr":
+                r *= d_pos if r > 0.0 else d_neg
+                sn *= d_avg
+            elif variant != "vanilla":
+                raise ValueError(variant)
             Rn.append(r)
-            Sn.append(float(S[o + a]) + wt * pibar * sigma[a])
+            Sn.append(sn)
         return {"q": list(range(o, o + k)), "rtilde": rt, "pibar": pibar, "R": Rn, "S": Sn,
                 "sigma": sigma}

@@ -12,7 +12,11 @@
 * the paper's own dense-matrix formulation (Section 3), evaluated literally;
 * invariants: strategies are distributions, CFR+ regrets are nonnegative,
   exploitability is nonnegative and bounded by the regret bounds of the CFR
-  convergence theorem behind the 2-epsilon statement of Section 2.3.
+  convergence theorem behind the 2-epsilon statement of Section 2.3;
+* discounted CFR: with alpha = beta = 1 it is linear CFR (iteration s's regret
+  weighted by s and its strategy by s^gamma, accumulated without discounting)
+  up to the positive scales (t+1) and (t+1)^gamma, which the tests accumulate
+  separately; with beta far below 0 no cumulative regret stays negative.
 """
 import math
 
@@ -308,3 +312,70 @@ def test_exploitability_falls_at_least_like_inverse_sqrt():
             ex[T] = br.exploitability(t, cfr.average_strategy(t, st.S))["expl"]
     slope = math.log(ex[1600] / ex[100]) / math.log(16)
     assert slope < -0.45
+
+
+# ---------------------------------------------------------------- discounted CFR
+
+@pytest.mark.parametrize("gamma", [1.0, 2.0])
+@pytest.mark.parametrize("maker", [
+    lambda: games.kuhn_like(3, "joint"),
+    lambda: games.random_game(8, deal="sequential", depth=4),
+    lambda: games.leduc_like(3, 2, deal="sequential"),
+])
+def test_dcfr_with_unit_exponents_is_linear_cfr(maker, gamma):
+    """Linear CFR accumulates s * r~_s and s^gamma * pibar sigma_s with no discount; the
+    discounted recursion with alpha = beta = 1 must equal it divided by (t+1) (regrets) and
+    (t+1)^gamma (strategy sums) after every iteration t, with the same strategies."""
+    t = _tree(maker())
+    st = cfr.State.zeros(t)
+    RL, SL = [0.0] * t.Q, [0.0] * t.Q
+    for it in range(1, 41):
+        st, info = cfr.iterate(t, st, cfr.DCFR, dcfr=(1.0, 1.0, gamma))
+        # linear CFR's own step at its own regrets: a vanilla walk supplies sigma, r~ and pibar
+        _, lin = cfr.iterate(t, cfr.State(it - 1, list(RL), list(SL)), cfr.VANILLA)
+        np.testing.assert_allclose(info["sigma"], lin["sigma"], rtol=0, atol=1e-12)
+        for h in t.rational:
+            for a in range(t.nact[h]):
+                q = t.qoff[h] + a
+                RL[q] += it * lin["rtilde"][q]
+                SL[q] += it ** gamma * lin["pibar"][h] * lin["sigma"][q]
+        scale_r = max(max(abs(x) for x in RL), 1e-300)
+        scale_s = max(max(abs(x) for x in SL), 1e-300)
+        assert max(abs(st.R[q] * (it + 1) - RL[q]) for q in range(t.Q)) <= 1e-10 * scale_r
+        assert max(abs(st.S[q] * (it + 1) ** gamma - SL[q]) for q in range(t.Q)) <= 1e-10 * scale_s
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: games.random_game(9, deal="joint", depth=4),
+    lambda: games.leduc_like(3, 2, deal="sequential"),
+])
+def test_dcfr_discounts_negative_regrets_by_their_own_factor(maker):
+    """beta = -40 makes the factor on non-positive cumulative regrets 2^-40 or less from the
+    second iteration on, alpha = 1 keeps positive ones: no regret may stay below
+    -1e-9 of the largest, some must stay positive, and the strategy is still a distribution.
+    Testing the sign before adding r~, or swapping the two factors, fails this."""
+    t = _tree(maker())
+    st = cfr.State.zeros(t)
+    for it in range(1, 31):
+        st, info = cfr.iterate(t, st, cfr.DCFR, dcfr=(1.0, -40.0, 2.0))
+        top = max(abs(x) for x in st.R)
+        if it >= 2:
+            assert min(st.R) >= -1e-9 * top
+        assert max(st.R) > 0.0
+        for h in t.rational:
+            s = info["next_sigma"][t.qoff[h]:t.qoff[h] + t.nact[h]]
+            assert min(s) >= 0.0 and abs(sum(s) - 1.0) < 1e-12
+
+
+def test_dcfr_converges_faster_than_vanilla_on_a_poker_game():
+    """The weighting work's claim on poker-like games, at its recommended (1.5, 0, 2)."""
+    t = _tree(games.leduc_like(3, 2, deal="sequential"))
+    ex = {}
+    for variant in (cfr.VANILLA, cfr.DCFR):
+        st = cfr.State.zeros(t)
+        for it in range(1, 201):
+            st, _ = cfr.iterate(t, st, variant)
+            if it in (20, 200):
+                ex[variant, it] = br.exploitability(t, cfr.average_strategy(t, st.S))["expl"]
+    assert ex[cfr.DCFR, 200] < ex[cfr.DCFR, 20] / 4
+    assert ex[cfr.DCFR, 200] < ex[cfr.VANILLA, 200] / 2

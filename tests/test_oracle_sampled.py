@@ -15,6 +15,7 @@ from oracle.tree import Tree
     (lambda: games.random_game(41, deal="sequential", depth=5), "cfr+"),
     (lambda: games.poker_game(5, 2, 2, 40, max_deals=6), "cfr+"),
     (lambda: games.subgame(102), "vanilla"),
+    (lambda: games.random_game(42, deal="joint", depth=5), "dcfr"),
 ])
 def test_sampler_equals_recursive_oracle(maker, variant):
     g = maker()
