@@ -211,6 +211,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exploitability", action="store_true")
     ap.add_argument("--engine", choices=["auto", "node"], default="auto")
+    ap.add_argument("--variant", choices=["cfr+", "vanilla", "dcfr"], default="cfr+",
+                    help="update rule of the large-game line (the reported workload is CFR+; "
+                         "dcfr: discounted CFR with exponents 1.5, 0, 2)")
     ap.add_argument("--workload", choices=["large", "batch"], default="large",
                     help="large: the large single game (the reported line); batch: 512 subgames")
     ap.add_argument("--no-warm-start", action="store_true",
@@ -265,7 +268,7 @@ def main() -> int:
     g = games.large_game()
     log(f"game built: {g.n_nodes} nodes in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    s = Solver(g, "cfr+", device="cuda:0", engine=args.engine)
+    s = Solver(g, args.variant, device="cuda:0", engine=args.engine)
     torch.cuda.synchronize()
     log(f"solver built (flatten + upload + graph capture) in {time.perf_counter() - t0:.1f}s; "
         f"workspace {s.info['workspace_bytes'] / 2**30:.2f} GiB")
@@ -326,7 +329,9 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "large poker game: 13 ranks, 3 rounds, fold/call/pot/all-in, "
-                               "cap 3, stack 400, CFR+ (linear averaging), seed 2",
+                               "cap 3, stack 400, " + {
+                                   "cfr+": "CFR+ (linear averaging)", "vanilla": "vanilla CFR",
+                                   "dcfr": "discounted CFR (1.5, 0, 2)"}[args.variant] + ", seed 2",
                    "nodes": g.n_nodes, "infosets": s.info["n_infosets"], "q": s.info["n_q"],
                    "depth": s.info["depth"],
                    "engine": ["node", "public-block"][s.info["engine"]]},

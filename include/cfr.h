@@ -68,20 +68,33 @@ typedef struct cfr_game {
     const double* payoff_u2;            /* optional [n_nodes] u(t, 2), checked for zero sum */
 } cfr_game;
 
-enum { CFR_VANILLA = 0, CFR_PLUS = 1 };           /* regret update: R += r~ ; R = max(R + r~, 0) */
+/* Regret update of iteration t (1-based), r~ its instantaneous regrets:
+ *   CFR_VANILLA  R += r~                                  (Eq. average_counterfactual_regret,
+ *                                                          as a sum)
+ *   CFR_PLUS     R = max(R + r~, 0)
+ *   CFR_DCFR     R = (R + r~) * t^a / (t^a + 1) where R + r~ > 0, else (R + r~) * t^b / (t^b + 1);
+ *                and the strategy sums S = (S + pibar * sigma) * (t / (t + 1))^g
+ * The discounted variant is the weighting scheme the paper's discussion (Section 6) says
+ * applies by altering the average-regret and average-strategy equations; a, b, g are
+ * cfr_config.dcfr_alpha, dcfr_beta, dcfr_gamma. */
+enum { CFR_VANILLA = 0, CFR_PLUS = 1, CFR_DCFR = 2 };
 enum { CFR_AVG_DEFAULT = -1, CFR_AVG_UNIFORM = 0, CFR_AVG_LINEAR = 1 };
 /* Averaging weight of iteration t (1-based): 1 (uniform, Eq. average_strategy_profile) or t
- * (linear). DEFAULT = uniform for vanilla, linear for CFR+. */
+ * (linear). DEFAULT = uniform for vanilla, linear for CFR+; CFR_DCFR takes DEFAULT only (its
+ * gamma discount sets the weights). */
 
 #define CFR_FLAG_NO_GRAPH 1u    /* enqueue kernels directly instead of replaying a captured graph */
 #define CFR_FLAG_NODE_ENGINE 2u  /* use the breadth-first node engine even where the public-block
                                     engine applies (level-pure infosets, at most 16 actions) */
 
 typedef struct cfr_config {
-    int32_t variant;   /* CFR_VANILLA or CFR_PLUS */
+    int32_t variant;   /* CFR_VANILLA, CFR_PLUS or CFR_DCFR */
     int32_t averaging; /* CFR_AVG_* */
     uint32_t flags;    /* CFR_FLAG_* */
-    int32_t reserved[5];
+    float dcfr_alpha;  /* CFR_DCFR only: exponents, finite and in [-64, 64] (EINVAL otherwise); */
+    float dcfr_beta;   /* the weighting work recommends 1.5, 0 and 2; 1, 1, 1 is linear CFR */
+    float dcfr_gamma;
+    int32_t reserved[2];
 } cfr_config;
 
 /* Sizes of the game in the columns of the paper's game-properties table (Appendix). */

@@ -16,7 +16,7 @@ ERRORS = {
     -1: "CFR_EINVAL", -2: "CFR_ENOTTREE", -3: "CFR_EACTION", -4: "CFR_ECHANCE",
     -5: "CFR_EZEROSUM", -6: "CFR_ELEVEL", -7: "CFR_ENOMEM", -8: "CFR_ESTATE", -9: "CFR_EHIP",
 }
-CFR_VANILLA, CFR_PLUS = 0, 1
+CFR_VANILLA, CFR_PLUS, CFR_DCFR = 0, 1, 2
 CFR_AVG_DEFAULT, CFR_AVG_UNIFORM, CFR_AVG_LINEAR = -1, 0, 1
 CFR_FLAG_NO_GRAPH = 1
 CFR_FLAG_NODE_ENGINE = 2
@@ -48,7 +48,10 @@ class CfrConfig(ctypes.Structure):
         ("variant", ctypes.c_int32),
         ("averaging", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("dcfr_alpha", ctypes.c_float),
+        ("dcfr_beta", ctypes.c_float),
+        ("dcfr_gamma", ctypes.c_float),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

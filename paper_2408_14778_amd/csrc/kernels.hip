@@ -135,27 +135,36 @@ __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
     unsafeAtomicAdd(&pibar[node_infoset[p]], who == 1 ? r1 : r2);
 }
 
-// Infoset pass: regret update (vanilla R += r~, CFR+ R = max(R + r~, 0); Eq.
-// average_counterfactual_regrets_vector in cumulative form), average-strategy
-// accumulation S += w_T * pibar * sigma (Eq. average_strategy_profile_vector in
-// cumulative form), then regret matching for the next strategy. Clears the accumulators.
+// Infoset pass: regret update (vanilla R += r~, CFR+ R = max(R + r~, 0), discounted
+// R = (R + r~) * d+ or d-; Eq. average_counterfactual_regrets_vector in cumulative form),
+// average-strategy accumulation S += w_T * pibar * sigma (discounted: then S *= d_avg; Eq.
+// average_strategy_profile_vector in cumulative form), then regret matching for the next
+// strategy. Clears the accumulators.
 __global__ void k_infoset_update(int64_t Hp, const int32_t* __restrict__ q_offset,
                                  float* __restrict__ R, float* __restrict__ S,
                                  float* __restrict__ sigma, float* __restrict__ rtilde,
                                  float* __restrict__ pibar, const int64_t* __restrict__ T,
-                                 int variant, int linear) {
+                                 UpdateRule rule) {
     const int64_t h = gid();
     if (h >= Hp) return;
     const int32_t o = q_offset[h], k = q_offset[h + 1] - o;
-    const float wt = linear ? static_cast<float>(*T + 1) : 1.0f;
+    const float t = static_cast<float>(*T + 1);
+    float wt = rule.linear ? t : 1.0f;
+    float d_pos = 1.0f, d_neg = 1.0f, d_avg = 1.0f;
+    if (rule.variant == 2) {
+        wt = 1.0f;
+        dcfr_discounts(rule, t, d_pos, d_neg, d_avg);
+    }
     const float pb = pibar[h];
     pibar[h] = 0.0f;
     for (int32_t a = 0; a < k; ++a) {
         const int32_t q = o + a;
         float r = R[q] + rtilde[q];
-        if (variant == 1) r = fmaxf(r, 0.0f);
+        if (rule.variant == 1) r = fmaxf(r, 0.0f);
+        else if (rule.variant == 2) r *= r > 0.0f ? d_pos : d_neg;
         R[q] = r;
-        S[q] = fmaf(wt * pb, sigma[q], S[q]);
+        const float sn = fmaf(wt * pb, sigma[q], S[q]);
+        S[q] = rule.variant == 2 ? sn * d_avg : sn;
         rtilde[q] = 0.0f;
     }
     regret_match(R, sigma, o, k);
@@ -306,7 +315,7 @@ const char* kernel_kind_name(int kind) {
     }
 }
 
-void launch_iteration(const Dev& d, const int32_t* lo, int variant, int linear, hipStream_t st,
+void launch_iteration(const Dev& d, const int32_t* lo, const UpdateRule& rule, hipStream_t st,
                       LaunchTimer* timer) {
     auto pre = [&](int k, int l, int64_t n) { if (timer) timer->before(k, l, n, st); };
     auto post = [&](int k) { if (timer) timer->after(k, st); };
@@ -330,7 +339,7 @@ void launch_iteration(const Dev& d, const int32_t* lo, int variant, int linear, 
     if (d.Hp > 0) {
         pre(K_INFOSET, -1, d.Hp);
         hipLaunchKernelGGL(k_infoset_update, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
-                           d.q_offset, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T, variant, linear);
+                           d.q_offset, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T, rule);
         post(K_INFOSET);
     }
     pre(K_TICK, -1, 1);

@@ -67,8 +67,34 @@ struct LaunchTimer {
     virtual ~LaunchTimer() = default;
 };
 
+// The cumulative-regret and average-strategy update of an iteration (Eqs.
+// average_counterfactual_regrets_vector and average_strategy_profile_vector in cumulative form):
+// variant 0 vanilla, 1 CFR+ (regrets clipped at zero), 2 discounted (the weighting scheme the
+// paper's discussion names: exponents alpha on positive cumulative regrets, beta on the others,
+// gamma on the strategy sums); linear weights iteration t's strategy by t (variants 0 and 1).
+struct UpdateRule {
+    int32_t variant = 0;
+    int32_t linear = 0;
+    float alpha = 1.5f, beta = 0.0f, gamma = 2.0f;
+};
+
+// The discounted update's factors for iteration t (1-based): t^alpha / (t^alpha + 1) on positive
+// cumulative regrets, t^beta / (t^beta + 1) on the others, (t / (t + 1))^gamma on the strategy
+// sums; written as 1 / (1 + t^-x) so that a large t^x cannot overflow, and with the powers as
+// exp2(x log2 t) (t >= 1) on the hardware's base-2 exponential and logarithm, which keeps the
+// infoset update short. With y = x log2 t, a relative rounding e of y moves 1 / (1 + 2^-y) by a
+// relative e y ln2 / (1 + 2^y), below e for every y >= 0 and below e |y| for y < 0, where the
+// factor itself is below 2^y.
+__device__ __forceinline__ void dcfr_discounts(const UpdateRule& u, float t, float& pos, float& neg,
+                                               float& avg) {
+    const float lt = log2f(t);
+    pos = 1.0f / (1.0f + exp2f(-u.alpha * lt));
+    neg = 1.0f / (1.0f + exp2f(-u.beta * lt));
+    avg = exp2f(u.gamma * log2f(t / (t + 1.0f)));
+}
+
 // One iteration (Section 3.2): top-down reach, bottom-up values + regrets, infoset update.
-void launch_iteration(const Dev& d, const int32_t* level_offset_host, int variant, int linear,
+void launch_iteration(const Dev& d, const int32_t* level_offset_host, const UpdateRule& rule,
                       hipStream_t st, LaunchTimer* timer = nullptr);
 // Average strategy into d.avgprob (canonical order; chance tail copied at reset).
 void launch_average(const Dev& d, hipStream_t st);

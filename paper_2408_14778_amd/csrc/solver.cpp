@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstring>
 #include <thread>
 #include <utility>
@@ -33,8 +34,7 @@ struct cfr_solver {
     std::vector<int8_t> x_meta;                                 // host copy (top-down tiles)
     std::vector<int32_t> reach_threads_l, reach_npt_l, t_level_offset;
     std::vector<int64_t> reach_units;  // decision nodes per level
-    int variant = CFR_VANILLA;
-    int linear = 0;
+    cfr::UpdateRule rule;  // regret / average update (variant, linear weights, discounts)
     bool use_graph = true;
     bool level_pure = true;
     int64_t T = 0;
@@ -205,9 +205,9 @@ int upload(T* dst, const std::vector<T>& src, hipStream_t st) {
 
 void launch_one_iteration(cfr_solver* s, hipStream_t st, cfr::LaunchTimer* timer) {
     if (s->engine == ENGINE_BLOCK)
-        cfr::launch_x_iteration(s->xdev, s->variant, s->linear, st, timer);
+        cfr::launch_x_iteration(s->xdev, s->rule, st, timer);
     else
-        cfr::launch_iteration(s->dev, s->level_offset.data(), s->variant, s->linear, st, timer);
+        cfr::launch_iteration(s->dev, s->level_offset.data(), s->rule, st, timer);
 }
 
 int capture(cfr_solver* s) {
@@ -234,6 +234,36 @@ void discard(cfr_solver* s) {
     delete s;
 }
 
+// Validates a configuration (null: the defaults); CFR_OK or an error code with a message.
+int check_config(const cfr_config* c) {
+    if (c == nullptr) return CFR_OK;
+    if (c->variant < CFR_VANILLA || c->variant > CFR_DCFR) return set_err(CFR_EINVAL, "bad variant");
+    if (c->averaging < CFR_AVG_DEFAULT || c->averaging > CFR_AVG_LINEAR)
+        return set_err(CFR_EINVAL, "bad averaging");
+    if (c->variant == CFR_DCFR) {
+        if (c->averaging != CFR_AVG_DEFAULT)
+            return set_err(CFR_EINVAL, "discounted CFR weights the average by gamma: averaging "
+                                       "must be CFR_AVG_DEFAULT");
+        for (float v : {c->dcfr_alpha, c->dcfr_beta, c->dcfr_gamma})
+            if (!std::isfinite(v) || v < -64.0f || v > 64.0f)
+                return set_err(CFR_EINVAL, "discount exponents must be finite and in [-64, 64]");
+    }
+    return CFR_OK;
+}
+
+// The update rule a validated configuration asks for.
+cfr::UpdateRule rule_of(const cfr_config& c) {
+    cfr::UpdateRule u;
+    u.variant = c.variant;
+    u.linear = c.variant == CFR_DCFR ? 0
+               : c.averaging == CFR_AVG_DEFAULT ? (c.variant == CFR_PLUS)
+                                                : c.averaging;
+    u.alpha = c.dcfr_alpha;
+    u.beta = c.dcfr_beta;
+    u.gamma = c.dcfr_gamma;
+    return u;
+}
+
 }  // namespace
 
 extern "C" {
@@ -242,8 +272,7 @@ const char* cfr_last_error(void) { return g_err.c_str(); }
 
 int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out) {
     if (game == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
-    if (config != nullptr && (config->variant < 0 || config->variant > 1))
-        return set_err(CFR_EINVAL, "bad variant");
+    if (const int rc = check_config(config); rc != CFR_OK) return rc;
     cfr::Layout L;
     std::string err;
     const int rc = cfr::plan_sizes(*game, L, err);
@@ -413,8 +442,7 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     cfg.variant = CFR_VANILLA;
     cfg.averaging = CFR_AVG_DEFAULT;
     if (config != nullptr) cfg = *config;
-    if (cfg.variant < 0 || cfg.variant > 1) return set_err(CFR_EINVAL, "bad variant");
-    if (cfg.averaging < -1 || cfg.averaging > 1) return set_err(CFR_EINVAL, "bad averaging");
+    if (const int rc = check_config(&cfg); rc != CFR_OK) return rc;
     cfr::Layout L;
     std::string err;
     int rc = cfr::flatten(*game, L, err);
@@ -441,8 +469,7 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     s->dev = d;
     s->xdev = x;
     s->engine = z.engine;
-    s->variant = cfg.variant;
-    s->linear = cfg.averaging == CFR_AVG_DEFAULT ? (cfg.variant == CFR_PLUS) : cfg.averaging;
+    s->rule = rule_of(cfg);
     s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
     s->level_pure = L.level_pure;
     s->n_terminals = L.n_terminals;
@@ -894,8 +921,7 @@ extern "C" {
 int cfr_plan_batch(const cfr_game* games, int32_t n_games, const cfr_config* config,
                    cfr_plan_info* out) {
     if (games == nullptr || out == nullptr || n_games < 1) return set_err(CFR_EINVAL, "bad argument");
-    if (config != nullptr && (config->variant < 0 || config->variant > 1))
-        return set_err(CFR_EINVAL, "bad variant");
+    if (const int rc = check_config(config); rc != CFR_OK) return rc;
     Sizes z;
     z.engine = ENGINE_BLOCK;
     z.canonical = false;
@@ -940,8 +966,7 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     cfg.variant = CFR_VANILLA;
     cfg.averaging = CFR_AVG_DEFAULT;
     if (config != nullptr) cfg = *config;
-    if (cfg.variant < 0 || cfg.variant > 1) return set_err(CFR_EINVAL, "bad variant");
-    if (cfg.averaging < -1 || cfg.averaging > 1) return set_err(CFR_EINVAL, "bad averaging");
+    if (const int rc = check_config(&cfg); rc != CFR_OK) return rc;
     std::string err;
     std::vector<cfr::ExecPlan> plans;
     int32_t max_actions = 0;
@@ -974,8 +999,7 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     s->engine = ENGINE_BLOCK;
     s->n_games = n_games;
     s->canonical = false;
-    s->variant = cfg.variant;
-    s->linear = cfg.averaging == CFR_AVG_DEFAULT ? (cfg.variant == CFR_PLUS) : cfg.averaging;
+    s->rule = rule_of(cfg);
     s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
     s->level_pure = true;
     s->max_actions = max_actions;

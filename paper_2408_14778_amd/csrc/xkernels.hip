@@ -207,8 +207,7 @@ struct UpArgs {
     float* R;
     float* S;
     int64_t* T;
-    int variant;
-    int linear;
+    UpdateRule rule;
 };
 
 // Chance node ci (if ok) on a group of 2^glog lanes: lane l sums children l, l + 2^glog, ...,
@@ -231,8 +230,8 @@ __device__ __forceinline__ void chance_group(const UpArgs& a, int32_t ci, bool o
 
 // Phase 2 of a chunk for one infoset h (pair operands pr = R, ps = S, pp = sigma already
 // loaded): sums its members' LDS slots slo .. shi - 1 in member order, then the regret update
-// (vanilla, or CFR+ clipped), the average-strategy update S += w pi-bar sigma and regret
-// matching into sigma.
+// (vanilla, CFR+ clipped, or discounted), the average-strategy update S += w pi-bar sigma
+// (discounted: then scaled) and regret matching into sigma.
 template <int KMAX>
 __device__ __forceinline__ void update_infoset(const UpArgs& a, int32_t o, int32_t k, int player,
                                                int32_t slo, int32_t shi, const float* pr,
@@ -249,15 +248,24 @@ __device__ __forceinline__ void update_infoset(const UpArgs& a, int32_t o, int32
         own += s_own[sl];
     }
     const float sgn = player == 1 ? 1.0f : -1.0f;
-    const float wt = a.linear ? static_cast<float>(*a.T + 1) : 1.0f;
+    const float t = static_cast<float>(*a.T + 1);
+    const bool disc = a.rule.variant == 2;
+    float wt = a.rule.linear ? t : 1.0f;
+    float d_pos = 1.0f, d_neg = 1.0f, d_avg = 1.0f;
+    if (disc) {
+        wt = 1.0f;
+        dcfr_discounts(a.rule, t, d_pos, d_neg, d_avg);
+    }
     float pos_sum = 0.0f;
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) {
         if (j < k) {
             float r = fmaf(sgn, racc[j], pr[j]);
-            if (a.variant == 1) r = fmaxf(r, 0.0f);
+            if (a.rule.variant == 1) r = fmaxf(r, 0.0f);
+            else if (disc) r *= r > 0.0f ? d_pos : d_neg;
             a.R[o + j] = r;
-            a.S[o + j] = fmaf(wt * own, pp[j], ps[j]);
+            const float sn = fmaf(wt * own, pp[j], ps[j]);
+            a.S[o + j] = disc ? sn * d_avg : sn;
             racc[j] = r;
             pos_sum += fmaxf(r, 0.0f);
         }
@@ -746,7 +754,7 @@ void launch_x_reset(const XDev& x, hipStream_t st) {
 
 namespace {
 
-UpArgs up_args(const XDev& x, int variant, int linear) {
+UpArgs up_args(const XDev& x, const UpdateRule& rule) {
     UpArgs a;
     a.N = x.N;
     a.chunk_first = x.chunk_first;
@@ -766,8 +774,7 @@ UpArgs up_args(const XDev& x, int variant, int linear) {
     a.R = x.R;
     a.S = x.S;
     a.T = x.T;
-    a.variant = variant;
-    a.linear = linear;
+    a.rule = rule;
     return a;
 }
 
@@ -849,7 +856,7 @@ int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_
     return k;
 }
 
-void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st, LaunchTimer* timer) {
+void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, LaunchTimer* timer) {
     auto pre = [&](int k, int l, int64_t n) { if (timer) timer->before(k, l, n, st); };
     auto post = [&](int k) { if (timer) timer->after(k, st); };
     const int32_t* lo = x.level_offset_host;
@@ -886,7 +893,7 @@ void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st, 
         post(XK_REACH);
     }
     // bottom-up: a launch per deep level, then the shallow levels in one workgroup
-    const UpArgs a = up_args(x, variant, linear);
+    const UpArgs a = up_args(x, rule);
     const int32_t fu = x.fused_up;
     for (int32_t l = x.D; l >= fu; --l) {
         const int32_t nunits = x.h_level_offset_host[l + 1] - x.h_level_offset_host[l] +

@@ -100,7 +100,7 @@ int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_
                           int32_t max_actions);
 
 void launch_x_reset(const XDev& x, hipStream_t st);
-void launch_x_iteration(const XDev& x, int variant, int linear, hipStream_t st,
+void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st,
                         LaunchTimer* timer = nullptr);
 // Best responses of both players to sigma-bar (avgprob: exec pairs, then sigma_0); the root
 // values land in out2[2 g], out2[2 g + 1].

@@ -11,7 +11,9 @@ import numpy as np
 
 from . import _native as N
 
-VARIANTS = {"vanilla": N.CFR_VANILLA, "cfr+": N.CFR_PLUS}
+VARIANTS = {"vanilla": N.CFR_VANILLA, "cfr+": N.CFR_PLUS, "dcfr": N.CFR_DCFR}
+# discounted CFR's (alpha, beta, gamma) unless the caller gives others
+DCFR_DEFAULT = (1.5, 0.0, 2.0)
 AVERAGING = {None: N.CFR_AVG_DEFAULT, "uniform": N.CFR_AVG_UNIFORM, "linear": N.CFR_AVG_LINEAR}
 
 LAYOUT_DTYPES = {
@@ -57,7 +59,7 @@ class GameArgs:
 
 
 def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
-                engine: str = "auto") -> N.CfrConfig:
+                engine: str = "auto", dcfr=None) -> N.CfrConfig:
     if variant not in VARIANTS:
         raise ValueError(f"variant must be one of {list(VARIANTS)}")
     if engine not in ("auto", "node"):
@@ -65,14 +67,17 @@ def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
     cfg = N.CfrConfig()
     cfg.variant = VARIANTS[variant]
     cfg.averaging = AVERAGING[averaging]
+    if dcfr is not None and variant != "dcfr":
+        raise ValueError("dcfr exponents apply to variant 'dcfr' only")
+    cfg.dcfr_alpha, cfg.dcfr_beta, cfg.dcfr_gamma = (dcfr if dcfr is not None else DCFR_DEFAULT)
     cfg.flags = (0 if graph else N.CFR_FLAG_NO_GRAPH) | (N.CFR_FLAG_NODE_ENGINE if engine == "node" else 0)
     return cfg
 
 
-def plan(game, variant: str = "vanilla", averaging=None, engine: str = "auto") -> dict:
+def plan(game, variant: str = "vanilla", averaging=None, engine: str = "auto", dcfr=None) -> dict:
     lib = N.load()
     args = GameArgs(game)
-    cfg = make_config(variant, averaging, engine=engine)
+    cfg = make_config(variant, averaging, engine=engine, dcfr=dcfr)
     info = N.CfrPlanInfo()
     N.check(lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg), ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
@@ -117,16 +122,18 @@ def default_launch_shape(lib=None) -> "N.CfrLaunchShape":
 
 
 class Solver:
-    """CFR (vanilla or CFR+) over one game, resident on one GPU."""
+    """CFR (vanilla, CFR+ or discounted CFR) over one game, resident on one GPU. ``dcfr``:
+    (alpha, beta, gamma) of variant 'dcfr' (default (1.5, 0, 2))."""
 
     def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
-                 graph: bool = True, stream=None, engine: str = "auto", tuned: bool = True):
+                 graph: bool = True, stream=None, engine: str = "auto", tuned: bool = True,
+                 dcfr=None):
         import torch
 
         self._lib = N.load()
         self.variant = variant
         args = GameArgs(game)
-        cfg = make_config(variant, averaging, graph, engine)
+        cfg = make_config(variant, averaging, graph, engine, dcfr)
         info = N.CfrPlanInfo()
         N.check(self._lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg),
                                    ctypes.byref(info)))
@@ -279,7 +286,7 @@ class BatchSolver(Solver):
     ``pair_offsets[g]`` is where game g's pairs start."""
 
     def __init__(self, game_list, variant: str = "cfr+", averaging=None, device: str = "cuda",
-                 graph: bool = True, stream=None, tuned: bool = True):
+                 graph: bool = True, stream=None, tuned: bool = True, dcfr=None):
         import torch
 
         self._lib = N.load()
@@ -287,7 +294,7 @@ class BatchSolver(Solver):
         self._args = [GameArgs(g) for g in game_list]
         n = len(self._args)
         arr = (N.CfrGame * n)(*[a.struct for a in self._args])
-        cfg = make_config(variant, averaging, graph)
+        cfg = make_config(variant, averaging, graph, dcfr=dcfr)
         info = N.CfrPlanInfo()
         N.check(self._lib.cfr_plan_batch(arr, n, ctypes.byref(cfg), ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}

@@ -81,6 +81,27 @@ def test_validation_error_codes(mutate, code):
     assert str(e.value).startswith(code)
 
 
+def test_config_layout_and_discount_validation():
+    """cfr_config stays 32 bytes; the discounted variant takes finite exponents in [-64, 64]
+    and the default averaging only (its gamma sets the weights)."""
+    import ctypes
+
+    from paper_2408_14778_amd import CfrError, plan
+    from paper_2408_14778_amd import _native as N
+    assert ctypes.sizeof(N.CfrConfig) == 32
+    assert N.CfrConfig.dcfr_alpha.offset == 12 and N.CfrConfig.reserved.offset == 24
+    g = games.kuhn_like(3, "joint")
+    assert plan(g, "dcfr")["n_q"] == 24
+    assert plan(g, "dcfr", dcfr=(1.0, 1.0, 1.0))["n_q"] == 24
+    for bad in [(float("nan"), 0.0, 2.0), (1.5, float("inf"), 2.0), (1.5, 0.0, 65.0)]:
+        with pytest.raises(CfrError, match="CFR_EINVAL"):
+            plan(g, "dcfr", dcfr=bad)
+    with pytest.raises(CfrError, match="CFR_EINVAL"):
+        plan(g, "dcfr", averaging="linear")
+    with pytest.raises(ValueError):
+        plan(g, "cfr+", dcfr=(1.0, 1.0, 1.0))
+
+
 def test_terminal_with_infoset_rejected():
     from paper_2408_14778_amd import CfrError, plan
     g = _copy(games.kuhn_like(3, "joint"))

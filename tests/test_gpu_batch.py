@@ -24,7 +24,7 @@ def _mixed_games():
     return out
 
 
-@pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+", "dcfr"])
 def test_batch_one_iteration_matches_single_and_oracle(variant):
     from paper_2408_14778_amd import BatchSolver, Solver
     gl = _mixed_games()
