@@ -48,6 +48,12 @@ Each iteration's strategy then carries weight proportional to t^gamma in the
 normalised average, and with alpha = beta every iteration's regret carries a
 weight that grows as t^alpha; alpha = beta = gamma = 1 is linear CFR up to a
 positive scale, which the tests use as an independent pin.
+
+Alternating updates (the schedule of the CFR+ work the paper cites, which the
+discussion of Section 6 names as applicable to the matrix formulation): one
+iteration is two passes of steps 1-4 with the same t. The first updates only
+player 1's infosets (R, S, and so its strategy); the second, which sees player
+1's new strategy, updates only player 2's; then T += 1.
 """
 from __future__ import annotations
 
@@ -56,6 +62,7 @@ from dataclasses import dataclass
 from .tree import Tree
 
 VANILLA, CFR_PLUS, DCFR = "vanilla", "cfr+", "dcfr"
+SIMULTANEOUS, ALTERNATING = "simultaneous", "alternating"
 # the weighting work's recommended parameters (alpha, beta, gamma)
 DCFR_DEFAULT = (1.5, 0.0, 2.0)
 
@@ -111,10 +118,11 @@ def average_strategy(tree: Tree, S: list) -> list:
 
 
 def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = False,
-            dcfr=DCFR_DEFAULT):
+            dcfr=DCFR_DEFAULT, players=(1, 2), count: bool = True):
     """One CFR iteration. Returns (new_state, info); ``info`` holds sigma, r~,
     pibar and, if ``record``, per-node expected payoff u1 and reaches. ``dcfr`` holds
-    (alpha, beta, gamma) for the discounted variant."""
+    (alpha, beta, gamma) for the discounted variant. ``players``: whose infosets the
+    call updates (the others keep R and S); ``count``: whether it ends the iteration."""
     sigma = current_strategy(tree, state.R)
     rt = [0.0] * tree.Q
     pibar = {h: 0.0 for h in tree.rational}
@@ -170,6 +178,8 @@ def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = Fal
     if variant == DCFR:
         d_pos, d_neg, d_avg = dcfr_factors(state.T + 1, dcfr)
     for h in tree.rational:
+        if player[h] not in players:
+            continue
         o, k = qoff[h], tree.nact[h]
         for a in range(k):
             q = o + a
@@ -190,14 +200,25 @@ def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = Fal
     if record:
         info["node_u"] = node_u
         info["node_reach"] = node_reach
-    return State(state.T + 1, R, S), info
+    return State(state.T + (1 if count else 0), R, S), info
+
+
+def iterate_alternating(tree: Tree, state: State, variant: str = VANILLA, dcfr=DCFR_DEFAULT):
+    """One iteration of the alternating schedule: a pass updating player 1, then one updating
+    player 2 under player 1's new strategy, both with t = T + 1. Returns (new_state, info of
+    the second pass)."""
+    st, _ = iterate(tree, state, variant, dcfr=dcfr, players=(1,), count=False)
+    return iterate(tree, st, variant, dcfr=dcfr, players=(2,), count=True)
 
 
 def solve(tree: Tree, iterations: int, variant: str = VANILLA, state: State | None = None,
-          callback=None, dcfr=DCFR_DEFAULT) -> State:
+          callback=None, dcfr=DCFR_DEFAULT, schedule: str = SIMULTANEOUS) -> State:
     st = state.copy() if state is not None else State.zeros(tree)
     for _ in range(iterations):
-        st, _info = iterate(tree, st, variant, dcfr=dcfr)
+        if schedule == ALTERNATING:
+            st, _info = iterate_alternating(tree, st, variant, dcfr=dcfr)
+        else:
+            st, _info = iterate(tree, st, variant, dcfr=dcfr)
         if callback is not None:
             callback(st)
     return st
