@@ -214,6 +214,8 @@ def main() -> int:
     ap.add_argument("--variant", choices=["cfr+", "vanilla", "dcfr"], default="cfr+",
                     help="update rule of the large-game line (the reported workload is CFR+; "
                          "dcfr: discounted CFR with exponents 1.5, 0, 2)")
+    ap.add_argument("--schedule", choices=["simultaneous", "alternating"], default="simultaneous",
+                    help="alternating: an iteration is a player-1 pass and a player-2 pass")
     ap.add_argument("--workload", choices=["large", "batch"], default="large",
                     help="large: the large single game (the reported line); batch: 512 subgames")
     ap.add_argument("--no-warm-start", action="store_true",
@@ -268,7 +270,7 @@ def main() -> int:
     g = games.large_game()
     log(f"game built: {g.n_nodes} nodes in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    s = Solver(g, args.variant, device="cuda:0", engine=args.engine)
+    s = Solver(g, args.variant, device="cuda:0", engine=args.engine, schedule=args.schedule)
     torch.cuda.synchronize()
     log(f"solver built (flatten + upload + graph capture) in {time.perf_counter() - t0:.1f}s; "
         f"workspace {s.info['workspace_bytes'] / 2**30:.2f} GiB")
@@ -293,7 +295,9 @@ def main() -> int:
     ms_per_step = dt * 1e3 / args.steps
     per = np.array(group_s) * 1e3
     sem_ms = float(per.std(ddof=1) / np.sqrt(len(per))) if len(per) > 1 else 0.0
-    value = g.n_nodes * args.steps / dt
+    # a node-update is one node processed once: the alternating schedule makes two passes
+    passes = 2 if args.schedule == "alternating" else 1
+    value = g.n_nodes * passes * args.steps / dt
     log(f"timed {args.steps} iterations: {ms_per_step:.4f} +- {sem_ms:.4f} ms/iteration (SEM over "
         f"{len(per)} groups), {value:.4e} node-updates/s")
 
@@ -305,9 +309,9 @@ def main() -> int:
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
     avg_s = total_ms / launches * 1e-3
-    bytes_per_launch = algorithmic_bytes(dom, counts) * args.timed_kernel_steps / launches
+    bytes_per_launch = algorithmic_bytes(dom, counts) * passes * args.timed_kernel_steps / launches
     achieved = bytes_per_launch / avg_s / 1e9
-    iter_bytes = float(sum(algorithmic_bytes(k, counts) for k in ("block_reach", "block_up")))
+    iter_bytes = passes * float(sum(algorithmic_bytes(k, counts) for k in ("block_reach", "block_up")))
     attainable = copy_bandwidth()
     log(f"plain copy: {attainable:.0f} GB/s")
     kernels = {k: {"launches": n, "avg_us": ms / n * 1e3,
@@ -331,10 +335,13 @@ def main() -> int:
         "config": {"workload": "large poker game: 13 ranks, 3 rounds, fold/call/pot/all-in, "
                                "cap 3, stack 400, " + {
                                    "cfr+": "CFR+ (linear averaging)", "vanilla": "vanilla CFR",
-                                   "dcfr": "discounted CFR (1.5, 0, 2)"}[args.variant] + ", seed 2",
+                                   "dcfr": "discounted CFR (1.5, 0, 2)"}[args.variant] +
+                               (", alternating updates" if args.schedule == "alternating" else "") +
+                               ", seed 2",
                    "nodes": g.n_nodes, "infosets": s.info["n_infosets"], "q": s.info["n_q"],
                    "depth": s.info["depth"],
-                   "engine": ["node", "public-block"][s.info["engine"]]},
+                   "engine": ["node", "public-block"][s.info["engine"]],
+                   "passes_per_iteration": passes},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,

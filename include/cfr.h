@@ -86,6 +86,11 @@ enum { CFR_AVG_DEFAULT = -1, CFR_AVG_UNIFORM = 0, CFR_AVG_LINEAR = 1 };
 #define CFR_FLAG_NO_GRAPH 1u    /* enqueue kernels directly instead of replaying a captured graph */
 #define CFR_FLAG_NODE_ENGINE 2u  /* use the breadth-first node engine even where the public-block
                                     engine applies (level-pure infosets, at most 16 actions) */
+#define CFR_FLAG_ALTERNATING 4u  /* alternating updates (the schedule of the cited CFR+ work): an
+                                    iteration is a pass that updates player 1's infosets, then a
+                                    pass, under player 1's new strategy, that updates player 2's,
+                                    both with the same t; default: both players in one pass.
+                                    Other flag bits: CFR_EINVAL */
 
 typedef struct cfr_config {
     int32_t variant;   /* CFR_VANILLA, CFR_PLUS or CFR_DCFR */

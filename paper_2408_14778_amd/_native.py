@@ -20,6 +20,7 @@ CFR_VANILLA, CFR_PLUS, CFR_DCFR = 0, 1, 2
 CFR_AVG_DEFAULT, CFR_AVG_UNIFORM, CFR_AVG_LINEAR = -1, 0, 1
 CFR_FLAG_NO_GRAPH = 1
 CFR_FLAG_NODE_ENGINE = 2
+CFR_FLAG_ALTERNATING = 4
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i8p = ctypes.POINTER(ctypes.c_int8)

@@ -139,8 +139,9 @@ __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
 // R = (R + r~) * d+ or d-; Eq. average_counterfactual_regrets_vector in cumulative form),
 // average-strategy accumulation S += w_T * pibar * sigma (discounted: then S *= d_avg; Eq.
 // average_strategy_profile_vector in cumulative form), then regret matching for the next
-// strategy. Clears the accumulators.
+// strategy, for the infosets of the pass's players. Clears the accumulators of all.
 __global__ void k_infoset_update(int64_t Hp, const int32_t* __restrict__ q_offset,
+                                 const int8_t* __restrict__ infoset_player,
                                  float* __restrict__ R, float* __restrict__ S,
                                  float* __restrict__ sigma, float* __restrict__ rtilde,
                                  float* __restrict__ pibar, const int64_t* __restrict__ T,
@@ -157,6 +158,10 @@ __global__ void k_infoset_update(int64_t Hp, const int32_t* __restrict__ q_offse
     }
     const float pb = pibar[h];
     pibar[h] = 0.0f;
+    if (!((rule.players >> (infoset_player[h] - 1)) & 1)) {
+        for (int32_t a = 0; a < k; ++a) rtilde[o + a] = 0.0f;
+        return;
+    }
     for (int32_t a = 0; a < k; ++a) {
         const int32_t q = o + a;
         float r = R[q] + rtilde[q];
@@ -339,12 +344,15 @@ void launch_iteration(const Dev& d, const int32_t* lo, const UpdateRule& rule, h
     if (d.Hp > 0) {
         pre(K_INFOSET, -1, d.Hp);
         hipLaunchKernelGGL(k_infoset_update, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
-                           d.q_offset, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T, rule);
+                           d.q_offset, d.infoset_player, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T,
+                           rule);
         post(K_INFOSET);
     }
-    pre(K_TICK, -1, 1);
-    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, d.T);
-    post(K_TICK);
+    if (rule.count) {
+        pre(K_TICK, -1, 1);
+        hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, d.T);
+        post(K_TICK);
+    }
 }
 
 void launch_average(const Dev& d, hipStream_t st) {

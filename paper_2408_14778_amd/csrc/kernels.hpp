@@ -72,10 +72,15 @@ struct LaunchTimer {
 // variant 0 vanilla, 1 CFR+ (regrets clipped at zero), 2 discounted (the weighting scheme the
 // paper's discussion names: exponents alpha on positive cumulative regrets, beta on the others,
 // gamma on the strategy sums); linear weights iteration t's strategy by t (variants 0 and 1).
+// players: the players whose infosets a pass updates (bit 0 player 1, bit 1 player 2; the
+// others keep R, S and sigma); count: whether the pass ends the iteration (T += 1). The
+// alternating schedule is a pass with players 1, count 0, then one with players 2, count 1.
 struct UpdateRule {
     int32_t variant = 0;
     int32_t linear = 0;
     float alpha = 1.5f, beta = 0.0f, gamma = 2.0f;
+    int32_t players = 3;
+    int32_t count = 1;
 };
 
 // The discounted update's factors for iteration t (1-based): t^alpha / (t^alpha + 1) on positive

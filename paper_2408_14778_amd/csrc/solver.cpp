@@ -35,6 +35,7 @@ struct cfr_solver {
     std::vector<int32_t> reach_threads_l, reach_npt_l, t_level_offset;
     std::vector<int64_t> reach_units;  // decision nodes per level
     cfr::UpdateRule rule;  // regret / average update (variant, linear weights, discounts)
+    bool alternating = false;  // two passes per iteration: player 1, then player 2
     bool use_graph = true;
     bool level_pure = true;
     int64_t T = 0;
@@ -204,10 +205,22 @@ int upload(T* dst, const std::vector<T>& src, hipStream_t st) {
 }
 
 void launch_one_iteration(cfr_solver* s, hipStream_t st, cfr::LaunchTimer* timer) {
-    if (s->engine == ENGINE_BLOCK)
-        cfr::launch_x_iteration(s->xdev, s->rule, st, timer);
-    else
-        cfr::launch_iteration(s->dev, s->level_offset.data(), s->rule, st, timer);
+    auto pass = [&](const cfr::UpdateRule& r) {
+        if (s->engine == ENGINE_BLOCK)
+            cfr::launch_x_iteration(s->xdev, r, st, timer);
+        else
+            cfr::launch_iteration(s->dev, s->level_offset.data(), r, st, timer);
+    };
+    if (!s->alternating) {
+        pass(s->rule);
+        return;
+    }
+    cfr::UpdateRule first = s->rule, second = s->rule;
+    first.players = 1;
+    first.count = 0;
+    second.players = 2;
+    pass(first);
+    pass(second);
 }
 
 int capture(cfr_solver* s) {
@@ -238,6 +251,8 @@ void discard(cfr_solver* s) {
 int check_config(const cfr_config* c) {
     if (c == nullptr) return CFR_OK;
     if (c->variant < CFR_VANILLA || c->variant > CFR_DCFR) return set_err(CFR_EINVAL, "bad variant");
+    if (c->flags & ~(CFR_FLAG_NO_GRAPH | CFR_FLAG_NODE_ENGINE | CFR_FLAG_ALTERNATING))
+        return set_err(CFR_EINVAL, "unknown flag bits");
     if (c->averaging < CFR_AVG_DEFAULT || c->averaging > CFR_AVG_LINEAR)
         return set_err(CFR_EINVAL, "bad averaging");
     if (c->variant == CFR_DCFR) {
@@ -470,6 +485,7 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     s->xdev = x;
     s->engine = z.engine;
     s->rule = rule_of(cfg);
+    s->alternating = (cfg.flags & CFR_FLAG_ALTERNATING) != 0;
     s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
     s->level_pure = L.level_pure;
     s->n_terminals = L.n_terminals;
@@ -1000,6 +1016,7 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     s->n_games = n_games;
     s->canonical = false;
     s->rule = rule_of(cfg);
+    s->alternating = (cfg.flags & CFR_FLAG_ALTERNATING) != 0;
     s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
     s->level_pure = true;
     s->max_actions = max_actions;

@@ -237,6 +237,7 @@ __device__ __forceinline__ void update_infoset(const UpArgs& a, int32_t o, int32
                                                int32_t slo, int32_t shi, const float* pr,
                                                const float* ps, const float* pp,
                                                float (*s_con)[KMAX], const float* s_own) {
+    if (!((a.rule.players >> (player - 1)) & 1)) return;  // not this pass's player
     float racc[KMAX];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) racc[j] = 0.0f;
@@ -471,7 +472,7 @@ __global__ void __launch_bounds__(kFuseThreads) k_x_up_top(UpArgs a, LevelTable 
         }
         __syncthreads();
     }
-    if (tid == 0) *a.T += 1;
+    if (tid == 0 && a.rule.count) *a.T += 1;
 }
 
 __global__ void k_x_reset_nodes(int64_t N, int32_t n_roots, const int8_t* __restrict__ meta,
@@ -918,7 +919,7 @@ void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, L
         pre(XK_UP, -1, x.m_level_offset_host[fu] - x.m_level_offset_host[0]);
         hipLaunchKernelGGL(k_x_up_top, dim3(1), dim3(kFuseThreads), 0, st, a, t);
         post(XK_UP);
-    } else {
+    } else if (rule.count) {
         // the linear-averaging weight of every launch above read T: count the iteration last
         hipLaunchKernelGGL(k_x_tick, dim3(1), dim3(64), 0, st, x.T);
     }

@@ -59,7 +59,7 @@ class GameArgs:
 
 
 def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
-                engine: str = "auto", dcfr=None) -> N.CfrConfig:
+                engine: str = "auto", dcfr=None, schedule: str = "simultaneous") -> N.CfrConfig:
     if variant not in VARIANTS:
         raise ValueError(f"variant must be one of {list(VARIANTS)}")
     if engine not in ("auto", "node"):
@@ -70,14 +70,19 @@ def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
     if dcfr is not None and variant != "dcfr":
         raise ValueError("dcfr exponents apply to variant 'dcfr' only")
     cfg.dcfr_alpha, cfg.dcfr_beta, cfg.dcfr_gamma = (dcfr if dcfr is not None else DCFR_DEFAULT)
-    cfg.flags = (0 if graph else N.CFR_FLAG_NO_GRAPH) | (N.CFR_FLAG_NODE_ENGINE if engine == "node" else 0)
+    if schedule not in ("simultaneous", "alternating"):
+        raise ValueError("schedule must be 'simultaneous' or 'alternating'")
+    cfg.flags = ((0 if graph else N.CFR_FLAG_NO_GRAPH) |
+                 (N.CFR_FLAG_NODE_ENGINE if engine == "node" else 0) |
+                 (N.CFR_FLAG_ALTERNATING if schedule == "alternating" else 0))
     return cfg
 
 
-def plan(game, variant: str = "vanilla", averaging=None, engine: str = "auto", dcfr=None) -> dict:
+def plan(game, variant: str = "vanilla", averaging=None, engine: str = "auto", dcfr=None,
+         schedule: str = "simultaneous") -> dict:
     lib = N.load()
     args = GameArgs(game)
-    cfg = make_config(variant, averaging, engine=engine, dcfr=dcfr)
+    cfg = make_config(variant, averaging, engine=engine, dcfr=dcfr, schedule=schedule)
     info = N.CfrPlanInfo()
     N.check(lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg), ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
@@ -123,17 +128,18 @@ def default_launch_shape(lib=None) -> "N.CfrLaunchShape":
 
 class Solver:
     """CFR (vanilla, CFR+ or discounted CFR) over one game, resident on one GPU. ``dcfr``:
-    (alpha, beta, gamma) of variant 'dcfr' (default (1.5, 0, 2))."""
+    (alpha, beta, gamma) of variant 'dcfr' (default (1.5, 0, 2)); ``schedule``: 'simultaneous'
+    (both players' updates in one pass) or 'alternating' (player 1's pass, then player 2's)."""
 
     def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
                  graph: bool = True, stream=None, engine: str = "auto", tuned: bool = True,
-                 dcfr=None):
+                 dcfr=None, schedule: str = "simultaneous"):
         import torch
 
         self._lib = N.load()
         self.variant = variant
         args = GameArgs(game)
-        cfg = make_config(variant, averaging, graph, engine, dcfr)
+        cfg = make_config(variant, averaging, graph, engine, dcfr, schedule)
         info = N.CfrPlanInfo()
         N.check(self._lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg),
                                    ctypes.byref(info)))
@@ -286,7 +292,8 @@ class BatchSolver(Solver):
     ``pair_offsets[g]`` is where game g's pairs start."""
 
     def __init__(self, game_list, variant: str = "cfr+", averaging=None, device: str = "cuda",
-                 graph: bool = True, stream=None, tuned: bool = True, dcfr=None):
+                 graph: bool = True, stream=None, tuned: bool = True, dcfr=None,
+                 schedule: str = "simultaneous"):
         import torch
 
         self._lib = N.load()
@@ -294,7 +301,7 @@ class BatchSolver(Solver):
         self._args = [GameArgs(g) for g in game_list]
         n = len(self._args)
         arr = (N.CfrGame * n)(*[a.struct for a in self._args])
-        cfg = make_config(variant, averaging, graph, dcfr=dcfr)
+        cfg = make_config(variant, averaging, graph, dcfr=dcfr, schedule=schedule)
         info = N.CfrPlanInfo()
         N.check(self._lib.cfr_plan_batch(arr, n, ctypes.byref(cfg), ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}

@@ -100,6 +100,20 @@ def test_config_layout_and_discount_validation():
         plan(g, "dcfr", averaging="linear")
     with pytest.raises(ValueError):
         plan(g, "cfr+", dcfr=(1.0, 1.0, 1.0))
+    assert plan(g, "cfr+", schedule="alternating")["n_q"] == 24
+
+
+def test_unknown_flag_bits_rejected():
+    import ctypes
+
+    from paper_2408_14778_amd import _native as N
+    from paper_2408_14778_amd.solver import GameArgs, make_config
+    lib = N.load()
+    args = GameArgs(games.kuhn_like(3, "joint"))
+    cfg = make_config("cfr+")
+    cfg.flags |= 64
+    info = N.CfrPlanInfo()
+    assert lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg), ctypes.byref(info)) != 0
 
 
 def test_terminal_with_infoset_rejected():

@@ -52,6 +52,33 @@ def test_batch_one_iteration_matches_single_and_oracle(variant):
             assert _rel(Rg, new.R) <= 1e-6 and _rel(Sg, new.S) <= 1e-6
 
 
+def test_batch_alternating_matches_single_and_oracle():
+    """The alternating schedule over a forest: per game, what the single-game solver and the
+    oracle's two passes give."""
+    from paper_2408_14778_amd import BatchSolver, Solver
+    gl = _mixed_games()
+    states = [games.random_state(g, seed=70 + i, nonnegative=True) for i, g in enumerate(gl)]
+    T = 11
+    R = np.concatenate([st[1] for st in states])
+    S = np.concatenate([st[2] for st in states])
+    b = BatchSolver(gl, "cfr+", schedule="alternating")
+    b.set_state(T, R, S)
+    b.iterate(1)
+    Tb, Rb, Sb = b.get_state()
+    assert Tb == T + 1
+    for g, (Rg, Sg), st in zip(gl, zip(b.split(Rb), b.split(Sb)), states):
+        s = Solver(g, "cfr+", schedule="alternating")
+        s.set_state(T, st[1], st[2])
+        s.iterate(1)
+        _, Rs, Ss = s.get_state()
+        assert _rel(Rg, Rs) <= 1e-6 and _rel(Sg, Ss) <= 1e-6
+        if g.n_nodes <= 20000:
+            t = Tree(g)
+            new, _ = cfr.iterate_alternating(t, cfr.State(T, [float(x) for x in st[1]],
+                                                          [float(x) for x in st[2]]), "cfr+")
+            assert _rel(Rg, new.R) <= 1e-6 and _rel(Sg, new.S) <= 1e-6
+
+
 def test_batch_exploitability_per_game():
     from paper_2408_14778_amd import BatchSolver, Solver
     gl = _mixed_games()

@@ -135,6 +135,46 @@ def test_exploitability_after_T_iterations(name, variant, iters, engine):
 
 
 @pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+", "dcfr"])
+@pytest.mark.parametrize("name", ["kuhn", "leduc3x2", "rand_joint", "rand_seq", "rps", "subgame"])
+def test_alternating_one_iteration_parity(name, variant, engine):
+    """Alternating schedule: player 1's pass, then player 2's under player 1's new strategy,
+    one t; from a seeded state, R' and S' within 1e-6 of the oracle's two passes."""
+    g = SMALL_GAMES[name]()
+    T, R, S = games.random_state(g, seed=len(name) + 1, nonnegative=(variant == "cfr+"))
+    s = _solver(g, variant, engine=engine, schedule="alternating")
+    s.set_state(T, R, S)
+    s.iterate(1)
+    T2, R2, S2 = s.get_state()
+    t = Tree(g)
+    new, _ = cfr.iterate_alternating(t, cfr.State(T, [float(x) for x in R], [float(x) for x in S]),
+                                     variant)
+    assert T2 == T + 1
+    assert _rel(R2, new.R) <= 1e-6 and _rel(S2, new.S) <= 1e-6
+
+
+@pytest.mark.parametrize("name,variant,iters", [
+    ("kuhn", "cfr+", 1000),
+    ("rand_seq", "cfr+", 300),
+    ("leduc3x2", "cfr+", 50),
+    ("kuhn", "vanilla", 1000),
+])
+@pytest.mark.parametrize("engine", ENGINES)
+def test_alternating_exploitability_after_T_iterations(name, variant, iters, engine):
+    """As for discounted CFR, the two-round game is compared early (T = 50): alternating
+    CFR+ there amplifies fp32-level differences fast enough that by T = 100 the GPU and
+    oracle runs are about 1.4e-4 apart in exploitability."""
+    g = SMALL_GAMES[name]()
+    s = _solver(g, variant, engine=engine, schedule="alternating")
+    s.iterate(iters)
+    e = s.exploitability()
+    t = Tree(g)
+    st = cfr.solve(t, iters, variant, schedule=cfr.ALTERNATING)
+    ref = br.exploitability(t, cfr.average_strategy(t, st.S))
+    assert abs(e["expl"] - ref["expl"]) <= 1e-4, (e, ref)
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
 def test_medium_game_exploitability_against_golden(variant, engine):
     """1,000 iterations on the medium game against the FP64 oracle's stored result. The
