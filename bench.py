@@ -179,8 +179,9 @@ def warm_start_eval(game_list) -> dict:
     return res
 
 
-def cpu_baseline(seconds_cap: float = 30.0) -> dict:
-    """The FP64 oracle (single-threaded Python) on the first 16 of the 156 deals."""
+def cpu_baseline(seconds_min: float = 10.0) -> dict:
+    """The FP64 oracle (single-threaded Python) on the first 16 of the 156 deals: whole CFR+
+    iterations until at least `seconds_min` of them have run (about 10-15 s)."""
     import games
     from oracle import cfr
     from oracle.tree import Tree
@@ -190,7 +191,7 @@ def cpu_baseline(seconds_cap: float = 30.0) -> dict:
     st = cfr.State.zeros(t)
     t0 = time.perf_counter()
     iters = 0
-    while iters < 3 and time.perf_counter() - t0 < seconds_cap:
+    while iters < 1 or (time.perf_counter() - t0 < seconds_min and iters < 50):
         st, _ = cfr.iterate(t, st, cfr.CFR_PLUS)
         iters += 1
     dt = time.perf_counter() - t0
