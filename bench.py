@@ -314,6 +314,7 @@ def main() -> int:
     achieved = bytes_per_launch / avg_s / 1e9
     iter_bytes = passes * float(sum(algorithmic_bytes(k, counts) for k in ("block_reach", "block_up")))
     attainable = copy_bandwidth()
+    traffic = measured_traffic(dom)  # rocprofv3 HBM bytes per launch of the same kernel
     log(f"plain copy: {attainable:.0f} GB/s")
     kernels = {k: {"launches": n, "avg_us": ms / n * 1e3,
                    "share": ms / sum(v[1] for v in kt.values())} for k, (n, ms) in kt.items()}
@@ -344,7 +345,8 @@ def main() -> int:
                    "engine": ["node", "public-block"][s.info["engine"]],
                    "passes_per_iteration": passes},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": None if traffic is None else traffic / avg_s / 1e9,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
                      "iteration_bytes": iter_bytes, "attainable_copy_gbs": attainable,
                      "iteration_gbs": iter_bytes / (ms_per_step * 1e-3) / 1e9},
