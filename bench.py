@@ -137,9 +137,12 @@ def bench_batch(args, gl) -> dict:
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kt = b.iterate_timed(args.timed_kernel_steps)
-    t1 = time.perf_counter()
-    e = b.exploitability()
-    torch.cuda.synchronize()
+    br_s = []  # the first best response also writes the terminal values once
+    for _ in range(3):
+        t1 = time.perf_counter()
+        e = b.exploitability()
+        torch.cuda.synchronize()
+        br_s.append(time.perf_counter() - t1)
     return {"metric": METRIC, "value": nodes * args.steps / dt, "unit": "node-updates/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -148,7 +151,7 @@ def bench_batch(args, gl) -> dict:
                        "nodes": nodes},
             "kernels": {k: {"launches": n, "avg_us": ms / n * 1e3} for k, (n, ms) in kt.items()},
             "exploitability": {"max": float(np.max(e["expl"])), "median": float(np.median(e["expl"])),
-                               "seconds": time.perf_counter() - t1}}
+                               "seconds_first": br_s[0], "seconds": min(br_s[1:])}}
 
 
 def warm_start_eval(game_list) -> dict:
