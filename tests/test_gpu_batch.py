@@ -20,7 +20,8 @@ def _mixed_games():
     # subgames of several start rounds and depths, plus small games of other shapes
     out = [games.subgame(s) for s in (102, 103, 109, 111, 113)]
     out += [games.kuhn_like(3, "joint"), games.random_game(61, deal="sequential", depth=5),
-            games.leduc_like(3, 2, deal="sequential"), games.rock_paper_scissors()]
+            games.leduc_like(3, 2, deal="sequential"), games.rock_paper_scissors(),
+            games.random_game(66, deal="sequential", depth=30, max_actions=2, p_terminal=0.3)]
     return out
 
 

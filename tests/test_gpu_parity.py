@@ -50,6 +50,8 @@ SMALL_GAMES = {
     "rand_perfect": lambda: games.random_game(23, deal="none", depth=7),
     "rps": lambda: games.rock_paper_scissors(),
     "subgame": lambda: games.subgame(102),
+    # 33 levels: past the single-workgroup kernels' 16 and the path kernel's 5
+    "deep": lambda: games.random_game(66, deal="sequential", depth=30, max_actions=2, p_terminal=0.3),
 }
 
 
@@ -112,6 +114,8 @@ def test_one_iteration_parity(name, variant, engine):
     ("rand_joint", "vanilla", 600),
     ("rand_seq", "cfr+", 600),
     ("leduc3x2", "vanilla", 200),
+    ("deep", "cfr+", 300),
+    ("deep", "vanilla", 300),
     ("kuhn", "dcfr", 1000),
     ("rand_seq", "dcfr", 600),
     ("leduc3x2", "dcfr", 60),
