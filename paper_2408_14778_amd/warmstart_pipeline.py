@@ -259,6 +259,63 @@ def eval_only(args) -> int:
     return 0
 
 
+def select_weight(val, infer, weights, by: str = "seconds") -> tuple:
+    """Evaluates each warm-start weight on the validation games; returns (the chosen weight, the
+    sweep). by='seconds': the least wall time until every validation game reaches the target
+    (the metric itself); by='iterations': the fewest mean per-game iterations to it (less
+    noisy, but blind to the slowest games that set the batch's time)."""
+    sweep = {}
+    for w in weights:
+        r = evaluate(val, infer, w)
+        sweep[w] = r
+        log(f"validation weight {w}: plain {r['plain']['seconds']:.3f}s, mean "
+            f"{r['paired']['mean_iterations_plain']:.0f} it; warm {r['warm']['seconds']:.3f}s, "
+            f"mean {r['paired']['mean_iterations_warm']:.0f} it")
+    if by == "iterations":
+        return min(sweep, key=lambda w: sweep[w]["paired"]["mean_iterations_warm"]), sweep
+    return min(sweep, key=lambda w: sweep[w]["warm"]["seconds"]), sweep
+
+
+def _validation_summary(sweep) -> dict:
+    return {str(w): {"plain_s": r["plain"]["seconds"], "warm_s": r["warm"]["seconds"],
+                     "plain_mean_it": r["paired"]["mean_iterations_plain"],
+                     "warm_mean_it": r["paired"]["mean_iterations_warm"]}
+            for w, r in sweep.items()}
+
+
+def select_only(args) -> int:
+    """Re-chooses the weight of the stored network on the validation games and re-evaluates it
+    on the held-out games (no training); rewrites the weight in the sidecar."""
+    pool = Pool(args.workers)  # forked before this process touches the GPU
+    pend_val = pool.map_async(_subgame, list(range(VAL_SEED, VAL_SEED + args.val_games)), chunksize=4)
+    pend_test = pool.map_async(_subgame, list(range(100, 100 + args.eval_games)), chunksize=4)
+    import torch
+    from . import warmstart as ws
+    torch.cuda.set_device(0)
+    side = os.path.splitext(args.out_weights)[0] + ".json"
+    with open(side) as f:
+        meta = json.load(f)
+    net = ws.WarmStartNet(max_batch=65536)
+    net.set_params(np.load(args.out_weights))
+    weight, sweep = select_weight(pend_val.get(), net, [float(v) for v in args.weights.split(",")],
+                                  args.select_by)
+    gl = pend_test.get()
+    pool.close()
+    res = evaluate(gl, net, weight)
+    res.update({"weight": weight, "eval_games": args.eval_games,
+                "eval_seeds": [100, 99 + args.eval_games], "val_games": args.val_games,
+                "validation": _validation_summary(sweep)})
+    log(json.dumps(res))
+    meta["weight"] = weight
+    meta["selection"] = res
+    with open(side, "w") as f:
+        json.dump(meta, f, indent=1)
+    if args.out_json:
+        with open(args.out_json, "w") as f:
+            json.dump(res, f, indent=1)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-games", type=int, default=20000)
@@ -267,9 +324,11 @@ def main() -> int:
     ap.add_argument("--per-game", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--weights", default="3,10,30,100",
+    ap.add_argument("--weights", default="10,15,20,30,45,60,100",
                     help="warm-start weights tried on the validation games; the best is used")
-    ap.add_argument("--val-games", type=int, default=128)
+    ap.add_argument("--select-by", choices=["seconds", "iterations"], default="seconds",
+                    help="validation criterion for the weight (see select_weight)")
+    ap.add_argument("--val-games", type=int, default=256)
     ap.add_argument("--eval-games", type=int, default=512)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out-weights", default=WEIGHTS_PATH)
@@ -277,9 +336,14 @@ def main() -> int:
     ap.add_argument("--eval-only", action="store_true",
                     help="evaluate the stored network (weights and chosen weight next to "
                          "--out-weights) on the held-out games, without training")
+    ap.add_argument("--select-only", action="store_true",
+                    help="choose the weight of the stored network again on the validation games "
+                         "(--weights, --val-games), then evaluate it on the held-out games")
     args = ap.parse_args()
     if args.eval_only:
         return eval_only(args)
+    if args.select_only:
+        return select_only(args)
     sys.path.insert(0, ROOT)
     # the worker processes are forked before this process touches the GPU
     pool = Pool(args.workers)
@@ -326,15 +390,8 @@ def main() -> int:
     # the weight is chosen on validation games (seeds disjoint from training and evaluation)
     val = pending.get()
     pending = pool.map_async(_subgame, list(range(100, 100 + args.eval_games)), chunksize=4)
-    sweep = {}
-    for w in [float(v) for v in args.weights.split(",")]:
-        r = evaluate(val, infer, w)
-        sweep[w] = r
-        log(f"validation weight {w}: plain {r['plain']['seconds']:.3f}s, mean "
-            f"{r['paired']['mean_iterations_plain']:.0f} it; warm {r['warm']['seconds']:.3f}s, "
-            f"mean {r['paired']['mean_iterations_warm']:.0f} it")
-    # chosen by the mean per-game iterations to the target (less noisy than the slowest game)
-    weight = min(sweep, key=lambda w: sweep[w]["paired"]["mean_iterations_warm"])
+    weight, sweep = select_weight(val, infer, [float(v) for v in args.weights.split(",")],
+                                  args.select_by)
     del val
     gl = pending.get()
     pool.close()
@@ -344,11 +401,7 @@ def main() -> int:
     res.update({"train_games": args.train_games, "solve_iters": args.solve_iters,
                 "samples": int(len(data["desc"])), "losses": losses, "weight": weight,
                 "eval_games": args.eval_games, "eval_seeds": [100, 99 + args.eval_games],
-                "validation": {str(w): {"plain_s": r["plain"]["seconds"],
-                                        "warm_s": r["warm"]["seconds"],
-                                        "plain_mean_it": r["paired"]["mean_iterations_plain"],
-                                        "warm_mean_it": r["paired"]["mean_iterations_warm"]}
-                               for w, r in sweep.items()}})
+                "validation": _validation_summary(sweep)})
     log(json.dumps(res))
     side = os.path.splitext(args.out_weights)[0] + ".json"
     with open(side, "w") as f:
