@@ -286,8 +286,12 @@ def main() -> int:
     # the per-iteration time comes with its standard error over the groups
     groups = [args.steps // 10 + (1 if i < args.steps % 10 else 0) for i in range(10)]
     group_s = []
+    # hipEvents on the solver's stream (torch's current stream) around the whole timed region
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    assert s.stream == torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(s.stream)
     for n in groups:
         if n == 0:
             continue
@@ -295,7 +299,10 @@ def main() -> int:
         s.iterate(n)
         torch.cuda.synchronize()
         group_s.append(((time.perf_counter() - tg) / n))
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gpu_iter_s = ev0.elapsed_time(ev1) * 1e-3 / args.steps
     ms_per_step = dt * 1e3 / args.steps
     per = np.array(group_s) * 1e3
     sem_ms = float(per.std(ddof=1) / np.sqrt(len(per))) if len(per) > 1 else 0.0
@@ -312,7 +319,12 @@ def main() -> int:
     counts = level_counts(lay)
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
-    avg_s = total_ms / launches * 1e-3
+    # per-launch duration of the dominant kernel in the timed graph replays: the event-timed
+    # iteration split by the kernels' shares of the per-launch event times (each launch timed
+    # between two events, outside the graph, which also counts its dispatch gap)
+    share = total_ms / sum(v[1] for v in kt.values())
+    avg_s = gpu_iter_s * share / (launches / args.timed_kernel_steps)
+    avg_direct_s = total_ms / launches * 1e-3
     bytes_per_launch = algorithmic_bytes(dom, counts) * passes * args.timed_kernel_steps / launches
     achieved = bytes_per_launch / avg_s / 1e9
     iter_bytes = passes * float(sum(algorithmic_bytes(k, counts) for k in ("block_reach", "block_up")))
@@ -351,6 +363,8 @@ def main() -> int:
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_gbs": None if traffic is None else traffic / avg_s / 1e9,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
+                     "avg_launch_us_direct": avg_direct_s * 1e6,
+                     "iteration_us_events": gpu_iter_s * 1e6,
                      "iteration_bytes": iter_bytes, "attainable_copy_gbs": attainable,
                      "iteration_gbs": iter_bytes / (ms_per_step * 1e-3) / 1e9},
         "kernels": kernels,
