@@ -1,0 +1,23 @@
+"""Host checks of bench.py's bytes model: the two-sweep streaming model's per-iteration bytes
+for the large game equal the 596.0 MB (27.7 B per node) that the model's derivation gives for
+it, and the per-level counts it is built from add up to the plan's sizes."""
+import numpy as np
+
+import bench
+
+
+def test_streaming_model_of_the_large_game(large_game):
+    from paper_2408_14778_amd.solver import host_layout
+    lay = host_layout(large_game, ["level_offset", "node_player", "parent", "q_offset",
+                                   "child_begin", "member_offset", "members"])
+    counts = bench.level_counts(lay)
+    assert sum(c["nodes"] for c in counts) == large_game.n_nodes == 21509281
+    assert sum(c["infosets"] for c in counts) == 793910
+    assert sum(c["q"] for c in counts) == 2068430
+    reach = bench.algorithmic_bytes("block_reach", counts)
+    up = bench.algorithmic_bytes("block_up", counts)
+    assert round((reach + up) / 1e6, 1) == 596.0
+    assert round((reach + up) / large_game.n_nodes, 1) == 27.7
+    # the node engine's split of the bottom-up terms adds up to the fused kernel's
+    assert np.isclose(bench.algorithmic_bytes("value_level", counts) +
+                      bench.algorithmic_bytes("infoset_update", counts), up)
