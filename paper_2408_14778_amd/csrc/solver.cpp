@@ -444,6 +444,21 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     x.fused_up = cfr::fusable_up_levels(x.m_level_offset_host, x.h_level_offset_host,
                                         x.c_level_offset_host, x.chance_glog_host, P.D,
                                         x.max_actions);
+    // the sigma ranges that the single-workgroup kernels read: pairs and chance probabilities
+    // of the levels above the first one each leaves to per-level launches
+    for (int e = 0; e < 2; ++e) {
+        const int32_t l1 = std::min(e == 0 ? x.fused_reach : x.fused_up, P.D + 1);
+        x.top_q_lo[e] = P.q_offset[P.h_level_offset[0]];
+        x.top_q_hi[e] = P.q_offset[P.h_level_offset[l1]];
+        const int32_t c0 = P.c_level_offset[0], c1 = P.c_level_offset[l1];
+        int32_t clo = 0, chi = 0;
+        for (int32_t c = c0; c < c1; ++c) {
+            clo = c == c0 ? P.chance_base[c] : std::min(clo, P.chance_base[c]);
+            chi = std::max(chi, P.chance_base[c] + P.chance_k[c]);
+        }
+        x.top_c_lo[e] = clo;
+        x.top_c_hi[e] = chi;
+    }
     return apply_shapes(s, st);
 }
 

@@ -19,6 +19,8 @@
 // needed) and give each thread several independent nodes or members.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "xkernels.hpp"
 
 namespace cfr {
@@ -172,13 +174,28 @@ struct LevelTable {
     int32_t glog[kFuseMax];  // log2 lanes per chance node (bottom-up)
 };
 
+// Touches the table's lines: each of the workgroup's kFuseThreads threads loads one byte of
+// its line (or of the range's last line) in every range, all loads issued before the first
+// wait. The bytes themselves are not needed.
+__device__ __forceinline__ void warm_lines(const WarmTable& w, int tid) {
+    if (w.lines[0] == 0) return;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < kWarmMax; ++r) {
+        const int32_t i = tid < w.lines[r] ? tid : w.lines[r] - 1;
+        acc ^= w.p[r][static_cast<int64_t>(i) * kWarmLine];
+    }
+    asm volatile("" ::"v"(acc));
+}
+
 // The first top-down levels in one workgroup: a barrier between levels instead of a launch.
-__global__ void __launch_bounds__(kFuseThreads) k_x_reach_top(LevelTable t, int64_t N,
+__global__ void __launch_bounds__(kFuseThreads) k_x_reach_top(LevelTable t, WarmTable w, int64_t N,
                                                               const int32_t* __restrict__ parent,
                                                               const int32_t* __restrict__ edge,
                                                               const int8_t* __restrict__ meta,
                                                               const float* __restrict__ prob,
                                                               float* __restrict__ reach) {
+    warm_lines(w, threadIdx.x);
     for (int32_t i = 0; i < t.n; ++i) {
         reach_nodes<2>(t.lo[i] + threadIdx.x, kFuseThreads, t.hi[i], N, parent, edge, meta, prob,
                        reach);
@@ -458,10 +475,11 @@ __global__ void __launch_bounds__(CH) k_x_up_level(UpArgs a, int32_t klo, int32_
 
 // The shallowest levels, deepest first, in one workgroup (each level's chance nodes fit one
 // pass of the workgroup); then the iteration is counted (every read of T came before).
-__global__ void __launch_bounds__(kFuseThreads) k_x_up_top(UpArgs a, LevelTable t) {
+__global__ void __launch_bounds__(kFuseThreads) k_x_up_top(UpArgs a, LevelTable t, WarmTable w) {
     __shared__ float s_con[kFuseThreads][4];
     __shared__ float s_own[kFuseThreads];
     const int tid = threadIdx.x;
+    warm_lines(w, tid);
     for (int32_t i = 0; i < t.n; ++i) {
         const int g = t.glog[i];
         const int32_t ci = t.clo[i] + (tid >> g);
@@ -857,6 +875,77 @@ int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_
     return k;
 }
 
+namespace {
+
+// Adds elements [lo, hi) of an array of elem-byte elements to a warm table (empty: skipped;
+// clipped to kFuseThreads lines).
+template <typename E>
+void warm_add(WarmTable& w, int& n, const E* base, int64_t lo, int64_t hi) {
+    if (hi <= lo || n == kWarmMax) return;
+    const int64_t bytes = (hi - lo) * static_cast<int64_t>(sizeof(E));
+    w.p[n] = reinterpret_cast<const uint8_t*>(base + lo);
+    w.lines[n] = static_cast<int32_t>(std::min<int64_t>((bytes + kWarmLine - 1) / kWarmLine,
+                                                        kFuseThreads));
+    ++n;
+}
+
+void warm_fill(WarmTable& w, int n) {
+    for (int r = n; r < kWarmMax; ++r) {
+        w.p[r] = n > 0 ? w.p[0] : nullptr;
+        w.lines[r] = n > 0 ? w.lines[0] : 0;
+    }
+}
+
+// What k_x_reach_top reads: parent, edge and kind of levels 1 .. fr, the reach planes of
+// levels 0 .. fr - 1 and sigma at those levels' pairs and chance probabilities.
+WarmTable reach_warm(const XDev& x, int32_t fr) {
+    WarmTable w{};
+    int n = 0;
+    const int32_t* lo = x.level_offset_host;
+    warm_add(w, n, x.reach, lo[0], lo[fr]);
+    warm_add(w, n, x.reach + x.N, lo[0], lo[fr]);
+    warm_add(w, n, x.reach + 2 * x.N, lo[0], lo[fr]);
+    warm_add(w, n, x.parent, lo[1], lo[1 + fr]);
+    warm_add(w, n, x.edge, lo[1], lo[1 + fr]);
+    warm_add(w, n, x.meta, lo[1], lo[1 + fr]);
+    warm_add(w, n, x.prob, x.top_q_lo[0], x.top_q_hi[0]);
+    warm_add(w, n, x.prob, x.top_c_lo[0], x.top_c_hi[0]);
+    warm_fill(w, n);
+    return w;
+}
+
+// What k_x_up_top reads at levels 0 .. fu - 1: chunk, member and infoset records, chance
+// tables, child offsets, the three reach planes, the children's values (one level deeper)
+// and the infosets' regrets, average and sigma, and the chance probabilities.
+WarmTable up_warm(const XDev& x, int32_t fu) {
+    WarmTable w{};
+    int n = 0;
+    const int32_t* lo = x.level_offset_host;
+    const int32_t l1 = std::min(fu + 1, x.D + 1);
+    warm_add(w, n, x.value, lo[0], lo[l1]);
+    warm_add(w, n, x.chunk_first, x.k_level_offset_host[0], x.k_level_offset_host[fu] + 1);
+    warm_add(w, n, x.chunk_m, x.k_level_offset_host[0], x.k_level_offset_host[fu] + 1);
+    warm_add(w, n, x.mem_rec, x.m_level_offset_host[0], x.m_level_offset_host[fu]);
+    warm_add(w, n, x.mem_kp, x.m_level_offset_host[0], x.m_level_offset_host[fu]);
+    warm_add(w, n, x.set_rec, x.h_level_offset_host[0], x.h_level_offset_host[fu]);
+    warm_add(w, n, x.chance_nodes, x.c_level_offset_host[0], x.c_level_offset_host[fu]);
+    warm_add(w, n, x.chance_base, x.c_level_offset_host[0], x.c_level_offset_host[fu]);
+    warm_add(w, n, x.chance_k, x.c_level_offset_host[0], x.c_level_offset_host[fu]);
+    warm_add(w, n, x.child_begin, lo[0], lo[fu]);
+    warm_add(w, n, x.child_stride, lo[0], lo[fu]);
+    warm_add(w, n, x.reach, lo[0], lo[fu]);
+    warm_add(w, n, x.reach + x.N, lo[0], lo[fu]);
+    warm_add(w, n, x.reach + 2 * x.N, lo[0], lo[fu]);
+    warm_add(w, n, x.R, x.top_q_lo[1], x.top_q_hi[1]);
+    warm_add(w, n, x.S, x.top_q_lo[1], x.top_q_hi[1]);
+    warm_add(w, n, x.prob, x.top_q_lo[1], x.top_q_hi[1]);
+    warm_add(w, n, x.prob, x.top_c_lo[1], x.top_c_hi[1]);
+    warm_fill(w, n);
+    return w;
+}
+
+}  // namespace
+
 void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, LaunchTimer* timer) {
     auto pre = [&](int k, int l, int64_t n) { if (timer) timer->before(k, l, n, st); };
     auto post = [&](int k) { if (timer) timer->after(k, st); };
@@ -871,7 +960,8 @@ void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, L
             t.hi[i] = lo[2 + i];
         }
         pre(XK_REACH, -1, lo[1 + fr] - lo[1]);
-        hipLaunchKernelGGL(k_x_reach_top, dim3(1), dim3(kFuseThreads), 0, st, t, x.N, x.parent,
+        hipLaunchKernelGGL(k_x_reach_top, dim3(1), dim3(kFuseThreads), 0, st, t, reach_warm(x, fr),
+                           x.N, x.parent,
                            x.edge, x.meta, x.prob, x.reach);
         post(XK_REACH);
     }
@@ -917,7 +1007,7 @@ void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, L
             t.glog[i] = x.chance_glog_host[l];
         }
         pre(XK_UP, -1, x.m_level_offset_host[fu] - x.m_level_offset_host[0]);
-        hipLaunchKernelGGL(k_x_up_top, dim3(1), dim3(kFuseThreads), 0, st, a, t);
+        hipLaunchKernelGGL(k_x_up_top, dim3(1), dim3(kFuseThreads), 0, st, a, t, up_warm(x, fu));
         post(XK_UP);
     } else if (rule.count) {
         // the linear-averaging weight of every launch above read T: count the iteration last

@@ -26,6 +26,17 @@ constexpr int kFuseThreads = 1024;
 constexpr int kPathDepth = 5;
 constexpr int64_t kPathNodes = 200000;
 constexpr int kPathThreads = 256;
+// Byte ranges that a single-workgroup kernel reads, touched once before its level chain (one
+// byte per kWarmLine-byte line, every load in flight together), so that the chain's dependent
+// loads find their lines in the L2 cache of the workgroup's XCD instead of going to memory
+// one level at a time. Every entry is a valid range (unused ones repeat entry 0); lines[0]
+// == 0: no ranges.
+constexpr int kWarmMax = 18;
+constexpr int kWarmLine = 64;
+struct WarmTable {
+    const uint8_t* p[kWarmMax];
+    int32_t lines[kWarmMax];  // 1 .. kFuseThreads lines each
+};
 
 struct XDev {
     int64_t N, Hp, Qp, Q0, M, L, C;
@@ -53,6 +64,10 @@ struct XDev {
     // top-down levels fused_reach + 1 .. path_reach run in one path launch (path_reach <=
     // fused_reach: none)
     int32_t path_reach;
+    // pair ranges [lo, hi) of prob that the single-workgroup kernels read (host): the infosets'
+    // pairs and the chance probabilities of levels 0 .. fused_reach - 1 (entry 0) and
+    // 0 .. fused_up - 1 (entry 1)
+    int32_t top_q_lo[2], top_q_hi[2], top_c_lo[2], top_c_hi[2];
     // plan arrays (exec order)
     int32_t* parent;
     int32_t* edge;
