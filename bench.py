@@ -63,22 +63,27 @@ def level_counts(lay: dict) -> list:
     return out
 
 
-def algorithmic_bytes(kernel: str, counts: list) -> float:
+def algorithmic_bytes(kernel: str, counts: list, reach_launch=None) -> float:
     """Bytes `kernel` must move per iteration under the two-sweep streaming model (fp32 values,
     int32 indices; N_int = internal nodes, chance included; only internal nodes need reach):
     top-down, per internal non-root node, parent index and edge label 8, parent reach 8 and
     its own reach 8 (24 B); bottom-up, per node read as a child its value 12 with its
     structure, per internal node its value write and the acting player's reach 8, per pair
     36 (R and S read and written, the instantaneous regret, sigma read and written, sigma
-    gathers) and per infoset 8. A kernel's launches over one iteration move the sum of the
-    levels they process; the per-launch figure is that sum divided by the launches.
-    block_reach / reach_level: top-down; block_up: bottom-up (values, regrets and the
-    infoset update fused); value_level and infoset_update: the node engine's split of the
-    bottom-up terms.
+    gathers) and per infoset 8. A level whose reach its bottom-up launch computes
+    (reach_launch[l] == 4, the solver's reach_launch layout) needs no reach written and read
+    back: its bottom-up launch moves 12 B more per internal node (parent index, edge label and
+    parent reach, less the reach read) and the top-down pass nothing for it. A kernel's
+    launches over one iteration move the sum of the levels they process; the per-launch figure
+    is that sum divided by the launches. block_reach / reach_level: top-down; block_up:
+    bottom-up (values, regrets and the infoset update fused); value_level and infoset_update:
+    the node engine's split of the bottom-up terms.
     """
     D = len(counts) - 1
-    reach = sum(24 * c["decision"] for c in counts[1:D])
+    fused = [l for l in range(D + 1) if reach_launch is not None and reach_launch[l] == 4]
+    reach = sum(24 * counts[l]["decision"] for l in range(1, D) if l not in fused)
     values = sum(12 * counts[l + 1]["nodes"] + 8 * counts[l]["decision"] for l in range(D))
+    values += sum(12 * counts[l]["decision"] for l in fused)
     infoset = sum(36 * c["q"] + 8 * c["infosets"] for c in counts)
     return float({"block_reach": reach, "reach_level": reach, "block_up": values + infoset,
                   "value_level": values, "infoset_update": infoset}.get(kernel, 0.0))
@@ -317,6 +322,7 @@ def main() -> int:
     lay = {k: s.layout(k) for k in ("level_offset", "node_player", "parent", "q_offset",
                                      "child_begin", "member_offset", "members")}
     counts = level_counts(lay)
+    rl = s.layout("reach_launch")
     dom = max(kt, key=lambda k: kt[k][1])
     launches, total_ms = kt[dom]
     # per-launch duration of the dominant kernel in the timed graph replays: the event-timed
@@ -325,9 +331,9 @@ def main() -> int:
     share = total_ms / sum(v[1] for v in kt.values())
     avg_s = gpu_iter_s * share / (launches / args.timed_kernel_steps)
     avg_direct_s = total_ms / launches * 1e-3
-    bytes_per_launch = algorithmic_bytes(dom, counts) * passes * args.timed_kernel_steps / launches
+    bytes_per_launch = algorithmic_bytes(dom, counts, rl) * passes * args.timed_kernel_steps / launches
     achieved = bytes_per_launch / avg_s / 1e9
-    iter_bytes = passes * float(sum(algorithmic_bytes(k, counts) for k in ("block_reach", "block_up")))
+    iter_bytes = passes * float(sum(algorithmic_bytes(k, counts, rl) for k in ("block_reach", "block_up")))
     attainable = copy_bandwidth()
     traffic = measured_traffic(dom)  # rocprofv3 HBM bytes per launch of the same kernel
     log(f"plain copy: {attainable:.0f} GB/s")

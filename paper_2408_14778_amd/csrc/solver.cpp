@@ -279,6 +279,29 @@ cfr::UpdateRule rule_of(const cfr_config& c) {
     return u;
 }
 
+// Per level, which launch computes its top-down reach (0: none, the roots; 1: the
+// single-workgroup launch of the first levels; 2: the launch of several small levels; 3: a
+// launch of its own; 4: the level's bottom-up launch).
+// Deepest level of the solver's iteration (a batch: of its forest).
+int32_t launch_depth(const cfr_solver* s) {
+    return s->engine == ENGINE_BLOCK ? s->xdev.D : s->dev.D;
+}
+
+std::vector<int32_t> reach_launch(const cfr_solver* s) {
+    const int32_t D = launch_depth(s);
+    std::vector<int32_t> r(D + 1, 3);
+    r[0] = 0;
+    if (s->engine != ENGINE_BLOCK) return r;
+    const cfr::XDev& x = s->xdev;
+    for (int32_t l = 1; l <= D; ++l) {
+        if (l <= x.fused_reach) r[l] = 1;
+        else if (l <= x.path_reach) r[l] = 2;
+    }
+    if (const int32_t ld = cfr::derived_reach_level(x); ld >= 0) r[ld] = 4;
+    return r;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -816,9 +839,11 @@ int cfr_set_state(cfr_solver* s, int64_t T, const float* R, const float* S, int6
 }
 
 int64_t cfr_layout_bytes(cfr_solver* s, const char* name) {
-    if (s == nullptr || name == nullptr || !s->canonical) return CFR_EINVAL;
-    const cfr::Dev& d = s->dev;
+    if (s == nullptr || name == nullptr) return CFR_EINVAL;
     const std::string n(name);
+    if (n == "reach_launch") return (launch_depth(s) + 1) * 4;  // batches too
+    if (!s->canonical) return CFR_EINVAL;
+    const cfr::Dev& d = s->dev;
     if (n == "level_offset") return (d.D + 2) * 4;
     if (n == "node_id" || n == "parent" || n == "node_infoset" || n == "node_edge") return d.N * 4;
     if (n == "child_begin") return (d.N + 1) * 4;
@@ -835,12 +860,18 @@ int64_t cfr_layout_bytes(cfr_solver* s, const char* name) {
     return CFR_EINVAL;
 }
 
+
 int cfr_get_layout(cfr_solver* s, const char* name, void* out, int64_t bytes) {
     const int64_t need = cfr_layout_bytes(s, name);
     if (need < 0) return set_err(CFR_EINVAL, "unknown layout array");
     if (out == nullptr || bytes != need) return set_err(CFR_EINVAL, "wrong output size");
     const cfr::Dev& d = s->dev;
     const std::string n(name);
+    if (n == "reach_launch") {
+        const std::vector<int32_t> r = reach_launch(s);
+        std::memcpy(out, r.data(), bytes);
+        return CFR_OK;
+    }
     const void* src = nullptr;
     if (n == "level_offset") src = d.level_offset;
     else if (n == "node_id") src = d.node_id;

@@ -220,12 +220,44 @@ struct UpArgs {
     const int32_t* chance_k;
     float* prob;
     float* value;
-    const float* reach;
+    float* reach;
     float* R;
     float* S;
     int64_t* T;
     UpdateRule rule;
+    // derive_reach != 0 (the deepest decision level, whose children are all terminal): the
+    // level had no top-down launch; a member's reach is its parent's times its edge probability
+    // on the factor of whoever acted (the top-down products), computed and stored here
+    int32_t derive_reach;
+    const int32_t* parent;
+    const int32_t* edge;
+    const int8_t* meta;
 };
+
+// The three reach planes of member node x: loaded, or (derive_reach) computed from the
+// parent's as the top-down pass would and stored.
+__device__ __forceinline__ void member_reach(const UpArgs& a, int32_t x, float& r1, float& r2,
+                                             float& rc) {
+    if (!a.derive_reach) {
+        r1 = a.reach[x];
+        r2 = a.reach[a.N + x];
+        rc = a.reach[2 * a.N + x];
+        return;
+    }
+    const int kind = a.meta[x];
+    const int32_t p = a.parent[x], e = a.edge[x];
+    r1 = a.reach[p];
+    r2 = a.reach[a.N + p];
+    rc = a.reach[2 * a.N + p];
+    const float s = a.prob[e];
+    const int actor = kind >> 2;  // 1 chance, 2 player 1, 3 player 2
+    if (actor == 2) r1 *= s;
+    else if (actor == 3) r2 *= s;
+    else rc *= s;
+    a.reach[x] = r1;
+    a.reach[a.N + x] = r2;
+    a.reach[2 * a.N + x] = rc;
+}
 
 // Chance node ci (if ok) on a group of 2^glog lanes: lane l sums children l, l + 2^glog, ...,
 // then a butterfly over the group (a fixed order). Every lane of the wavefront must call it
@@ -365,11 +397,7 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
         for (int u = 0; u < MPT; ++u) {
             r1[u] = r2[u] = rc[u] = 0.0f;
             const int kk = kp[u] & 31;
-            if (kk > 0) {
-                r1[u] = a.reach[x[u]];
-                r2[u] = a.reach[a.N + x[u]];
-                rc[u] = a.reach[2 * a.N + x[u]];
-            }
+            if (kk > 0) member_reach(a, x[u], r1[u], r2[u], rc[u]);
 #pragma unroll
             for (int j = 0; j < KMAX; ++j) {
                 w[u][j] = sg[u][j] = 0.0f;
@@ -417,7 +445,8 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
                 }
             }
             a.value[xm] = v;
-            const float r1 = a.reach[xm], r2 = a.reach[a.N + xm], rc = a.reach[2 * a.N + xm];
+            float r1, r2, rc;
+            member_reach(a, xm, r1, r2, rc);
             const bool p2 = (kpm & 64) != 0;
             const float cf = (p2 ? r1 : r2) * rc;
             own += p2 ? r2 : r1;
@@ -794,6 +823,10 @@ UpArgs up_args(const XDev& x, const UpdateRule& rule) {
     a.S = x.S;
     a.T = x.T;
     a.rule = rule;
+    a.derive_reach = 0;
+    a.parent = x.parent;
+    a.edge = x.edge;
+    a.meta = x.meta;
     return a;
 }
 
@@ -946,6 +979,16 @@ WarmTable up_warm(const XDev& x, int32_t fu) {
 
 }  // namespace
 
+int32_t derived_reach_level(const XDev& x) {
+    // the deepest decision level (its children are all terminal), when it has a launch of its
+    // own on both sweeps and no chance nodes
+    const int32_t ld = x.D - 1;
+    const int32_t top = x.path_reach > x.fused_reach ? x.path_reach : x.fused_reach;
+    const bool ok = ld >= 1 + top && ld >= x.fused_up &&
+                    x.c_level_offset_host[ld + 1] == x.c_level_offset_host[ld];
+    return ok ? ld : -1;
+}
+
 void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, LaunchTimer* timer) {
     auto pre = [&](int k, int l, int64_t n) { if (timer) timer->before(k, l, n, st); };
     auto post = [&](int k) { if (timer) timer->after(k, st); };
@@ -977,22 +1020,28 @@ void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, L
             post(XK_REACH);
         }
     }
+    const int32_t ld = derived_reach_level(x);
+    const bool derive = ld >= 0;
     for (int32_t l = 1 + (fp > fr ? fp : fr); l < x.D; ++l) {
         if (x.t_level_offset_host[l + 1] == x.t_level_offset_host[l]) continue;
+        if (derive && l == ld) continue;
         pre(XK_REACH, l, x.reach_units_host[l]);
         launch_reach_level(x, l, st);
         post(XK_REACH);
     }
     // bottom-up: a launch per deep level, then the shallow levels in one workgroup
     const UpArgs a = up_args(x, rule);
+    UpArgs ad = a;
+    ad.derive_reach = 1;
     const int32_t fu = x.fused_up;
     for (int32_t l = x.D; l >= fu; --l) {
         const int32_t nunits = x.h_level_offset_host[l + 1] - x.h_level_offset_host[l] +
                                x.c_level_offset_host[l + 1] - x.c_level_offset_host[l];
         if (nunits == 0) continue;
+        const UpArgs& al = derive && l == ld ? ad : a;
         pre(XK_UP, l, x.m_level_offset_host[l + 1] - x.m_level_offset_host[l]);
-        if (x.max_actions <= 4) launch_up<4>(x, a, l, st);
-        else launch_up<16>(x, a, l, st);
+        if (x.max_actions <= 4) launch_up<4>(x, al, l, st);
+        else launch_up<16>(x, al, l, st);
         post(XK_UP);
     }
     if (fu > 0) {

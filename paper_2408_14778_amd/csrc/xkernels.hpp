@@ -114,6 +114,10 @@ int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_
                           const int32_t* c_level_offset, const int32_t* chance_glog, int32_t D,
                           int32_t max_actions);
 
+// The level whose top-down reach its bottom-up launch computes (from the parents' stored
+// reach) instead of a top-down launch of its own, or -1.
+int32_t derived_reach_level(const XDev& x);
+
 void launch_x_reset(const XDev& x, hipStream_t st);
 void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st,
                         LaunchTimer* timer = nullptr);

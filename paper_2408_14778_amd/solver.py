@@ -23,6 +23,8 @@ LAYOUT_DTYPES = {
     "chance_id": np.int32, "cq_offset": np.int32, "member_offset": np.int32,
     "members": np.int32, "chance_prob": np.float32, "payoff": np.float32, "q_input": np.int32,
 }
+# per-solver launch facts exported by the same call (not part of the canonical layout)
+SOLVER_LAYOUT_DTYPES = {"reach_launch": np.int32}
 
 
 def _ptr(a: np.ndarray, ctype):
@@ -259,7 +261,7 @@ class Solver:
         nbytes = self._lib.cfr_layout_bytes(self._h, name.encode())
         if nbytes < 0:
             raise KeyError(name)
-        dt = np.dtype(LAYOUT_DTYPES[name])
+        dt = np.dtype(LAYOUT_DTYPES.get(name) or SOLVER_LAYOUT_DTYPES[name])
         out = np.empty(nbytes // dt.itemsize, dtype=dt)
         N.check(self._lib.cfr_get_layout(self._h, name.encode(),
                                           out.ctypes.data_as(ctypes.c_void_p), nbytes))

@@ -1,6 +1,7 @@
 """Host checks of bench.py's bytes model: the two-sweep streaming model's per-iteration bytes
 for the large game equal the 596.0 MB (27.7 B per node) that the model's derivation gives for
-it, and the per-level counts it is built from add up to the plan's sizes."""
+it (594.1 MB with the deepest decision level's reach taken in its bottom-up launch), and the
+per-level counts it is built from add up to the plan's sizes."""
 import numpy as np
 
 import bench
@@ -18,6 +19,16 @@ def test_streaming_model_of_the_large_game(large_game):
     up = bench.algorithmic_bytes("block_up", counts)
     assert round((reach + up) / 1e6, 1) == 596.0
     assert round((reach + up) / large_game.n_nodes, 1) == 27.7
+    # the deepest decision level (14) with its reach taken in its bottom-up launch: 24 B per
+    # internal node leave the top-down pass, 12 B join the bottom-up one
+    rl = np.full(16, 3, dtype=np.int32)
+    rl[0] = 0
+    rl[14] = 4
+    assert counts[14]["decision"] == 154440
+    assert bench.algorithmic_bytes("block_reach", counts, rl) == reach - 24 * 154440
+    assert bench.algorithmic_bytes("block_up", counts, rl) == up + 12 * 154440
+    assert round((bench.algorithmic_bytes("block_reach", counts, rl) +
+                  bench.algorithmic_bytes("block_up", counts, rl)) / 1e6, 1) == 594.1
     # the node engine's split of the bottom-up terms adds up to the fused kernel's
     assert np.isclose(bench.algorithmic_bytes("value_level", counts) +
                       bench.algorithmic_bytes("infoset_update", counts), up)

@@ -17,11 +17,14 @@ def _rel(a, b):
 
 
 def _mixed_games():
-    # subgames of several start rounds and depths, plus small games of other shapes
+    # subgames of several start rounds and depths, plus small games of other shapes; the last
+    # one (33 levels) alone reaches the forest's deepest decision level, which has no chance
+    # node, so the forest takes that level's reach in its bottom-up launch
     out = [games.subgame(s) for s in (102, 103, 109, 111, 113)]
     out += [games.kuhn_like(3, "joint"), games.random_game(61, deal="sequential", depth=5),
             games.leduc_like(3, 2, deal="sequential"), games.rock_paper_scissors(),
-            games.random_game(66, deal="sequential", depth=30, max_actions=2, p_terminal=0.3)]
+            games.random_game(64, deal="sequential", depth=30, max_actions=2, p_terminal=0.3,
+                              p_chance=0.05)]
     return out
 
 
@@ -36,6 +39,8 @@ def test_batch_one_iteration_matches_single_and_oracle(variant):
     S = np.concatenate([st[2] for st in states])
     b = BatchSolver(gl, variant)
     assert b.n_q == len(R)
+    rl = b.layout("reach_launch")
+    assert rl[len(rl) - 2] == 4  # the deepest decision level: reach in its bottom-up launch
     b.set_state(T, R, S)
     b.iterate(1)
     Tb, Rb, Sb = b.get_state()

@@ -52,6 +52,10 @@ SMALL_GAMES = {
     "subgame": lambda: games.subgame(102),
     # 33 levels: past the single-workgroup kernels' 16 and the path kernel's 5
     "deep": lambda: games.random_game(66, deal="sequential", depth=30, max_actions=2, p_terminal=0.3),
+    # 33 levels, no chance node on the deepest decision level: its reach is taken in its
+    # bottom-up launch
+    "deep_nochance": lambda: games.random_game(64, deal="sequential", depth=30, max_actions=2,
+                                               p_terminal=0.3, p_chance=0.05),
 }
 
 
@@ -64,6 +68,25 @@ def test_device_layout_bit_exact(name):
               "node_edge", "infoset_id", "infoset_player", "q_offset", "chance_id", "cq_offset",
               "member_offset", "members", "chance_prob", "payoff", "q_input"):
         assert np.array_equal(s.layout(k), ref[k]), k
+
+
+def test_deepest_level_reach_in_its_bottom_up_launch():
+    """The deepest decision level of deep_nochance (children all terminal, no chance nodes)
+    takes its reach in its bottom-up launch, so that game's one-iteration parity (reach of
+    every decision node, values, R, S) covers that path; the deep game (chance nodes on that
+    level) and the node engine launch every level."""
+    g = SMALL_GAMES["deep_nochance"]()
+    s = _solver(g)
+    D = s.info["depth"]
+    rl = s.layout("reach_launch")
+    assert rl.shape == (D + 1,) and rl[0] == 0
+    assert rl[D - 1] == 4
+    assert np.all(rl[1:D - 1] != 4) and np.all(rl[1:] != 0)
+    assert np.all(np.diff(rl[1:D - 1]) >= 0)  # first levels, then the path, then their own
+    rn = _solver(g, engine="node").layout("reach_launch")
+    assert rn[0] == 0 and np.all(rn[1:] == 3)
+    gd = SMALL_GAMES["deep"]()
+    assert np.all(_solver(gd).layout("reach_launch") != 4)
 
 
 @pytest.mark.parametrize("engine", ENGINES)
