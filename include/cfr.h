@@ -199,8 +199,9 @@ int cfr_set_state(cfr_solver* s, int64_t T, const float* R, const float* S, int6
  * level_offset, node_id, parent, child_begin, node_player, node_infoset, node_edge,
  * infoset_id, infoset_player, q_offset, chance_id, cq_offset, member_offset, members,
  * chance_prob, payoff, q_input; or reach_launch: int32 per level 0 .. D, which launch of an
- * iteration computes the level's reach (0: none, the roots; 1: the single-workgroup launch of
- * the first levels; 2: the launch of several small levels; 3: a launch of its own; 4: the
+ * iteration computes the level's reach (0: none, the roots and levels without decision nodes;
+ * 1: the single-workgroup launch of the first levels; 2: the launch that walks several small
+ * levels up to the last stored one; 3: a launch of its own; 4: the
  * level's bottom-up launch, from the parents' reach; for a batch, the levels of its forest).
  * cfr_layout_bytes returns the size (< 0 for an unknown name, or for a batch any name but
  * reach_launch). */

@@ -279,9 +279,9 @@ cfr::UpdateRule rule_of(const cfr_config& c) {
     return u;
 }
 
-// Per level, which launch computes its top-down reach (0: none, the roots; 1: the
-// single-workgroup launch of the first levels; 2: the launch of several small levels; 3: a
-// launch of its own; 4: the level's bottom-up launch).
+// Per level, which launch computes its top-down reach (0: none, the roots and levels without
+// decision nodes; 1: the single-workgroup launch of the first levels; 2: the launch of several
+// small levels; 3: a launch of its own; 4: the level's bottom-up launch).
 // Deepest level of the solver's iteration (a batch: of its forest).
 int32_t launch_depth(const cfr_solver* s) {
     return s->engine == ENGINE_BLOCK ? s->xdev.D : s->dev.D;
@@ -291,10 +291,12 @@ std::vector<int32_t> reach_launch(const cfr_solver* s) {
     const int32_t D = launch_depth(s);
     std::vector<int32_t> r(D + 1, 3);
     r[0] = 0;
+    r[D] = 0;  // the deepest level holds only terminal nodes
     if (s->engine != ENGINE_BLOCK) return r;
     const cfr::XDev& x = s->xdev;
     for (int32_t l = 1; l <= D; ++l) {
-        if (l <= x.fused_reach) r[l] = 1;
+        if (x.reach_units_host[l] == 0) r[l] = 0;
+        else if (l <= x.fused_reach) r[l] = 1;
         else if (l <= x.path_reach) r[l] = 2;
     }
     if (const int32_t ld = cfr::derived_reach_level(x); ld >= 0) r[ld] = 4;
@@ -463,7 +465,14 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     x.c_level_offset_host = s->x_c_level_offset.data();
     x.chance_glog_host = s->chance_glog.data();
     x.fused_reach = cfr::fusable_reach_levels(x.level_offset_host, P.D);
-    x.path_reach = cfr::path_reach_levels(s->reach_units.data(), x.fused_reach, P.D);
+    x.path_reach = cfr::path_reach_levels(s->reach_units.data(), x.fused_reach, P.D,
+                                          cfr::kPathDepthBelowTop);
+    // the path launch alone, from the roots, when it covers as many levels: one launch fewer
+    const int32_t p0 = cfr::path_reach_levels(s->reach_units.data(), 0, P.D, cfr::kPathDepth);
+    if (x.path_reach > x.fused_reach && p0 >= x.path_reach) {
+        x.fused_reach = 0;
+        x.path_reach = p0;
+    }
     x.fused_up = cfr::fusable_up_levels(x.m_level_offset_host, x.h_level_offset_host,
                                         x.c_level_offset_host, x.chance_glog_host, P.D,
                                         x.max_actions);

@@ -887,11 +887,12 @@ int32_t fusable_reach_levels(const int32_t* level_offset, int32_t D) {
     return k;
 }
 
-int32_t path_reach_levels(const int64_t* units, int32_t fused, int32_t D) {
-    // levels fused + 1 .. l with at most kPathNodes decision nodes each and at most kPathDepth
-    // levels below the last stored one
+int32_t path_reach_levels(const int64_t* units, int32_t fused, int32_t D, int32_t max_depth) {
+    // levels fused + 1 .. l with at most kPathNodes decision nodes each and at most max_depth
+    // (<= kPathDepth) levels below the last stored one
+    const int32_t depth = max_depth < kPathDepth ? max_depth : kPathDepth;
     int32_t l = fused;
-    while (l + 1 < D && l + 1 - fused <= kPathDepth && units[l + 1] <= kPathNodes) ++l;
+    while (l + 1 < D && l + 1 - fused <= depth && units[l + 1] <= kPathNodes) ++l;
     return l;
 }
 

@@ -22,8 +22,12 @@ int shape_bucket(int64_t units);
 constexpr int kFuseMax = 16;
 constexpr int kFuseThreads = 1024;
 // Top-down levels after those computed in one launch by walking up to the last stored level:
-// at most kPathDepth levels of at most kPathNodes decision nodes; tiles of kPathThreads nodes.
-constexpr int kPathDepth = 5;
+// levels of at most kPathNodes decision nodes, at most kPathDepthBelowTop of them below the
+// single-workgroup levels, or at most kPathDepth from the roots when that covers as many
+// levels as both launches (then there is no single-workgroup top-down launch); tiles of
+// kPathThreads nodes.
+constexpr int kPathDepth = 7;
+constexpr int kPathDepthBelowTop = 5;
 constexpr int64_t kPathNodes = 200000;
 constexpr int kPathThreads = 256;
 // Byte ranges that a single-workgroup kernel reads, touched once before its level chain (one
@@ -109,7 +113,8 @@ struct XDev {
 
 // How many first levels the single-workgroup kernels take (from the plan's level tables).
 int32_t fusable_reach_levels(const int32_t* level_offset, int32_t D);
-int32_t path_reach_levels(const int64_t* decision_nodes_per_level, int32_t fused, int32_t D);
+int32_t path_reach_levels(const int64_t* decision_nodes_per_level, int32_t fused, int32_t D,
+                          int32_t max_depth);
 int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_offset,
                           const int32_t* c_level_offset, const int32_t* chance_glog, int32_t D,
                           int32_t max_actions);

@@ -79,14 +79,23 @@ def test_deepest_level_reach_in_its_bottom_up_launch():
     s = _solver(g)
     D = s.info["depth"]
     rl = s.layout("reach_launch")
-    assert rl.shape == (D + 1,) and rl[0] == 0
+    assert rl.shape == (D + 1,) and rl[0] == 0 and rl[D] == 0  # roots; terminals only
     assert rl[D - 1] == 4
-    assert np.all(rl[1:D - 1] != 4) and np.all(rl[1:] != 0)
+    assert np.all(rl[1:D - 1] != 4) and np.all(rl[1:D] != 0)
     assert np.all(np.diff(rl[1:D - 1]) >= 0)  # first levels, then the path, then their own
+    assert rl[1] == 1  # 33 tiny levels: the single-workgroup launch takes the first 16
     rn = _solver(g, engine="node").layout("reach_launch")
-    assert rn[0] == 0 and np.all(rn[1:] == 3)
+    assert rn[0] == 0 and np.all(rn[1:D] == 3) and rn[D] == 0
     gd = SMALL_GAMES["deep"]()
     assert np.all(_solver(gd).layout("reach_launch") != 4)
+
+
+def test_large_game_launch_plan(large_game):
+    """The large game's top-down launches: levels 1-7 (at most 175,032 decision nodes each) in
+    the launch that walks up to the roots, levels 8-13 one launch each, level 14 (the deepest
+    decision level, no chance nodes) in its bottom-up launch, level 15 terminal only."""
+    s = _solver(large_game, "cfr+")
+    assert s.layout("reach_launch").tolist() == [0] + [2] * 7 + [3] * 6 + [4, 0]
 
 
 @pytest.mark.parametrize("engine", ENGINES)
