@@ -74,7 +74,7 @@ typedef struct cfr_game {
  *   CFR_PLUS     R = max(R + r~, 0)
  *   CFR_DCFR     R = (R + r~) * t^a / (t^a + 1) where R + r~ > 0, else (R + r~) * t^b / (t^b + 1);
  *                and the strategy sums S = (S + pibar * sigma) * (t / (t + 1))^g
- * The discounted variant is the weighting scheme the paper's discussion (Section 6) says
+ * The discounted variant is the weighting scheme the paper's discussion (Section 5) says
  * applies by altering the average-regret and average-strategy equations; a, b, g are
  * cfr_config.dcfr_alpha, dcfr_beta, dcfr_gamma. */
 enum { CFR_VANILLA = 0, CFR_PLUS = 1, CFR_DCFR = 2 };

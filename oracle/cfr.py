@@ -38,7 +38,7 @@ cumulative regrets clipped at zero after each update, linear averaging with no
 delay, the same simultaneous schedule and the same uniform fallback.
 
 Discounted CFR (DCFR with parameters alpha, beta, gamma) is the discounting of
-the cited weighting work, which the paper's discussion (Section 6) says enters
+the cited weighting work, which the paper's discussion (Section 5) says enters
 only through the average-regret and average-strategy equations. Read here, for
 iteration t = T + 1 (1-based) and the same r~, pibar and sigma as above:
    R(h,a) <- (R + r~) * t^alpha / (t^alpha + 1)   where R + r~ > 0,
@@ -50,7 +50,7 @@ weight that grows as t^alpha; alpha = beta = gamma = 1 is linear CFR up to a
 positive scale, which the tests use as an independent pin.
 
 Alternating updates (the schedule of the CFR+ work the paper cites, which the
-discussion of Section 6 names as applicable to the matrix formulation): one
+discussion of Section 5 names as applicable to the matrix formulation): one
 iteration is two passes of steps 1-4 with the same t. The first updates only
 player 1's infosets (R, S, and so its strategy); the second, which sees player
 1's new strategy, updates only player 2's; then T += 1.
@@ -122,9 +122,13 @@ def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = Fal
     """One CFR iteration. Returns (new_state, info); ``info`` holds sigma, r~,
     pibar and, if ``record``, per-node expected payoff u1 and reaches. ``dcfr`` holds
     (alpha, beta, gamma) for the discounted variant. ``players``: whose infosets the
-    call updates (the others keep R and S); ``count``: whether it ends the iteration."""
+    call updates (the others keep R and S); ``count``: whether it ends the iteration.
+    ``info["rtilde_scale"]`` is, per pair, the sum of the magnitudes the regret is summed from,
+    |pi_{-i}(d)| (|w_a| + |u|) over the infoset's nodes d: the size that rounding errors in
+    r~ scale with (r~ itself can be much smaller, by cancellation)."""
     sigma = current_strategy(tree, state.R)
     rt = [0.0] * tree.Q
+    rt_scale = [0.0] * tree.Q  # sum of |cf| (|w_a| + |u|): the magnitude r~ is summed from
     pibar = {h: 0.0 for h in tree.rational}
     n = tree.n
     node_u = [0.0] * n if record else None
@@ -165,6 +169,7 @@ def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = Fal
                 cf, own, sgn = p1 * pc, p2, -1.0
             for a in range(len(ch)):
                 rt[o + a] += cf * sgn * (w[a] - u)
+                rt_scale[o + a] += abs(cf) * (abs(w[a]) + abs(u))
             pibar[h] += own
         if record:
             node_u[v] = u
@@ -195,7 +200,8 @@ def iterate(tree: Tree, state: State, variant: str = VANILLA, record: bool = Fal
             S[q] = S[q] + w * pibar[h] * sigma[q]
             if variant == DCFR:
                 S[q] = S[q] * d_avg
-    info = {"sigma": sigma, "rtilde": rt, "pibar": pibar, "root_value": root_value,
+    info = {"sigma": sigma, "rtilde": rt, "rtilde_scale": rt_scale, "pibar": pibar,
+            "root_value": root_value,
             "next_sigma": current_strategy(tree, R)}
     if record:
         info["node_u"] = node_u

@@ -60,3 +60,43 @@ def test_adam_first_step_is_signed_lr():
     for k in mlp.PARAMS:
         nz = g[k] != 0
         np.testing.assert_allclose((q[k] - p[k])[nz], -1e-3 * np.sign(g[k][nz]), rtol=1e-9)
+
+
+def _const_grads(values):
+    return {k: np.full((2, 3), v) for k, v in zip(mlp.PARAMS, values)}
+
+
+def test_adam_constant_gradient_moves_by_lr_every_step():
+    """A gradient that never changes gives m_t = g (1 - b1^t) and v_t = g^2 (1 - b2^t), so the
+    bias-corrected step is exactly -lr * sign(g) at every t (eps = 0). A step counter that
+    does not advance, or a correction with another power of beta, fails from t = 2 on."""
+    vals = [0.5, -2.0, 3e-3, -7.0, 1.0, -0.25]
+    g = _const_grads(vals)
+    p = {k: np.zeros((2, 3)) for k in mlp.PARAMS}
+    state = {}
+    for t in range(1, 8):
+        before = {k: v.copy() for k, v in p.items()}
+        mlp.adam_step(p, g, state, lr=1e-2, eps=0.0)
+        assert state["t"] == t
+        for k, v in zip(mlp.PARAMS, vals):
+            np.testing.assert_allclose(p[k] - before[k], -1e-2 * np.sign(v), rtol=1e-12)
+
+
+def test_adam_alternating_gradient_closed_form():
+    """Gradients g, -g, g, ... : v_t = g^2 (1 - b2^t) so the corrected second moment is g^2,
+    and m_t = (1 - b1) g (-1)^(t-1) sum_{j<t} (-b1)^j, so the step at t is
+    -lr (-1)^(t-1) sign(g) (1 - b1)(1 - (-b1)^t) / ((1 + b1)(1 - b1^t)) (eps = 0). This pins the
+    momentum recursion (which past gradient gets which power of b1) on steps 1-6."""
+    b1, b2, lr = 0.8, 0.99, 1e-2
+    vals = [1.5, -0.5, 2.0, -3.0, 0.25, 4.0]
+    p = {k: np.zeros((2, 3)) for k in mlp.PARAMS}
+    state = {}
+    for t in range(1, 7):
+        sgn = (-1.0) ** (t - 1)
+        g = _const_grads([sgn * v for v in vals])
+        before = {k: v.copy() for k, v in p.items()}
+        mlp.adam_step(p, g, state, lr=lr, beta1=b1, beta2=b2, eps=0.0)
+        frac = (1 - b1) * (1 - (-b1) ** t) / ((1 + b1) * (1 - b1 ** t))
+        for k, v in zip(mlp.PARAMS, vals):
+            np.testing.assert_allclose(p[k] - before[k], -lr * sgn * np.sign(v) * frac,
+                                       rtol=1e-12)
