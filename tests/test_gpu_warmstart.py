@@ -107,6 +107,41 @@ def test_training_reduces_loss():
     assert last < first and last - entropy < 0.5 * (first - entropy)
 
 
+def test_adam_matches_fp64_reference_over_steps():
+    """Six training steps with lr > 0: after each, the GPU's FP32 master parameters equal the
+    FP64 Adam of the oracle applied to the GPU's own gradient of that step, with the oracle's
+    moments carried over from step to step (b1 0.9, b2 0.999, eps 1e-8, bias corrections by
+    the step count). The parameters are compared at FP32 rounding of their magnitude plus
+    1e-5 of the step size."""
+    import torch
+    F, H, A, B = 40, 64, 4, 256
+    rng = np.random.default_rng(17)
+    X = bf16(rng.standard_normal((B, F)))
+    mask = (rng.random((B, A)) < 0.8).astype(np.float64)
+    mask[:, 0] = 1.0
+    T = rng.random((B, A)) * mask
+    T /= T.sum(axis=1, keepdims=True)
+    net = _net(F, H, A, B, 3)
+    xt = torch.from_numpy(X.astype(np.float32)).to("cuda").to(torch.bfloat16)
+    tt = torch.from_numpy(T.astype(np.float32)).to("cuda")
+    mt = torch.from_numpy(mask.astype(np.float32)).to("cuda")
+    lr = 3e-3
+    state = {}
+    for step in range(6):
+        before = _unflat(net.params(), F, H, A)
+        net.train_step(xt, tt, mt, lr=lr)
+        g = _unflat(net.grads(), F, H, A)
+        after = _unflat(net.params(), F, H, A)
+        ref = mlp.adam_step({k: v.copy() for k, v in before.items()}, g, state, lr=lr)
+        for k in mlp.PARAMS:
+            tol = 2.0 ** -23 * np.abs(ref[k]) + 1e-5 * lr
+            err = np.abs(after[k] - ref[k])
+            assert np.all(err <= tol), (step, k, float((err / tol).max()))
+            moved = np.abs(after[k] - before[k]).max()
+            assert moved > 0.1 * lr, (step, k, moved)  # every tensor takes real steps
+    net.close()
+
+
 def test_features_match_definition():
     import torch
     from paper_2408_14778_amd import warmstart as ws
