@@ -89,7 +89,15 @@ enum { CFR_AVG_DEFAULT = -1, CFR_AVG_UNIFORM = 0, CFR_AVG_LINEAR = 1 };
 #define CFR_FLAG_ALTERNATING 4u  /* alternating updates (the schedule of the cited CFR+ work): an
                                     iteration is a pass that updates player 1's infosets, then a
                                     pass, under player 1's new strategy, that updates player 2's,
-                                    both with the same t; default: both players in one pass.
+                                    both with the same t; default: both players in one pass. */
+#define CFR_FLAG_KEEP_NODE_VALUES 8u /* the subtree-pack launch (which keeps the values and reaches
+                                    of the nodes below its first level on chip) also stores them,
+                                    so that cfr_get_node_values can read every node; without it
+                                    cfr_get_node_values returns CFR_EINVAL for a game with packs. */
+#define CFR_FLAG_SUBTREE_PACKS 16u /* the public-block engine with subtree packs (below): the
+                                    highest blocks whose subtrees fit one workgroup's LDS, tier by
+                                    tier, run in pack launches instead of the per-level launches
+                                    (at most 4 actions per infoset; otherwise ignored).
                                     Other flag bits: CFR_EINVAL */
 
 typedef struct cfr_config {
@@ -217,15 +225,34 @@ int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes)
 
 /* Host-only flattening, for checking the canonical layout without a GPU: build the layout
  * of `game` on the host (validation as in cfr_plan), then read arrays by the names listed for
- * cfr_get_layout. For level-pure games the public-block execution plan is built too and its
- * arrays are readable as x_canon_of, x_parent, x_edge, x_meta, x_child_begin, x_child_stride,
+ * cfr_get_layout. For level-pure games the public-block execution plan is built too (with
+ * subtree packs if flags holds CFR_FLAG_SUBTREE_PACKS; flags: 0 or that flag, else
+ * CFR_EINVAL) and its arrays are readable as x_canon_of, x_parent, x_edge, x_meta, x_child_begin, x_child_stride,
  * x_child_list, x_infoset_canon, x_q_offset, x_member_offset, x_members, x_h_level_offset,
- * x_chance_nodes, x_c_level_offset, x_q_input. The handle owns host memory only. */
+ * x_chance_nodes, x_c_level_offset, x_q_input; and the subtree packs: x_up_end, x_h_up_end,
+ * x_c_up_end (per level, the end of the nodes, infosets and chance nodes that the per-level
+ * launches take; the rest of the level is in packs), x_tier_offset (int32, tiers + 1 entries:
+ * the packs of tier t are t_o[t - 1] .. t_o[t] - 1), x_packs (per pack, int32: tier, first
+ * level, levels, decision nodes, members, chance nodes, roots, infosets, pairs, chance
+ * children, then the offsets of its root, member, infoset, chance, chance-child and node
+ * records in x_pack_blob, then 9 entries each of the per-level member and chance-node ranges) and x_pack_blob (the records: roots 4 words {decision
+ * index | actor << 16, parent node, edge, node}; members 6 {decision index | k << 16 | player
+ * 2 << 19 | external children << 20 | child kinds << 24 (2 bits each: 0 in the pack, 1
+ * terminal payoff, 2 external node), first local pair, 4 children}; infosets 4 {first pair,
+ * first local pair, first member | end member << 16, k | player << 8}; chance nodes 4
+ * {decision index | external children << 20, k, first child record}; chance children 3
+ * {child, probability, kind}; nodes 1 per decision index). The handle owns host memory
+ * only. */
 typedef struct cfr_host_layout cfr_host_layout;
-int cfr_host_layout_create(const cfr_game* game, cfr_host_layout** out);
+int cfr_host_layout_create(const cfr_game* game, uint32_t flags, cfr_host_layout** out);
 int64_t cfr_host_layout_bytes(const cfr_host_layout* layout, const char* name);
 int cfr_host_layout_get(const cfr_host_layout* layout, const char* name, void* out, int64_t bytes);
 int cfr_host_layout_destroy(cfr_host_layout* layout);
+/* Host-only plan of a batch (the forest cfr_build_batch lays out, with the same validation and
+ * errors as cfr_plan_batch): only the plan arrays (x_* names, and x_level_offset) are readable.
+ * flags: 0 or CFR_FLAG_SUBTREE_PACKS (CFR_EINVAL otherwise). */
+int cfr_host_layout_create_batch(const cfr_game* games, int32_t n_games, uint32_t flags,
+                                 cfr_host_layout** out);
 
 /* Batched solving: n_games independent games (e.g. the subgames of a larger game) solved
  * together. They are laid out as one forest, level-major (level l holds level l of every game,

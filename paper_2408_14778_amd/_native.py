@@ -21,6 +21,8 @@ CFR_AVG_DEFAULT, CFR_AVG_UNIFORM, CFR_AVG_LINEAR = -1, 0, 1
 CFR_FLAG_NO_GRAPH = 1
 CFR_FLAG_NODE_ENGINE = 2
 CFR_FLAG_ALTERNATING = 4
+CFR_FLAG_KEEP_NODE_VALUES = 8
+CFR_FLAG_SUBTREE_PACKS = 16
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i8p = ctypes.POINTER(ctypes.c_int8)
@@ -106,12 +108,15 @@ SIGNATURES = {
                                       ctypes.c_int64]),
     "cfr_get_node_values": (ctypes.c_int, [ctypes.c_void_p, _f32p, _f32p, ctypes.c_int64]),
     "cfr_destroy": (ctypes.c_int, [ctypes.c_void_p]),
-    "cfr_host_layout_create": (ctypes.c_int, [ctypes.POINTER(CfrGame),
+    "cfr_host_layout_create": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_uint32,
                                               ctypes.POINTER(ctypes.c_void_p)]),
     "cfr_host_layout_bytes": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_char_p]),
     "cfr_host_layout_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
                                            ctypes.c_int64]),
     "cfr_host_layout_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "cfr_host_layout_create_batch": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_int32,
+                                                    ctypes.c_uint32,
+                                                    ctypes.POINTER(ctypes.c_void_p)]),
     "cfr_plan_batch": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_int32,
                                       ctypes.POINTER(CfrConfig), ctypes.POINTER(CfrPlanInfo)]),
     "cfr_build_batch": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_int32,

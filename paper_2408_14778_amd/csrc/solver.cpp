@@ -13,6 +13,7 @@
 #include "../../include/cfr.h"
 #include "../../include/cfr_warmstart.h"
 #include "flatten.hpp"
+#include "host_plan.hpp"
 #include "mlp.hpp"
 #include "kernels.hpp"
 #include "xkernels.hpp"
@@ -33,7 +34,13 @@ struct cfr_solver {
     std::vector<int32_t> up_threads, chunk_cap, chance_glog;  // per level
     std::vector<int8_t> x_meta;                                 // host copy (top-down tiles)
     std::vector<int32_t> reach_threads_l, reach_npt_l, t_level_offset;
-    std::vector<int64_t> reach_units;  // decision nodes per level
+    std::vector<int64_t> reach_units;  // upper decision nodes per level
+    // upper prefixes per level (the parts outside the subtree packs) and per-level flags
+    std::vector<int32_t> x_up_end, x_h_up_end, x_c_up_end, x_k_up_end, x_m_up_end;
+    std::vector<int8_t> only_terminal_children;
+    bool keep_nodes = false;  // the pack launches also store node values and reaches
+    std::vector<int32_t> tier_offset;  // packs of each tier
+    std::vector<int64_t> tier_dec;     // decision nodes of each tier
     cfr::UpdateRule rule;  // regret / average update (variant, linear weights, discounts)
     bool alternating = false;  // two passes per iteration: player 1, then player 2
     bool use_graph = true;
@@ -97,7 +104,22 @@ struct Sizes {
     int engine = ENGINE_NODE;
     bool canonical = true;   // false for a batch: only the execution plan is on the device
     int32_t n_games = 1;
+    bool packs = false;      // subtree packs (their records are on the device)
 };
+
+// Bounds on the subtree packs of a plan over N nodes, M members, Hp infosets and C chance nodes
+// with D + 1 levels: packs are cut greedily along each level of a tier, so two consecutive packs
+// hold together more than 96 decision nodes and chance children (more than kPackDec = 512
+// decision nodes, more than 384 pairs of at most 4 actions each, more than 128 chance nodes, or
+// more than 1,024 chance children), so more than 48 nodes. Records: 4 words per root, infoset and chance node, 6 per member, 3 per chance
+// child, 1 per decision node, and up to 3 words of alignment before each of 3 sections and
+// after the last.
+int64_t max_packs(int64_t N, int32_t D) {
+    return 2 * N / 48 + int64_t{D + 1} * cfr::kMaxTiers + 1;
+}
+int64_t max_pack_words(int64_t N, int64_t M, int64_t Hp, int64_t C, int32_t D) {
+    return 4 * N + 4 * Hp + 6 * M + 4 * C + 3 * N + N + 12 * max_packs(N, D);
+}
 
 int choose_engine(bool level_pure, int32_t max_actions, uint32_t flags) {
     if ((flags & CFR_FLAG_NODE_ENGINE) != 0 || !level_pure || max_actions > 16) return ENGINE_NODE;
@@ -175,6 +197,11 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
         x.chunk_m = c.take<int32_t>(Hp + D + 2);
         x.q_input = c.take<int32_t>(Qp);
         x.payoff = c.take<float>(N);
+        x.pack_done = c.take<uint32_t>(1);
+        if (z.packs) {
+            x.packs = c.take<cfr::PackDesc>(max_packs(N, D));
+            x.pack_blob = c.take<int32_t>(max_pack_words(N, M, Hp, z.C, D));
+        }
         x.prob = d.prob;
         x.R = d.R;
         x.S = d.S;
@@ -251,7 +278,8 @@ void discard(cfr_solver* s) {
 int check_config(const cfr_config* c) {
     if (c == nullptr) return CFR_OK;
     if (c->variant < CFR_VANILLA || c->variant > CFR_DCFR) return set_err(CFR_EINVAL, "bad variant");
-    if (c->flags & ~(CFR_FLAG_NO_GRAPH | CFR_FLAG_NODE_ENGINE | CFR_FLAG_ALTERNATING))
+    if (c->flags & ~(CFR_FLAG_NO_GRAPH | CFR_FLAG_NODE_ENGINE | CFR_FLAG_ALTERNATING |
+                     CFR_FLAG_KEEP_NODE_VALUES | CFR_FLAG_SUBTREE_PACKS))
         return set_err(CFR_EINVAL, "unknown flag bits");
     if (c->averaging < CFR_AVG_DEFAULT || c->averaging > CFR_AVG_LINEAR)
         return set_err(CFR_EINVAL, "bad averaging");
@@ -281,7 +309,9 @@ cfr::UpdateRule rule_of(const cfr_config& c) {
 
 // Per level, which launch computes its top-down reach (0: none, the roots and levels without
 // decision nodes; 1: the single-workgroup launch of the first levels; 2: the launch of several
-// small levels; 3: a launch of its own; 4: the level's bottom-up launch).
+// small levels; 3: a launch of its own; 4: the level's bottom-up launch; 5: the subtree-pack
+// launch, for a level whose decision nodes all lie in packs). For a level split between the
+// per-level launches and the packs, the code names the launch of the upper part.
 // Deepest level of the solver's iteration (a batch: of its forest).
 int32_t launch_depth(const cfr_solver* s) {
     return s->engine == ENGINE_BLOCK ? s->xdev.D : s->dev.D;
@@ -295,7 +325,8 @@ std::vector<int32_t> reach_launch(const cfr_solver* s) {
     if (s->engine != ENGINE_BLOCK) return r;
     const cfr::XDev& x = s->xdev;
     for (int32_t l = 1; l <= D; ++l) {
-        if (x.reach_units_host[l] == 0) r[l] = 0;
+        const bool in_packs = x.up_end_host[l] < x.level_offset_host[l + 1];
+        if (x.reach_units_host[l] == 0) r[l] = in_packs && l < D ? 5 : 0;
         else if (l <= x.fused_reach) r[l] = 1;
         else if (l <= x.path_reach) r[l] = 2;
     }
@@ -322,6 +353,8 @@ int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out)
     z.terminals = L.n_terminals;
     z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
     z.engine = choose_engine(L.level_pure, L.max_actions, config ? config->flags : 0u);
+    z.packs = z.engine == ENGINE_BLOCK && L.max_actions <= 4 && config != nullptr &&
+              (config->flags & CFR_FLAG_SUBTREE_PACKS) != 0;
     cfr::Dev d{};
     cfr::XDev x{};
     std::memset(out, 0, sizeof *out);
@@ -363,7 +396,7 @@ int apply_shapes(cfr_solver* s, hipStream_t st) {
         s->reach_npt_l[l] = npt;
         const int32_t cap = threads * npt;
         int32_t x0 = s->x_level_offset[l];
-        const int32_t x1 = s->x_level_offset[l + 1];
+        const int32_t x1 = s->x_up_end[l];  // the upper prefix: packs take the rest
         while (x0 < x1) {
             while (x0 < x1 && (s->x_meta[x0] & 3) == 0) ++x0;
             int32_t e = x0;
@@ -388,7 +421,7 @@ int apply_shapes(cfr_solver* s, hipStream_t st) {
             s->chunk_cap[l] = cfr::kFuseThreads;
             continue;
         }
-        const int b = cfr::shape_bucket(s->x_m_level_offset[l + 1] - s->x_m_level_offset[l]);
+        const int b = cfr::shape_bucket(s->x_m_up_end[l] - s->x_m_level_offset[l]);
         s->up_threads[l] = s->shape.up_threads[b];
         s->chunk_cap[l] = s->shape.up_threads[b] * s->shape.up_members[b];
     }
@@ -396,7 +429,8 @@ int apply_shapes(cfr_solver* s, hipStream_t st) {
     x.chunk_cap_host = s->chunk_cap.data();
     std::vector<int32_t> chunk_first, chunk_m;
     cfr::build_chunks(s->x_h_level_offset, s->x_member_offset, s->chunk_cap.data(), chunk_first,
-                      s->x_k_level_offset);
+                      s->x_k_level_offset, &s->x_h_up_end, &s->x_k_up_end);
+    x.k_up_end_host = s->x_k_up_end.data();
     chunk_m.resize(chunk_first.size());
     for (size_t c = 0; c < chunk_first.size(); ++c) chunk_m[c] = s->x_member_offset[chunk_first[c]];
     x.k_level_offset_host = s->x_k_level_offset.data();
@@ -437,18 +471,42 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
         (rc = upload(x.chance_base, P.chance_base, st)) || (rc = upload(x.chance_k, P.chance_k, st)) ||
         (rc = upload(x.q_input, P.q_input, st)) || (rc = upload(x.payoff, P.payoff, st)))
         return rc;
+    if (!P.packs.empty() && x.packs == nullptr)
+        return set_err(CFR_EINVAL, "subtree packs planned without their storage");
+    if (static_cast<int64_t>(P.packs.size()) > max_packs(P.N, P.D) ||
+        static_cast<int64_t>(P.pack_blob.size()) > max_pack_words(P.N, P.M, P.Hp, P.C, P.D))
+        return set_err(CFR_EINVAL, "subtree packs exceed their bound");
+    if ((rc = upload(const_cast<cfr::PackDesc*>(x.packs), P.packs, st)) ||
+        (rc = upload(const_cast<int32_t*>(x.pack_blob), P.pack_blob, st)))
+        return rc;
     HIP_TRY(hipStreamSynchronize(st), "plan upload");
+    x.n_tiers = P.n_tiers;
+    s->tier_offset = P.tier_offset;
+    s->tier_dec.assign(P.n_tiers, 0);
+    for (int32_t t = 1; t <= P.n_tiers; ++t)
+        for (int32_t i = P.tier_offset[t - 1]; i < P.tier_offset[t]; ++i)
+            s->tier_dec[t - 1] += P.packs[i].n_dec;
+    x.tier_offset_host = s->tier_offset.data();
+    x.tier_dec_host = s->tier_dec.data();
+    x.keep_nodes = s->keep_nodes ? 1 : 0;
+    s->x_up_end = P.up_end;
+    s->x_h_up_end = P.h_up_end;
+    s->x_c_up_end = P.c_up_end;
+    x.up_end_host = s->x_up_end.data();
+    x.h_up_end_host = s->x_h_up_end.data();
+    x.c_up_end_host = s->x_c_up_end.data();
     s->x_level_offset = P.level_offset;
     s->x_h_level_offset = P.h_level_offset;
     s->x_c_level_offset = P.c_level_offset;
     s->x_member_offset = P.member_offset;
     s->x_meta = P.meta;
-    s->reach_units.assign(P.D + 1, 0);
-    for (int32_t l = 0; l <= P.D; ++l)
-        for (int32_t v = P.level_offset[l]; v < P.level_offset[l + 1]; ++v)
-            s->reach_units[l] += (P.meta[v] & 3) != 0;
+    // upper decision nodes per level, and whether their children are all terminal
+    cfr::upper_level_stats(P, s->reach_units, s->only_terminal_children);
+    x.only_terminal_children_host = s->only_terminal_children.data();
     s->x_m_level_offset.resize(P.D + 2);
     for (int32_t l = 0; l <= P.D + 1; ++l) s->x_m_level_offset[l] = P.member_offset[P.h_level_offset[l]];
+    s->x_m_up_end.resize(P.D + 1);
+    for (int32_t l = 0; l <= P.D; ++l) s->x_m_up_end[l] = P.member_offset[P.h_up_end[l]];
     // lanes per chance node: the level's largest fan-out rounded up to a power of two, <= 64
     s->chance_glog.assign(P.D + 1, 0);
     for (int32_t l = 0; l <= P.D; ++l) {
@@ -464,7 +522,7 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     x.h_level_offset_host = s->x_h_level_offset.data();
     x.c_level_offset_host = s->x_c_level_offset.data();
     x.chance_glog_host = s->chance_glog.data();
-    x.fused_reach = cfr::fusable_reach_levels(x.level_offset_host, P.D);
+    x.fused_reach = cfr::fusable_reach_levels(x.level_offset_host, x.up_end_host, P.D);
     x.path_reach = cfr::path_reach_levels(s->reach_units.data(), x.fused_reach, P.D,
                                           cfr::kPathDepthBelowTop);
     // the path launch alone, from the roots, when it covers as many levels: one launch fewer
@@ -473,9 +531,19 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
         x.fused_reach = 0;
         x.path_reach = p0;
     }
-    x.fused_up = cfr::fusable_up_levels(x.m_level_offset_host, x.h_level_offset_host,
-                                        x.c_level_offset_host, x.chance_glog_host, P.D,
-                                        x.max_actions);
+    x.fused_up = cfr::fusable_up_levels(x.m_level_offset_host, s->x_m_up_end.data(),
+                                        x.h_level_offset_host, x.h_up_end_host,
+                                        x.c_level_offset_host, x.c_up_end_host,
+                                        x.chance_glog_host, P.D, x.max_actions);
+    // levels with nothing outside the packs need no single-workgroup launch
+    auto upper_up = [&](int32_t l) {
+        return x.h_up_end_host[l] > x.h_level_offset_host[l] ||
+               x.c_up_end_host[l] > x.c_level_offset_host[l];
+    };
+    while (x.fused_up > 0 && !upper_up(x.fused_up - 1)) --x.fused_up;
+    x.upper_bottom_up = 0;
+    for (int32_t l = 0; l <= P.D; ++l) x.upper_bottom_up |= upper_up(l) ? 1 : 0;
+    while (x.fused_reach > 0 && s->reach_units[x.fused_reach] == 0) --x.fused_reach;
     // the sigma ranges that the single-workgroup kernels read: pairs and chance probabilities
     // of the levels above the first one each leaves to per-level launches
     for (int e = 0; e < 2; ++e) {
@@ -514,9 +582,12 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     z.terminals = L.n_terminals;
     z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
     z.engine = choose_engine(L.level_pure, L.max_actions, cfg.flags);
+    z.packs = z.engine == ENGINE_BLOCK && L.max_actions <= 4 && (cfg.flags & CFR_FLAG_SUBTREE_PACKS);
     cfr::ExecPlan P;
     if (z.engine == ENGINE_BLOCK) {
-        rc = cfr::build_exec_plan(L, P, err);
+        // subtree packs are instantiated for at most 4 actions per infoset
+        rc = cfr::build_exec_plan(L, P, err,
+                                  L.max_actions <= 4 && (cfg.flags & CFR_FLAG_SUBTREE_PACKS));
         if (rc != CFR_OK) return set_err(rc, err);
     }
     cfr::Dev d{};
@@ -534,6 +605,7 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     s->rule = rule_of(cfg);
     s->alternating = (cfg.flags & CFR_FLAG_ALTERNATING) != 0;
     s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
+    s->keep_nodes = (cfg.flags & CFR_FLAG_KEEP_NODE_VALUES) != 0;
     s->level_pure = L.level_pure;
     s->n_terminals = L.n_terminals;
     s->max_actions = L.max_actions;
@@ -909,6 +981,9 @@ int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes)
     if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
     if (!s->canonical) return set_err(CFR_EINVAL, "node values are not exported for a batch");
     if (n_nodes != s->dev.N) return set_err(CFR_EINVAL, "n_nodes does not match the game");
+    if (s->engine == ENGINE_BLOCK && s->xdev.n_tiers > 0 && !s->keep_nodes)
+        return set_err(CFR_EINVAL, "the subtree packs keep node values on chip: build with "
+                                   "CFR_FLAG_KEEP_NODE_VALUES to read them");
     const int64_t N = s->dev.N;
     std::vector<float> val(u1 != nullptr ? N : 0), planes(reach != nullptr ? 3 * N : 0);
     std::vector<int32_t> canon(s->engine == ENGINE_BLOCK ? N : 0);
@@ -945,46 +1020,6 @@ int cfr_destroy(cfr_solver* s) {
 
 namespace {
 
-// Flattens and plans every game on host threads; all must be level pure with <= 16 actions.
-int plan_games(const cfr_game* games, int32_t n, std::vector<cfr::ExecPlan>& plans,
-               int32_t& max_actions, std::string& err) {
-    plans.assign(n, cfr::ExecPlan());
-    std::vector<int> codes(n, CFR_OK);
-    std::vector<std::string> errs(n);
-    std::vector<int32_t> maxa(n, 0);
-    std::atomic<int32_t> next{0};
-    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    auto work = [&]() {
-        for (int32_t g = next++; g < n; g = next++) {
-            cfr::Layout L;
-            int rc = cfr::flatten(games[g], L, errs[g]);
-            if (rc == CFR_OK && !L.level_pure) {
-                rc = CFR_ELEVEL;
-                errs[g] = "an infoset spans several levels";
-            }
-            if (rc == CFR_OK && L.max_actions > 16) {
-                rc = CFR_EINVAL;
-                errs[g] = "more than 16 actions in an infoset";
-            }
-            if (rc == CFR_OK) rc = cfr::build_exec_plan(L, plans[g], errs[g]);
-            maxa[g] = L.max_actions;
-            codes[g] = rc;
-        }
-    };
-    std::vector<std::thread> pool;
-    for (unsigned t = 0; t < std::min<unsigned>(hw, static_cast<unsigned>(n)); ++t) pool.emplace_back(work);
-    for (auto& t : pool) t.join();
-    max_actions = 0;
-    for (int32_t g = 0; g < n; ++g) {
-        if (codes[g] != CFR_OK) {
-            err = "game " + std::to_string(g) + ": " + errs[g];
-            return codes[g];
-        }
-        max_actions = std::max(max_actions, maxa[g]);
-    }
-    return CFR_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -1012,6 +1047,7 @@ int cfr_plan_batch(const cfr_game* games, int32_t n_games, const cfr_config* con
         terminals += L.n_terminals;
         z.terminals += L.n_terminals;
     }
+    z.packs = z.max_actions <= 4 && config != nullptr && (config->flags & CFR_FLAG_SUBTREE_PACKS);
     cfr::Dev d{};
     cfr::XDev x{};
     std::memset(out, 0, sizeof *out);
@@ -1041,7 +1077,8 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     std::string err;
     std::vector<cfr::ExecPlan> plans;
     int32_t max_actions = 0;
-    int rc = plan_games(games, n_games, plans, max_actions, err);
+    int rc = cfr::plan_games(games, n_games, plans, max_actions, err,
+                             (cfg.flags & CFR_FLAG_SUBTREE_PACKS) != 0);
     if (rc != CFR_OK) return set_err(rc, err);
     cfr::ExecPlan F;
     rc = cfr::build_forest_plan(plans, F, err);
@@ -1055,6 +1092,7 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     z.engine = ENGINE_BLOCK;
     z.canonical = false;
     z.n_games = n_games;
+    z.packs = max_actions <= 4 && (cfg.flags & CFR_FLAG_SUBTREE_PACKS);
     cfr::Dev d{};
     cfr::XDev x{};
     // cfr_plan_batch bounds the explicit child lists by the node count, so a workspace of the
@@ -1138,114 +1176,3 @@ extern "C" int cfr_warm_start(cfr_solver* s, const float* probs, int64_t n_q, fl
     return check_hip("warm start");
 }
 
-struct cfr_host_layout {
-    cfr::Layout L;
-    cfr::ExecPlan P;
-    bool has_plan = false;
-};
-
-namespace {
-
-// (pointer, bytes) of a named host layout array
-std::pair<const void*, int64_t> host_array(const cfr::Layout& L, const std::string& n) {
-    auto v = [](const auto& vec) {
-        return std::pair<const void*, int64_t>(
-            vec.data(), static_cast<int64_t>(vec.size() * sizeof(vec[0])));
-    };
-    if (n == "level_offset") return v(L.level_offset);
-    if (n == "node_id") return v(L.node_id);
-    if (n == "parent") return v(L.parent);
-    if (n == "child_begin") return v(L.child_begin);
-    if (n == "node_player") return v(L.node_player);
-    if (n == "node_infoset") return v(L.node_infoset);
-    if (n == "node_edge") return v(L.node_edge);
-    if (n == "infoset_id") return v(L.infoset_id);
-    if (n == "infoset_player") return v(L.infoset_player);
-    if (n == "q_offset") return v(L.q_offset);
-    if (n == "chance_id") return v(L.chance_id);
-    if (n == "cq_offset") return v(L.cq_offset);
-    if (n == "member_offset") return v(L.member_offset);
-    if (n == "members") return v(L.members);
-    if (n == "chance_prob") return v(L.chance_prob);
-    if (n == "payoff") return v(L.payoff);
-    if (n == "q_input") return v(L.q_input);
-    return {nullptr, -1};
-}
-
-std::pair<const void*, int64_t> plan_array(const cfr::ExecPlan& P, const std::string& n) {
-    auto v = [](const auto& vec) {
-        return std::pair<const void*, int64_t>(
-            vec.data(), static_cast<int64_t>(vec.size() * sizeof(vec[0])));
-    };
-    if (n == "x_canon_of") return v(P.canon_of);
-    if (n == "x_parent") return v(P.parent);
-    if (n == "x_edge") return v(P.edge);
-    if (n == "x_meta") return v(P.meta);
-    if (n == "x_child_begin") return v(P.child_begin);
-    if (n == "x_child_stride") return v(P.child_stride);
-    if (n == "x_child_list") return v(P.child_list);
-    if (n == "x_infoset_canon") return v(P.infoset_canon);
-    if (n == "x_q_offset") return v(P.q_offset);
-    if (n == "x_member_offset") return v(P.member_offset);
-    if (n == "x_members") return v(P.members);
-    if (n == "x_h_level_offset") return v(P.h_level_offset);
-    if (n == "x_chance_nodes") return v(P.chance_nodes);
-    if (n == "x_c_level_offset") return v(P.c_level_offset);
-    if (n == "x_q_input") return v(P.q_input);
-    return {nullptr, -1};
-}
-
-std::pair<const void*, int64_t> any_array(const cfr_host_layout* h, const std::string& n) {
-    if (n.rfind("x_", 0) == 0) {
-        if (!h->has_plan) return {nullptr, -1};
-        return plan_array(h->P, n);
-    }
-    return host_array(h->L, n);
-}
-
-}  // namespace
-
-extern "C" {
-
-int cfr_host_layout_create(const cfr_game* game, cfr_host_layout** out) {
-    if (game == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
-    auto* h = new cfr_host_layout();
-    std::string err;
-    int rc = cfr::flatten(*game, h->L, err);
-    if (rc != CFR_OK) {
-        delete h;
-        return set_err(rc, err);
-    }
-    if (h->L.level_pure) {
-        rc = cfr::build_exec_plan(h->L, h->P, err);
-        if (rc != CFR_OK) {
-            delete h;
-            return set_err(rc, err);
-        }
-        h->has_plan = true;
-    }
-    *out = h;
-    return CFR_OK;
-}
-
-int64_t cfr_host_layout_bytes(const cfr_host_layout* layout, const char* name) {
-    if (layout == nullptr || name == nullptr) return CFR_EINVAL;
-    const auto a = any_array(layout, name);
-    return a.second < 0 ? CFR_EINVAL : a.second;
-}
-
-int cfr_host_layout_get(const cfr_host_layout* layout, const char* name, void* out, int64_t bytes) {
-    if (layout == nullptr || name == nullptr) return set_err(CFR_EINVAL, "null argument");
-    const auto a = any_array(layout, name);
-    if (a.second < 0) return set_err(CFR_EINVAL, "unknown layout array");
-    if (bytes != a.second || (bytes > 0 && out == nullptr)) return set_err(CFR_EINVAL, "wrong output size");
-    if (bytes > 0) std::memcpy(out, a.first, static_cast<size_t>(bytes));
-    return CFR_OK;
-}
-
-int cfr_host_layout_destroy(cfr_host_layout* layout) {
-    delete layout;
-    return CFR_OK;
-}
-
-}  // extern "C"

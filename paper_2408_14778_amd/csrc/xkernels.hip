@@ -280,25 +280,26 @@ __device__ __forceinline__ void chance_group(const UpArgs& a, int32_t ci, bool o
 // Phase 2 of a chunk for one infoset h (pair operands pr = R, ps = S, pp = sigma already
 // loaded): sums its members' LDS slots slo .. shi - 1 in member order, then the regret update
 // (vanilla, CFR+ clipped, or discounted), the average-strategy update S += w pi-bar sigma
-// (discounted: then scaled) and regret matching into sigma.
+// (discounted: then scaled) and regret matching into sigma, written to Ro, So, Po (the
+// infoset's first pair, in memory or in LDS); t is the 1-based iteration.
 template <int KMAX>
-__device__ __forceinline__ void update_infoset(const UpArgs& a, int32_t o, int32_t k, int player,
-                                               int32_t slo, int32_t shi, const float* pr,
-                                               const float* ps, const float* pp,
-                                               float (*s_con)[KMAX], const float* s_own) {
+__device__ __forceinline__ void update_infoset(const UpArgs& a, float* Ro, float* So, float* Po,
+                                               int32_t k, int player, int32_t slo, int32_t shi,
+                                               const float* pr, const float* ps, const float* pp,
+                                               float (*s_con)[KMAX], const float* s_own, float t) {
     if (!((a.rule.players >> (player - 1)) & 1)) return;  // not this pass's player
     float racc[KMAX];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) racc[j] = 0.0f;
     float own = 0.0f;
-#pragma unroll 1
+    // member order; unrolled so that several members' slots are read at once
+#pragma unroll 4
     for (int32_t sl = slo; sl < shi; ++sl) {
 #pragma unroll
         for (int j = 0; j < KMAX; ++j) racc[j] += s_con[sl][j];
         own += s_own[sl];
     }
     const float sgn = player == 1 ? 1.0f : -1.0f;
-    const float t = static_cast<float>(*a.T + 1);
     const bool disc = a.rule.variant == 2;
     float wt = a.rule.linear ? t : 1.0f;
     float d_pos = 1.0f, d_neg = 1.0f, d_avg = 1.0f;
@@ -313,9 +314,9 @@ __device__ __forceinline__ void update_infoset(const UpArgs& a, int32_t o, int32
             float r = fmaf(sgn, racc[j], pr[j]);
             if (a.rule.variant == 1) r = fmaxf(r, 0.0f);
             else if (disc) r *= r > 0.0f ? d_pos : d_neg;
-            a.R[o + j] = r;
+            Ro[j] = r;
             const float sn = fmaf(wt * own, pp[j], ps[j]);
-            a.S[o + j] = disc ? sn * d_avg : sn;
+            So[j] = disc ? sn * d_avg : sn;
             racc[j] = r;
             pos_sum += fmaxf(r, 0.0f);
         }
@@ -323,12 +324,12 @@ __device__ __forceinline__ void update_infoset(const UpArgs& a, int32_t o, int32
     if (pos_sum > 0.0f) {
 #pragma unroll
         for (int j = 0; j < KMAX; ++j)
-            if (j < k) a.prob[o + j] = fmaxf(racc[j], 0.0f) / pos_sum;
+            if (j < k) Po[j] = fmaxf(racc[j], 0.0f) / pos_sum;
     } else {
         const float unif = 1.0f / static_cast<float>(k);
 #pragma unroll
         for (int j = 0; j < KMAX; ++j)
-            if (j < k) a.prob[o + j] = unif;
+            if (j < k) Po[j] = unif;
     }
 }
 
@@ -462,8 +463,9 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
     if (big) {
         if (tid == 0) {
             if (!kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
-            update_infoset<KMAX>(a, o, k, player, 0, nm < CH ? nm : CH, pr, ps, pp, s_con,
-                                 s_own);
+            update_infoset<KMAX>(a, a.R + o, a.S + o, a.prob + o, k, player, 0,
+                                 nm < CH ? nm : CH, pr, ps, pp, s_con, s_own,
+                                 static_cast<float>(*a.T + 1));
         }
         return;
     }
@@ -482,7 +484,8 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
             player = (hr.w & 64) ? 2 : 1;
         }
         if (u > 0 || !kPrefetch) load_pairs<KMAX>(a, o, k, pr, ps, pp);
-        update_infoset<KMAX>(a, o, k, player, slo, shi, pr, ps, pp, s_con, s_own);
+        update_infoset<KMAX>(a, a.R + o, a.S + o, a.prob + o, k, player, slo, shi, pr, ps, pp,
+                             s_con, s_own, static_cast<float>(*a.T + 1));
     }
 }
 
@@ -520,6 +523,328 @@ __global__ void __launch_bounds__(kFuseThreads) k_x_up_top(UpArgs a, LevelTable 
         __syncthreads();
     }
     if (tid == 0 && a.rule.count) *a.T += 1;
+}
+
+// ---- subtree packs (xplan.hpp): one workgroup per pack, both sweeps on chip
+//
+// The pack's decision nodes are numbered 0 .. n_dec - 1 (didx); LDS holds their reach planes and
+// values and the pack's pairs (sigma, and R and S where the launch updates them). Each thread
+// keeps its members' records in registers (member m in slot m / T of thread m % T). The
+// arithmetic is that of the per-level kernels in the same order: a child's reach is its
+// parent's times the edge probability on the actor's factor; a member's value is sum_a
+// sigma(a) w_a in action order; its regret contributions cf (w_a - v) and own reach go to its
+// slot, and each infoset sums its slots in member order before update_infoset. Modes: 0 both
+// sweeps (tier 1), 1 top-down only (tiers >= 2: store the reach of the members and chance
+// nodes that have external children), 2 bottom-up (tiers >= 2: reach again on chip, then the
+// values, with the external children's values from memory, and the updates).
+
+struct PackArgs {
+    const PackDesc* packs;
+    const int32_t* blob;
+    int32_t first;  // the launch takes packs first .. first + gridDim.x - 1
+    int32_t mode;
+    int32_t keep;   // also store every decision node's value and reach
+    int32_t count;  // the launch ends the iteration: its last workgroup counts it (T += 1)
+    uint32_t* done; // workgroups of the launch that have finished (zero between launches)
+};
+
+__device__ __forceinline__ float as_float(int32_t w) { return __int_as_float(w); }
+
+template <int T>
+__global__ void __launch_bounds__(T) k_x_pack(UpArgs a, PackArgs pa) {
+    constexpr int S = kPackSlots;
+    constexpr int kDescWords = sizeof(PackDesc) / 4;
+    __shared__ float s_val[kPackDec];
+    __shared__ float s_rch[3][kPackDec];
+    __shared__ float s_sig[kPackPairs];
+    __shared__ float s_R[kPackPairs];
+    __shared__ float s_S[kPackPairs];
+    __shared__ float s_con[kPackDec][4];  // per member of the level being finished
+    __shared__ float s_own[kPackDec];
+    __shared__ int4 s_ch[kPackChance];
+    __shared__ int32_t s_kw[kPackKids];   // child: decision index, or value bits
+    __shared__ float s_kp[kPackKids];     // probability, sign bit set for a decision child
+    __shared__ int32_t s_desc[kDescWords];
+    __shared__ float s_t;
+    const int tid = threadIdx.x;
+    const int64_t N = a.N;
+    const int mode = pa.mode;
+    const bool bottom_up = mode != 1;
+    {
+        const int32_t* d = reinterpret_cast<const int32_t*>(pa.packs + pa.first + xcd_tile());
+        for (int w = tid; w < kDescWords; w += T) s_desc[w] = d[w];
+        if (tid == 0) s_t = static_cast<float>(*a.T + 1);  // read before this workgroup counts
+    }
+    __syncthreads();
+    const PackDesc& pk = *reinterpret_cast<const PackDesc*>(s_desc);
+    const int32_t* __restrict__ B = pa.blob;
+    const int32_t n_mem = pk.n_mem, n_inf = pk.n_inf, nlv = pk.nlv;
+
+    // every record the sweeps need, all loads in flight together: members and infosets into
+    // registers (record m in slot m / T of thread m % T), chance nodes and their children into
+    // LDS
+    int32_t rec[S][6];
+    int4 inf[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int32_t m = tid + j * T;
+#pragma unroll
+        for (int w = 0; w < 6; ++w) rec[j][w] = m < n_mem ? B[pk.off_mem + 6 * m + w] : 0;
+        inf[j] = m < n_inf ? *reinterpret_cast<const int4*>(B + pk.off_inf + 4 * m)
+                           : make_int4(0, 0, 0, 0);
+    }
+    // (unrolled, so that every load is issued before the first wait)
+    constexpr int KU = kPackKids / T, CU = (kPackChance + T - 1) / T, RU = kPackDec / T;
+    const int32_t n_kid = pk.n_kid, n_ch = pk.n_ch, n_root = pk.n_root;
+    int32_t kwv[KU], kpv[KU], kkv[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+        const int32_t c = tid + u * T;
+        kwv[u] = kpv[u] = kkv[u] = 0;
+        if (c < n_kid) {
+            const int32_t* kw = B + pk.off_kid + 3 * c;
+            kwv[u] = kw[0];
+            kpv[u] = kw[1];
+            kkv[u] = kw[2];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+        const int32_t c = tid + u * T;
+        if (c < n_ch) s_ch[c] = *reinterpret_cast<const int4*>(B + pk.off_ch + 4 * c);
+    }
+    int4 root[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        const int32_t i = tid + u * T;
+        root[u] = i < n_root ? *reinterpret_cast<const int4*>(B + pk.off_root + 4 * i)
+                             : make_int4(0, -1, 0, 0);
+    }
+    // second round: external children's values (bottom-up), the roots' parents' reach and
+    // edge probabilities, the pairs
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+        if (kkv[u] == 2 && bottom_up) {  // an external child: its value, as a constant
+            kwv[u] = __float_as_int(a.value[kwv[u]]);
+            kkv[u] = 1;
+        }
+    }
+    // pairs: sigma (and R, S for the updates)
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        if (tid + j * T >= n_inf) continue;
+        const int k = inf[j].w & 255;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c >= k) continue;
+            s_sig[inf[j].y + c] = a.prob[inf[j].x + c];
+            if (bottom_up) {
+                s_R[inf[j].y + c] = a.R[inf[j].x + c];
+                s_S[inf[j].y + c] = a.S[inf[j].x + c];
+            }
+        }
+    }
+    // roots: reach from their parents' stored reach (the game's root: 1)
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        if (tid + u * T >= n_root) continue;
+        const int4 r = root[u];
+        float r1 = 1.0f, r2 = 1.0f, rc = 1.0f;
+        if (r.y >= 0) {
+            r1 = a.reach[r.y];
+            r2 = a.reach[N + r.y];
+            rc = a.reach[2 * N + r.y];
+            const float s = a.prob[r.z];
+            const int actor = (r.x >> 16) & 3;  // 1 chance, 2 player 1, 3 player 2
+            if (actor == 2) r1 *= s;
+            else if (actor == 3) r2 *= s;
+            else rc *= s;
+        }
+        const int d = r.x & 0xffff;
+        s_rch[0][d] = r1;
+        s_rch[1][d] = r2;
+        s_rch[2][d] = rc;
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+        const int32_t c = tid + u * T;
+        if (c >= n_kid) continue;
+        s_kw[c] = kwv[u];
+        // probabilities are >= 0: the sign bit marks a child that is a decision node of the pack
+        s_kp[c] = kkv[u] == 0 ? -as_float(kpv[u]) : as_float(kpv[u]);
+    }
+    // bottom-up: the members' external children's values, read once and held as constants
+    if (mode == 2) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            if (tid + j * T >= n_mem || !((rec[j][0] >> 20) & 1)) continue;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (((rec[j][0] >> (24 + 2 * c)) & 3) == 2) {
+                    rec[j][2 + c] = __float_as_int(a.value[rec[j][2 + c]]);
+                    rec[j][0] ^= 3 << (24 + 2 * c);  // kind 2 -> kind 1 (a constant)
+                }
+        }
+    }
+    __syncthreads();
+
+    // top-down: each decision node of level d gives its decision children their reach
+    for (int32_t d = 0; d + 1 < nlv; ++d) {
+        const int32_t m0 = pk.mlo[d], m1 = pk.mlo[d + 1];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int32_t m = tid + j * T;
+            if (m < m0 || m >= m1) continue;
+            const int32_t w0 = rec[j][0];
+            const int dd = w0 & 0xffff, k = (w0 >> 16) & 7;
+            const bool p2 = (w0 >> 19) & 1;
+            const float r1 = s_rch[0][dd], r2 = s_rch[1][dd], rc = s_rch[2][dd];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c >= k || ((w0 >> (24 + 2 * c)) & 3) != 0) continue;
+                const int cd = rec[j][2 + c];
+                const float s = s_sig[rec[j][1] + c];
+                s_rch[0][cd] = p2 ? r1 : r1 * s;
+                s_rch[1][cd] = p2 ? r2 * s : r2;
+                s_rch[2][cd] = rc;
+            }
+        }
+        for (int32_t ci = pk.clo[d] + tid; ci < pk.clo[d + 1]; ci += T) {
+            const int4 r = s_ch[ci];
+            const int dd = r.x & 0xffff;
+            const float r1 = s_rch[0][dd], r2 = s_rch[1][dd], rc = s_rch[2][dd];
+#pragma unroll 4
+            for (int32_t c = r.z; c < r.z + r.y; ++c) {
+                const float p = s_kp[c];
+                if (!signbit(p)) continue;
+                const int cd = s_kw[c];
+                s_rch[0][cd] = r1;
+                s_rch[1][cd] = r2;
+                s_rch[2][cd] = rc * fabsf(p);
+            }
+        }
+        __syncthreads();
+    }
+    if (mode == 1) {
+        // the reach of the nodes with external children, for the lower tiers' roots
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            if (tid + j * T >= n_mem || !((rec[j][0] >> 20) & 1)) continue;
+            const int dd = rec[j][0] & 0xffff;
+            const int32_t x = B[pk.off_node + dd];
+            a.reach[x] = s_rch[0][dd];
+            a.reach[N + x] = s_rch[1][dd];
+            a.reach[2 * N + x] = s_rch[2][dd];
+        }
+        for (int32_t ci = tid; ci < pk.n_ch; ci += T) {
+            const int32_t w0 = s_ch[ci].x;
+            if (!((w0 >> 20) & 1)) continue;
+            const int dd = w0 & 0xffff;
+            const int32_t x = B[pk.off_node + dd];
+            a.reach[x] = s_rch[0][dd];
+            a.reach[N + x] = s_rch[1][dd];
+            a.reach[2 * N + x] = s_rch[2][dd];
+        }
+        return;
+    }
+
+    // bottom-up values, deepest level first: chance nodes, then members
+    const float t = s_t;
+    for (int32_t d = nlv - 1; d >= 0; --d) {
+        for (int32_t ci = pk.clo[d] + tid; ci < pk.clo[d + 1]; ci += T) {
+            const int4 r = s_ch[ci];
+            float v = 0.0f;
+#pragma unroll 4
+            for (int32_t c = r.z; c < r.z + r.y; ++c) {
+                const float p = s_kp[c];
+                v = fmaf(fabsf(p), signbit(p) ? s_val[s_kw[c]] : as_float(s_kw[c]), v);
+            }
+            s_val[r.x & 0xffff] = v;
+        }
+        // the level's members: values, and their regret contributions and own reach into the
+        // member's slot (slot = member index in the pack)
+        const int32_t m0 = pk.mlo[d], m1 = pk.mlo[d + 1];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int32_t m = tid + j * T;
+            if (m < m0 || m >= m1) continue;
+            const int32_t w0 = rec[j][0];
+            const int dd = w0 & 0xffff, k = (w0 >> 16) & 7;
+            float w[4], v = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                w[c] = 0.0f;
+                if (c >= k) continue;
+                const int kind = (w0 >> (24 + 2 * c)) & 3;
+                w[c] = kind == 0 ? s_val[rec[j][2 + c]] : as_float(rec[j][2 + c]);
+                v = fmaf(s_sig[rec[j][1] + c], w[c], v);
+            }
+            s_val[dd] = v;
+            const bool p2 = (w0 >> 19) & 1;
+            const float cf = (p2 ? s_rch[0][dd] : s_rch[1][dd]) * s_rch[2][dd];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s_con[m][c] = cf * (w[c] - v);
+            s_own[m] = p2 ? s_rch[1][dd] : s_rch[0][dd];
+        }
+        __syncthreads();
+    }
+    // every infoset of the pack at once (their updates read only their own members' slots and
+    // pairs, which no value below needs any more): sums in member order, then the update; the
+    // updated pairs stay in LDS until the end, so no barrier waits on stores
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        if (tid + j * T >= n_inf) continue;
+        const int4 r = inf[j];
+        const int32_t k = r.w & 255;
+        const int player = (r.w >> 8) & 3;
+        float pr[4], ps[4], pp[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            pr[c] = ps[c] = pp[c] = 0.0f;
+            if (c < k) {
+                pr[c] = s_R[r.y + c];
+                ps[c] = s_S[r.y + c];
+                pp[c] = s_sig[r.y + c];
+            }
+        }
+        update_infoset<4>(a, s_R + r.y, s_S + r.y, s_sig + r.y, k, player, r.z & 0xffff,
+                          r.z >> 16, pr, ps, pp, s_con, s_own, t);
+    }
+    __syncthreads();
+    // the updated pairs; the roots' values for the parents' bottom-up; every decision node's
+    // value and reach when they are kept for inspection
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        if (tid + j * T >= n_inf) continue;
+        const int4 r = inf[j];
+        const int k = r.w & 255;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c >= k) continue;
+            a.R[r.x + c] = s_R[r.y + c];
+            a.S[r.x + c] = s_S[r.y + c];
+            a.prob[r.x + c] = s_sig[r.y + c];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+        if (tid + u * T < n_root) a.value[root[u].w] = s_val[root[u].x & 0xffff];
+    if (pa.keep)
+        for (int32_t dd = tid; dd < pk.n_dec; dd += T) {
+            const int32_t x = B[pk.off_node + dd];
+            a.value[x] = s_val[dd];
+            a.reach[x] = s_rch[0][dd];
+            a.reach[N + x] = s_rch[1][dd];
+            a.reach[2 * N + x] = s_rch[2][dd];
+        }
+    // the launch's last workgroup counts the iteration: every workgroup read T at its start
+    if (pa.count && tid == 0) {
+        __threadfence();
+        if (atomicAdd(pa.done, 1u) == gridDim.x - 1) {
+            *a.T += 1;
+            *pa.done = 0;
+        }
+    }
 }
 
 __global__ void k_x_reset_nodes(int64_t N, int32_t n_roots, const int8_t* __restrict__ meta,
@@ -789,11 +1114,17 @@ const char* xkernel_kind_name(int kind) {
     switch (kind) {
         case XK_REACH: return "block_reach";
         case XK_UP: return "block_up";
+        case XK_SUBTREE: return "block_subtree";
         default: return "";
     }
 }
 
+__global__ void k_x_zero_u32(uint32_t* p) {
+    if (gid() == 0) *p = 0;
+}
+
 void launch_x_reset(const XDev& x, hipStream_t st) {
+    hipLaunchKernelGGL(k_x_zero_u32, dim3(1), dim3(64), 0, st, x.pack_done);
     hipLaunchKernelGGL(k_x_reset_nodes, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N,
                        x.level_offset_host[1], x.meta, x.payoff, x.value, x.reach);
     hipLaunchKernelGGL(k_x_br_setup, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N,
@@ -832,8 +1163,9 @@ UpArgs up_args(const XDev& x, const UpdateRule& rule) {
 
 template <int KMAX, int CH, int MPT>
 void launch_up_level(const XDev& x, const UpArgs& a, int32_t l, hipStream_t st) {
-    const int32_t klo = x.k_level_offset_host[l], nk = x.k_level_offset_host[l + 1] - klo;
-    const int32_t clo = x.c_level_offset_host[l], nc = x.c_level_offset_host[l + 1] - clo;
+    // the level's chunks and chance nodes outside the subtree packs
+    const int32_t klo = x.k_level_offset_host[l], nk = x.k_up_end_host[l] - klo;
+    const int32_t clo = x.c_level_offset_host[l], nc = x.c_up_end_host[l] - clo;
     const int glog = x.chance_glog_host[l];
     const int32_t per = CH >> glog;
     const int32_t grid = nk + (nc + per - 1) / per;
@@ -880,9 +1212,9 @@ void launch_reach_level(const XDev& x, int32_t l, hipStream_t st) {
 
 }  // namespace
 
-int32_t fusable_reach_levels(const int32_t* level_offset, int32_t D) {
+int32_t fusable_reach_levels(const int32_t* level_offset, const int32_t* up_end, int32_t D) {
     int32_t k = 0;
-    while (1 + k < D && k < kFuseMax && level_offset[k + 2] - level_offset[k + 1] <= 2 * kFuseThreads)
+    while (1 + k < D && k < kFuseMax && up_end[k + 1] - level_offset[k + 1] <= 2 * kFuseThreads)
         ++k;
     return k;
 }
@@ -896,14 +1228,15 @@ int32_t path_reach_levels(const int64_t* units, int32_t fused, int32_t D, int32_
     return l;
 }
 
-int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_offset,
-                          const int32_t* c_level_offset, const int32_t* chance_glog, int32_t D,
-                          int32_t max_actions) {
+int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* m_up_end,
+                          const int32_t* h_level_offset, const int32_t* h_up_end,
+                          const int32_t* c_level_offset, const int32_t* c_up_end,
+                          const int32_t* chance_glog, int32_t D, int32_t max_actions) {
     if (max_actions > 4) return 0;
     int32_t k = 0;
-    while (k <= D && k < kFuseMax && m_level_offset[k + 1] - m_level_offset[k] <= kFuseThreads &&
-           h_level_offset[k + 1] - h_level_offset[k] <= kFuseThreads &&
-           (static_cast<int64_t>(c_level_offset[k + 1] - c_level_offset[k]) << chance_glog[k]) <=
+    while (k <= D && k < kFuseMax && m_up_end[k] - m_level_offset[k] <= kFuseThreads &&
+           h_up_end[k] - h_level_offset[k] <= kFuseThreads &&
+           (static_cast<int64_t>(c_up_end[k] - c_level_offset[k]) << chance_glog[k]) <=
                kFuseThreads)
         ++k;
     return k;
@@ -981,12 +1314,14 @@ WarmTable up_warm(const XDev& x, int32_t fu) {
 }  // namespace
 
 int32_t derived_reach_level(const XDev& x) {
-    // the deepest decision level (its children are all terminal), when it has a launch of its
-    // own on both sweeps and no chance nodes
-    const int32_t ld = x.D - 1;
+    // the deepest level with upper decision nodes, when their children are all terminal (no
+    // pack starts below them), it has a launch of its own on both sweeps and no upper chance
+    // nodes
+    int32_t ld = x.D - 1;
+    while (ld >= 1 && x.reach_units_host[ld] == 0) --ld;
     const int32_t top = x.path_reach > x.fused_reach ? x.path_reach : x.fused_reach;
-    const bool ok = ld >= 1 + top && ld >= x.fused_up &&
-                    x.c_level_offset_host[ld + 1] == x.c_level_offset_host[ld];
+    const bool ok = ld >= 1 + top && ld >= x.fused_up && x.only_terminal_children_host[ld] &&
+                    x.c_up_end_host[ld] == x.c_level_offset_host[ld];
     return ok ? ld : -1;
 }
 
@@ -999,15 +1334,18 @@ void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, L
     if (fr > 0) {
         LevelTable t{};
         t.n = fr;
-        for (int32_t i = 0; i < fr; ++i) {  // entry i is level 1 + i
+        int64_t units = 0;
+        for (int32_t i = 0; i < fr; ++i) {  // entry i is level 1 + i, its upper prefix
             t.lo[i] = lo[1 + i];
-            t.hi[i] = lo[2 + i];
+            t.hi[i] = x.up_end_host[1 + i];
+            units += x.reach_units_host[1 + i];
         }
-        pre(XK_REACH, -1, lo[1 + fr] - lo[1]);
-        hipLaunchKernelGGL(k_x_reach_top, dim3(1), dim3(kFuseThreads), 0, st, t, reach_warm(x, fr),
-                           x.N, x.parent,
-                           x.edge, x.meta, x.prob, x.reach);
-        post(XK_REACH);
+        if (units > 0) {
+            pre(XK_REACH, -1, units);
+            hipLaunchKernelGGL(k_x_reach_top, dim3(1), dim3(kFuseThreads), 0, st, t,
+                               reach_warm(x, fr), x.N, x.parent, x.edge, x.meta, x.prob, x.reach);
+            post(XK_REACH);
+        }
     }
     const int32_t fp = x.path_reach;
     if (fp > fr) {
@@ -1030,14 +1368,29 @@ void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, L
         launch_reach_level(x, l, st);
         post(XK_REACH);
     }
-    // bottom-up: a launch per deep level, then the shallow levels in one workgroup
     const UpArgs a = up_args(x, rule);
+    // the subtree packs, tier by tier: top-down from the highest tier, tier 1 through both
+    // sweeps, bottom-up from tier 2 (one workgroup per pack)
+    // with no upper level to finish bottom-up, the last pack launch counts the iteration
+    const bool pack_counts = rule.count && !x.upper_bottom_up && x.n_tiers >= 1;
+    auto pack_launch = [&](int32_t t, int mode, bool count) {
+        const int32_t p0 = x.tier_offset_host[t - 1], np = x.tier_offset_host[t] - p0;
+        PackArgs pa{x.packs, x.pack_blob, p0, mode, x.keep_nodes, count ? 1 : 0, x.pack_done};
+        pre(XK_SUBTREE, -10 * mode - t, x.tier_dec_host[t - 1]);
+        hipLaunchKernelGGL(k_x_pack<kPackThreads>, dim3(np), dim3(kPackThreads), 0, st, a, pa);
+        post(XK_SUBTREE);
+    };
+    for (int32_t t = x.n_tiers; t >= 2; --t) pack_launch(t, 1, false);
+    if (x.n_tiers >= 1) pack_launch(1, 0, pack_counts && x.n_tiers == 1);
+    for (int32_t t = 2; t <= x.n_tiers; ++t) pack_launch(t, 2, pack_counts && t == x.n_tiers);
+    // bottom-up: a launch per deep level, then the shallow levels in one workgroup (upper
+    // prefixes only)
     UpArgs ad = a;
     ad.derive_reach = 1;
     const int32_t fu = x.fused_up;
     for (int32_t l = x.D; l >= fu; --l) {
-        const int32_t nunits = x.h_level_offset_host[l + 1] - x.h_level_offset_host[l] +
-                               x.c_level_offset_host[l + 1] - x.c_level_offset_host[l];
+        const int32_t nunits = x.h_up_end_host[l] - x.h_level_offset_host[l] +
+                               x.c_up_end_host[l] - x.c_level_offset_host[l];
         if (nunits == 0) continue;
         const UpArgs& al = derive && l == ld ? ad : a;
         pre(XK_UP, l, x.m_level_offset_host[l + 1] - x.m_level_offset_host[l]);
@@ -1051,15 +1404,15 @@ void launch_x_iteration(const XDev& x, const UpdateRule& rule, hipStream_t st, L
         for (int32_t i = 0; i < fu; ++i) {  // entry i is level fu - 1 - i
             const int32_t l = fu - 1 - i;
             t.lo[i] = x.k_level_offset_host[l];
-            t.hi[i] = x.k_level_offset_host[l + 1];
+            t.hi[i] = x.k_up_end_host[l];
             t.clo[i] = x.c_level_offset_host[l];
-            t.chi[i] = x.c_level_offset_host[l + 1];
+            t.chi[i] = x.c_up_end_host[l];
             t.glog[i] = x.chance_glog_host[l];
         }
         pre(XK_UP, -1, x.m_level_offset_host[fu] - x.m_level_offset_host[0]);
         hipLaunchKernelGGL(k_x_up_top, dim3(1), dim3(kFuseThreads), 0, st, a, t, up_warm(x, fu));
         post(XK_UP);
-    } else if (rule.count) {
+    } else if (rule.count && !pack_counts) {
         // the linear-averaging weight of every launch above read T: count the iteration last
         hipLaunchKernelGGL(k_x_tick, dim3(1), dim3(64), 0, st, x.T);
     }

@@ -6,11 +6,12 @@
 #include <cstdint>
 
 #include "kernels.hpp"
+#include "xplan.hpp"
 
 namespace cfr {
 
 // Timer kinds continue after the node engine's kinds.
-enum XKernelKind { XK_REACH = K_NUM_KINDS, XK_UP = K_NUM_KINDS + 1 };
+enum XKernelKind { XK_REACH = K_NUM_KINDS, XK_UP = K_NUM_KINDS + 1, XK_SUBTREE = K_NUM_KINDS + 2 };
 const char* xkernel_kind_name(int kind);
 
 // Launch shapes are chosen per log2 bucket of a launch's work items:
@@ -62,12 +63,32 @@ struct XDev {
     const int32_t* level_offset_host;
     const int32_t* h_level_offset_host;
     const int32_t* c_level_offset_host;
+    // per level, the end of the upper prefix (the part outside the subtree packs) of its nodes,
+    // infosets, chance nodes and bottom-up chunks (host)
+    const int32_t* up_end_host;
+    const int32_t* h_up_end_host;
+    const int32_t* c_up_end_host;
+    const int32_t* k_up_end_host;
+    // subtree packs (device): descriptors and records; tiers 1 .. n_tiers, the packs of tier t
+    // at tier_offset_host[t - 1] .. tier_offset_host[t] - 1 with tier_dec_host[t - 1] decision
+    // nodes; keep_nodes != 0: the pack launches also store every node's value and reach
+    int32_t n_tiers;
+    const int32_t* tier_offset_host;
+    const int64_t* tier_dec_host;
+    const PackDesc* packs;
+    const int32_t* pack_blob;
+    uint32_t* pack_done;   // finished workgroups of the counting pack launch (0 between launches)
+    int32_t keep_nodes;
+    // some upper level has bottom-up work (else the last pack launch counts the iteration)
+    int32_t upper_bottom_up;
     // the first levels run in one workgroup: top-down levels 1 .. fused_reach and
     // bottom-up levels fused_up - 1 .. 0 (0: none)
     int32_t fused_reach, fused_up;
     // top-down levels fused_reach + 1 .. path_reach run in one path launch (path_reach <=
     // fused_reach: none)
     int32_t path_reach;
+    // per level (host): 1 if every upper decision node of the level has only terminal children
+    const int8_t* only_terminal_children_host;
     // pair ranges [lo, hi) of prob that the single-workgroup kernels read (host): the infosets'
     // pairs and the chance probabilities of levels 0 .. fused_reach - 1 (entry 0) and
     // 0 .. fused_up - 1 (entry 1)
@@ -112,12 +133,13 @@ struct XDev {
 };
 
 // How many first levels the single-workgroup kernels take (from the plan's level tables).
-int32_t fusable_reach_levels(const int32_t* level_offset, int32_t D);
+int32_t fusable_reach_levels(const int32_t* level_offset, const int32_t* up_end, int32_t D);
 int32_t path_reach_levels(const int64_t* decision_nodes_per_level, int32_t fused, int32_t D,
                           int32_t max_depth);
-int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* h_level_offset,
-                          const int32_t* c_level_offset, const int32_t* chance_glog, int32_t D,
-                          int32_t max_actions);
+int32_t fusable_up_levels(const int32_t* m_level_offset, const int32_t* m_up_end,
+                          const int32_t* h_level_offset, const int32_t* h_up_end,
+                          const int32_t* c_level_offset, const int32_t* c_up_end,
+                          const int32_t* chance_glog, int32_t D, int32_t max_actions);
 
 // The level whose top-down reach its bottom-up launch computes (from the parents' stored
 // reach) instead of a top-down launch of its own, or -1.

@@ -61,11 +61,13 @@ class GameArgs:
 
 
 def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
-                engine: str = "auto", dcfr=None, schedule: str = "simultaneous") -> N.CfrConfig:
+                engine: str = "auto", dcfr=None, schedule: str = "simultaneous",
+                keep_node_values: bool = False) -> N.CfrConfig:
     if variant not in VARIANTS:
         raise ValueError(f"variant must be one of {list(VARIANTS)}")
-    if engine not in ("auto", "node"):
-        raise ValueError("engine must be 'auto' (public-block engine where it applies) or 'node'")
+    if engine not in ("auto", "packs", "node"):
+        raise ValueError("engine must be 'auto' (the public-block engine where it applies), "
+                         "'packs' (the same with subtree packs) or 'node'")
     cfg = N.CfrConfig()
     cfg.variant = VARIANTS[variant]
     cfg.averaging = AVERAGING[averaging]
@@ -76,7 +78,9 @@ def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
         raise ValueError("schedule must be 'simultaneous' or 'alternating'")
     cfg.flags = ((0 if graph else N.CFR_FLAG_NO_GRAPH) |
                  (N.CFR_FLAG_NODE_ENGINE if engine == "node" else 0) |
-                 (N.CFR_FLAG_ALTERNATING if schedule == "alternating" else 0))
+                 (N.CFR_FLAG_SUBTREE_PACKS if engine == "packs" else 0) |
+                 (N.CFR_FLAG_ALTERNATING if schedule == "alternating" else 0) |
+                 (N.CFR_FLAG_KEEP_NODE_VALUES if keep_node_values else 0))
     return cfg
 
 
@@ -95,23 +99,60 @@ PLAN_DTYPES = {
     "x_child_begin": np.int32, "x_child_stride": np.int32, "x_child_list": np.int32,
     "x_infoset_canon": np.int32, "x_q_offset": np.int32, "x_member_offset": np.int32,
     "x_members": np.int32, "x_h_level_offset": np.int32, "x_chance_nodes": np.int32,
-    "x_c_level_offset": np.int32, "x_q_input": np.int32,
+    "x_c_level_offset": np.int32, "x_q_input": np.int32, "x_up_end": np.int32,
+    "x_h_up_end": np.int32, "x_c_up_end": np.int32, "x_packs": np.int32,
+    "x_pack_blob": np.int32, "x_tier_offset": np.int32,
 }
+# fields of one subtree pack in x_packs (int32 each; the per-level ranges have 9 entries)
+PACK_LEVELS = 8
+PACK_FIELDS = (["tier", "level0", "nlv", "n_dec", "n_mem", "n_ch", "n_root", "n_inf", "n_pairs",
+                "n_kid", "off_root", "off_mem", "off_inf", "off_ch", "off_kid", "off_node"] +
+               [f"{name}{i}" for name in ("mlo", "clo") for i in range(PACK_LEVELS + 1)])
 
 
-def host_layout(game, names=None) -> dict:
-    """The canonical layout flattened on the host by the library (no GPU needed)."""
+def packs(lay: dict) -> list:
+    """The subtree packs of a host layout (x_packs) as dicts; mlo and clo as lists."""
+    raw = lay["x_packs"].reshape(-1, len(PACK_FIELDS))
+    out = []
+    for row in raw:
+        pk = {name: int(v) for name, v in zip(PACK_FIELDS[:16], row[:16])}
+        for j, name in enumerate(("mlo", "clo")):
+            pk[name] = [int(v) for v in row[16 + j * 9:16 + (j + 1) * 9]]
+        out.append(pk)
+    return out
+
+
+def host_layout(game, names=None, packs: bool = False) -> dict:
+    """The canonical layout flattened on the host by the library (no GPU needed); the plan
+    arrays with subtree packs if ``packs``."""
     lib = N.load()
     args = GameArgs(game)
     h = ctypes.c_void_p()
-    N.check(lib.cfr_host_layout_create(ctypes.byref(args.struct), ctypes.byref(h)))
+    N.check(lib.cfr_host_layout_create(ctypes.byref(args.struct),
+                                       N.CFR_FLAG_SUBTREE_PACKS if packs else 0, ctypes.byref(h)))
+    return _read_host_layout(lib, h, names or LAYOUT_DTYPES)
+
+
+def host_batch_layout(game_list, names, packs: bool = False) -> dict:
+    """The forest plan of a batch, built on the host by the library (plan arrays only)."""
+    lib = N.load()
+    args = [GameArgs(g) for g in game_list]
+    arr = (N.CfrGame * len(args))(*[a.struct for a in args])
+    h = ctypes.c_void_p()
+    N.check(lib.cfr_host_layout_create_batch(arr, len(args),
+                                             N.CFR_FLAG_SUBTREE_PACKS if packs else 0,
+                                             ctypes.byref(h)))
+    return _read_host_layout(lib, h, names)
+
+
+def _read_host_layout(lib, h, names) -> dict:
     try:
         out = {}
-        for name in (names or LAYOUT_DTYPES):
+        for name in names:
             nbytes = lib.cfr_host_layout_bytes(h, name.encode())
             if nbytes < 0:
                 raise KeyError(name)
-            dt = np.dtype(LAYOUT_DTYPES.get(name) or PLAN_DTYPES[name])
+            dt = np.dtype(LAYOUT_DTYPES.get(name) or PLAN_DTYPES.get(name) or np.int32)
             arr = np.empty(nbytes // dt.itemsize, dtype=dt)
             N.check(lib.cfr_host_layout_get(h, name.encode(), arr.ctypes.data_as(ctypes.c_void_p),
                                             nbytes))
@@ -131,17 +172,19 @@ def default_launch_shape(lib=None) -> "N.CfrLaunchShape":
 class Solver:
     """CFR (vanilla, CFR+ or discounted CFR) over one game, resident on one GPU. ``dcfr``:
     (alpha, beta, gamma) of variant 'dcfr' (default (1.5, 0, 2)); ``schedule``: 'simultaneous'
-    (both players' updates in one pass) or 'alternating' (player 1's pass, then player 2's)."""
+    (both players' updates in one pass) or 'alternating' (player 1's pass, then player 2's);
+    ``keep_node_values``: the subtree-pack launch also stores every node's value and reach, so
+    that node_values() can read them (off by default: the packs keep them on chip)."""
 
     def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
                  graph: bool = True, stream=None, engine: str = "auto", tuned: bool = True,
-                 dcfr=None, schedule: str = "simultaneous"):
+                 dcfr=None, schedule: str = "simultaneous", keep_node_values: bool = False):
         import torch
 
         self._lib = N.load()
         self.variant = variant
         args = GameArgs(game)
-        cfg = make_config(variant, averaging, graph, engine, dcfr, schedule)
+        cfg = make_config(variant, averaging, graph, engine, dcfr, schedule, keep_node_values)
         info = N.CfrPlanInfo()
         N.check(self._lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg),
                                    ctypes.byref(info)))
@@ -295,7 +338,7 @@ class BatchSolver(Solver):
 
     def __init__(self, game_list, variant: str = "cfr+", averaging=None, device: str = "cuda",
                  graph: bool = True, stream=None, tuned: bool = True, dcfr=None,
-                 schedule: str = "simultaneous"):
+                 schedule: str = "simultaneous", engine: str = "auto"):
         import torch
 
         self._lib = N.load()
@@ -303,7 +346,9 @@ class BatchSolver(Solver):
         self._args = [GameArgs(g) for g in game_list]
         n = len(self._args)
         arr = (N.CfrGame * n)(*[a.struct for a in self._args])
-        cfg = make_config(variant, averaging, graph, dcfr=dcfr, schedule=schedule)
+        if engine not in ("auto", "packs"):
+            raise ValueError("a batch runs on the public-block engine: 'auto' or 'packs'")
+        cfg = make_config(variant, averaging, graph, engine=engine, dcfr=dcfr, schedule=schedule)
         info = N.CfrPlanInfo()
         N.check(self._lib.cfr_plan_batch(arr, n, ctypes.byref(cfg), ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}

@@ -1,0 +1,152 @@
+// Host-only driver of the planners, built by tests/test_host_sanitized.py with the address and
+// undefined-behaviour sanitizers: flattens and plans every game of a file, reads every array of
+// the host layout export, and plans the file's games as one batch (with and without subtree
+// packs), exercising the same host code cfr_build and cfr_build_batch run before they touch a
+// GPU.
+//
+// File format (little endian): int32 n_games; per game: int64 n_nodes, int32 parent[n],
+// int32 node_infoset[n], int32 node_action[n], int32 n_infosets, int8 infoset_player[h],
+// int32 infoset_num_actions[h], int64 n_chance, double chance_prob[n_chance],
+// double payoff_u1[n].
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/cfr.h"
+#include "../../paper_2408_14778_amd/csrc/flatten.hpp"
+#include "../../paper_2408_14778_amd/csrc/host_plan.hpp"
+#include "../../paper_2408_14778_amd/csrc/xplan.hpp"
+
+namespace {
+thread_local std::string g_err;
+}
+
+namespace cfr {
+int set_error(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+}  // namespace cfr
+
+extern "C" const char* cfr_last_error(void) { return g_err.c_str(); }
+
+namespace {
+
+struct GameData {
+    std::vector<int32_t> parent, node_infoset, node_action, nact;
+    std::vector<int8_t> player;
+    std::vector<double> chance, payoff;
+    cfr_game g{};
+};
+
+template <class T>
+bool read(FILE* f, std::vector<T>& v, int64_t n) {
+    v.resize(static_cast<size_t>(n));
+    return n == 0 || std::fread(v.data(), sizeof(T), static_cast<size_t>(n), f) == static_cast<size_t>(n);
+}
+
+const char* kNames[] = {"level_offset", "node_id", "parent", "child_begin", "node_player",
+                        "node_infoset", "node_edge", "infoset_id", "infoset_player", "q_offset",
+                        "chance_id", "cq_offset", "member_offset", "members", "chance_prob",
+                        "payoff", "q_input", "x_canon_of", "x_parent", "x_edge", "x_meta",
+                        "x_child_begin", "x_child_stride", "x_child_list", "x_infoset_canon",
+                        "x_q_offset", "x_member_offset", "x_members", "x_h_level_offset",
+                        "x_chance_nodes", "x_c_level_offset", "x_q_input", "x_up_end",
+                        "x_h_up_end", "x_c_up_end", "x_packs", "x_pack_blob", "x_tier_offset",
+                        "x_level_offset"};
+
+// Reads every array a host layout exports (names it does not hold report < 0); returns the
+// number read.
+int read_all(cfr_host_layout* h) {
+    int n = 0;
+    for (const char* name : kNames) {
+        const int64_t b = cfr_host_layout_bytes(h, name);
+        if (b < 0) continue;
+        std::vector<unsigned char> buf(static_cast<size_t>(b));
+        if (cfr_host_layout_get(h, name, buf.data(), b) != CFR_OK) return -1;
+        ++n;
+    }
+    return n;
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+    if (argc != 2) {
+        std::fprintf(stderr, "usage: plan_driver GAMES.bin\n");
+        return 2;
+    }
+    FILE* f = std::fopen(argv[1], "rb");
+    if (f == nullptr) return 2;
+    int32_t n_games = 0;
+    if (std::fread(&n_games, 4, 1, f) != 1 || n_games < 1) return 2;
+    std::vector<GameData> games(static_cast<size_t>(n_games));
+    for (GameData& d : games) {
+        int64_t n = 0, nc = 0;
+        int32_t h = 0;
+        bool ok = std::fread(&n, 8, 1, f) == 1 && read(f, d.parent, n) && read(f, d.node_infoset, n) &&
+                  read(f, d.node_action, n) && std::fread(&h, 4, 1, f) == 1 &&
+                  read(f, d.player, h) && read(f, d.nact, h) && std::fread(&nc, 8, 1, f) == 1 &&
+                  read(f, d.chance, nc) && read(f, d.payoff, n);
+        if (!ok) return 2;
+        if (d.chance.empty()) d.chance.push_back(0.0);
+        d.g.n_nodes = n;
+        d.g.parent = d.parent.data();
+        d.g.node_infoset = d.node_infoset.data();
+        d.g.node_action = d.node_action.data();
+        d.g.n_infosets = h;
+        d.g.infoset_player = d.player.data();
+        d.g.infoset_num_actions = d.nact.data();
+        d.g.chance_prob = d.chance.data();
+        d.g.payoff_u1 = d.payoff.data();
+        d.g.payoff_u2 = nullptr;
+    }
+    std::fclose(f);
+    std::vector<cfr_game> gs;
+    for (size_t i = 0; i < games.size(); ++i) {
+        GameData& d = games[i];
+        gs.push_back(d.g);
+        cfr_host_layout* h = nullptr;
+        if (cfr_host_layout_create(&d.g, CFR_FLAG_SUBTREE_PACKS, &h) != CFR_OK) {
+            std::printf("game %zu: %s\n", i, cfr_last_error());
+            return 1;
+        }
+        const int arrays = read_all(h);
+        cfr_host_layout_destroy(h);
+        // the per-level tables the solver derives from a plan, with and without packs
+        cfr::Layout L;
+        std::string err;
+        if (cfr::flatten(d.g, L, err) != CFR_OK) return 1;
+        for (bool packs : {true, false}) {
+            if (!L.level_pure) break;
+            cfr::ExecPlan P;
+            if (cfr::build_exec_plan(L, P, err, packs) != CFR_OK) return 1;
+            std::vector<int64_t> dec;
+            std::vector<int8_t> only;
+            cfr::upper_level_stats(P, dec, only);
+        }
+        std::printf("game %zu: %lld nodes, %d arrays\n", i, static_cast<long long>(d.g.n_nodes), arrays);
+    }
+    for (uint32_t flags : {0u, static_cast<uint32_t>(CFR_FLAG_SUBTREE_PACKS)}) {
+        cfr_host_layout* h = nullptr;
+        if (cfr_host_layout_create_batch(gs.data(), n_games, flags, &h) != CFR_OK) {
+            std::printf("batch: %s\n", cfr_last_error());
+            return 1;
+        }
+        const int arrays = read_all(h);
+        cfr_host_layout_destroy(h);
+        std::vector<cfr::ExecPlan> plans;
+        int32_t max_actions = 0;
+        std::string err;
+        if (cfr::plan_games(gs.data(), n_games, plans, max_actions, err, flags != 0) != CFR_OK) return 1;
+        cfr::ExecPlan F;
+        if (cfr::build_forest_plan(plans, F, err) != CFR_OK) return 1;
+        std::vector<int64_t> dec;
+        std::vector<int8_t> only;
+        cfr::upper_level_stats(F, dec, only);
+        std::printf("batch (flags %u): %d arrays, %zu packs, %d tiers\n", flags, arrays, F.packs.size(), F.n_tiers);
+    }
+    std::printf("ok\n");
+    return 0;
+}

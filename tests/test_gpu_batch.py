@@ -28,8 +28,12 @@ def _mixed_games():
     return out
 
 
+@pytest.mark.parametrize("engine", ["auto", "packs"])
 @pytest.mark.parametrize("variant", ["vanilla", "cfr+", "dcfr"])
-def test_batch_one_iteration_matches_single_and_oracle(variant):
+def test_batch_one_iteration_matches_single_and_oracle(variant, engine):
+    """Per game, the forest's iteration equals the game's own and the oracle's; with the
+    per-level launches over the forest's levels, and with subtree packs (each game's packs laid
+    out in the forest)."""
     from paper_2408_14778_amd import BatchSolver, Solver
     gl = _mixed_games()
     states = [games.random_state(g, seed=7 + i, nonnegative=(variant == "cfr+"))
@@ -37,16 +41,17 @@ def test_batch_one_iteration_matches_single_and_oracle(variant):
     T = 37
     R = np.concatenate([st[1] for st in states])
     S = np.concatenate([st[2] for st in states])
-    b = BatchSolver(gl, variant)
+    b = BatchSolver(gl, variant, engine=engine)
     assert b.n_q == len(R)
     rl = b.layout("reach_launch")
-    assert rl[len(rl) - 2] == 4  # the deepest decision level: reach in its bottom-up launch
+    # the deepest decision level: reach in its bottom-up launch, or inside the packs
+    assert rl[len(rl) - 2] == (4 if engine == "auto" else 5)
     b.set_state(T, R, S)
     b.iterate(1)
     Tb, Rb, Sb = b.get_state()
     assert Tb == T + 1
     for g, (Rg, Sg), st in zip(gl, zip(b.split(Rb), b.split(Sb)), states):
-        s = Solver(g, variant)
+        s = Solver(g, variant, engine=engine)
         s.set_state(T, st[1], st[2])
         s.iterate(1)
         _, Rs, Ss = s.get_state()

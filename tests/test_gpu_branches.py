@@ -46,11 +46,13 @@ def _rel(gpu, ref):
     return float(np.abs(gpu - ref).max()) / scale if ref.size else 0.0
 
 
-def _solver(name, variant):
+def _solver(name, variant, engine="auto", keep_node_values=False):
+    """engine 'auto' keeps every infoset in the per-level kernels, whose branches these tests
+    are about; 'packs' lets the subtree packs take what fits them."""
     from paper_2408_14778_amd import Solver
     make, cap, branch = GAMES[name]
     g = make()
-    s = Solver(g, variant)
+    s = Solver(g, variant, engine=engine, keep_node_values=keep_node_values)
     assert s.info["engine"] == 1, "expected the public-block engine"
     if cap is not None:
         s.set_launch_shape(up_threads=cap, up_members=1)
@@ -64,10 +66,11 @@ def _solver(name, variant):
     return g, s
 
 
+@pytest.mark.parametrize("engine", ["auto", "packs"])
 @pytest.mark.parametrize("variant", ["vanilla", "cfr+", "dcfr"])
 @pytest.mark.parametrize("name", sorted(GAMES))
-def test_one_iteration_parity_on_wide_and_big_infosets(name, variant):
-    g, s = _solver(name, variant)
+def test_one_iteration_parity_on_wide_and_big_infosets(name, variant, engine):
+    g, s = _solver(name, variant, engine, keep_node_values=True)
     T, R, S = games.random_state(g, seed=len(name) + 5, nonnegative=(variant == "cfr+"))
     s.set_state(T, R, S)
     s.iterate(1)

@@ -25,7 +25,7 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-ENGINES = ["auto", "node"]
+ENGINES = ["auto", "packs", "node"]
 
 
 def _solver(g, variant="vanilla", **kw):
@@ -93,9 +93,13 @@ def test_deepest_level_reach_in_its_bottom_up_launch():
 def test_large_game_launch_plan(large_game):
     """The large game's top-down launches: levels 1-7 (at most 175,032 decision nodes each) in
     the launch that walks up to the roots, levels 8-13 one launch each, level 14 (the deepest
-    decision level, no chance nodes) in its bottom-up launch, level 15 terminal only."""
+    decision level, no chance nodes) in its bottom-up launch, level 15 terminal only. With
+    subtree packs, levels 12-14 lie entirely in packs."""
     s = _solver(large_game, "cfr+")
     assert s.layout("reach_launch").tolist() == [0] + [2] * 7 + [3] * 6 + [4, 0]
+    rl = _solver(large_game, "cfr+", engine="packs").layout("reach_launch").tolist()
+    print("reach_launch with packs:", rl, flush=True)
+    assert rl[12:15] == [5, 5, 5] and rl[15] == 0
 
 
 @pytest.mark.parametrize("engine", ENGINES)
@@ -104,8 +108,8 @@ def test_large_game_launch_plan(large_game):
 def test_one_iteration_parity(name, variant, engine):
     g = SMALL_GAMES[name]()
     T, R, S = games.random_state(g, seed=len(name), nonnegative=(variant == "cfr+"))
-    s = _solver(g, variant, engine=engine)
-    if engine == "auto":
+    s = _solver(g, variant, engine=engine, keep_node_values=True)
+    if engine != "node":
         assert s.info["engine"] == 1  # level-pure, few actions: the public-block engine
     s.set_state(T, R, S)
     s.iterate(1)
@@ -210,23 +214,51 @@ def test_alternating_exploitability_after_T_iterations(name, variant, iters, eng
     assert abs(e["expl"] - ref["expl"]) <= 1e-4, (e, ref)
 
 
+def _strict_checkpoint(cps, band=2.5e-5):
+    """The last checkpoint before the fp32-noise ensemble first leaves `band` of the exact run."""
+    last = None
+    for T in sorted(cps, key=int):
+        if cps[T]["spread"] > band:
+            break
+        last = T
+    return last
+
+
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
 def test_medium_game_exploitability_against_golden(variant, engine):
-    """1,000 iterations on the medium game against the FP64 oracle's stored result. The
-    tolerance is 1e-4, widened to twice the spread that fp32-sized rounding noise alone
-    produces in the oracle's own result (stored beside it): past a few hundred iterations
-    regret matching amplifies differences at the unit-roundoff level."""
-    gold = json.load(open(os.path.join(HERE, "golden", "medium_game_expl.json")))
-    ref = gold[variant]
+    """The medium game (100,981 nodes) against the FP64 oracle's stored run, in two parts.
+
+    Strict: at the last checkpoint where every run of an ensemble that carries fp32-sized
+    rounding (tests/golden/make_golden.py: noise of D 2^-24 times the magnitude each regret is
+    summed from, the same on the strategy-sum increments, R and S rounded to fp32) stays within
+    2.5e-5 of the exact run (T = 100 for vanilla CFR, 200 for CFR+), the exploitability is
+    within 1e-4 of the exact run's.
+
+    At T = 1,000 the runs have decorrelated: regret matching switches strategies where regrets
+    cross zero, so unit-roundoff differences grow over the run, and the ensemble spreads over
+    2.4e-3 (vanilla) and 2.4e-4 (CFR+) around the exact value; no fp32 implementation can be
+    held to 1e-4 there. The GPU value must then lie within 4 standard deviations of the
+    ensemble's mean."""
+    gold = json.load(open(os.path.join(HERE, "golden", "medium_game_expl.json")))[variant]
+    cps = gold["checkpoints"]
+    T_strict = _strict_checkpoint(cps)
+    assert T_strict is not None and int(T_strict) >= 100
     g = games.leduc_like(6, 2, deal="joint")
     s = _solver(g, variant, engine=engine)
-    s.iterate(ref["iterations"])
-    e = s.exploitability()
-    tol = max(1e-4, 2.0 * ref["noise_spread"])
-    print(f"medium {variant} {engine}: gpu {e['expl']:.6g} oracle {ref['expl']:.6g} "
-          f"diff {abs(e['expl'] - ref['expl']):.3g} tol {tol:.3g}", flush=True)
-    assert abs(e["expl"] - ref["expl"]) <= tol, (e, ref)
+    s.iterate(int(T_strict))
+    e = s.exploitability()["expl"]
+    ref = cps[T_strict]["expl"]
+    print(f"medium {variant} {engine} T={T_strict}: gpu {e:.7f} oracle {ref:.7f} "
+          f"diff {abs(e - ref):.2e}", flush=True)
+    assert abs(e - ref) <= 1e-4
+    s.iterate(gold["iterations"] - int(T_strict))
+    e = s.exploitability()["expl"]
+    fin = cps[str(gold["iterations"])]
+    z = (e - fin["mean"]) / fin["std"]
+    print(f"medium {variant} {engine} T={gold['iterations']}: gpu {e:.6f} oracle {fin['expl']:.6f} "
+          f"ensemble {fin['mean']:.6f} +- {fin['std']:.2e} (z {z:+.2f})", flush=True)
+    assert abs(z) <= 4.0
 
 
 @pytest.mark.parametrize("engine", ENGINES)
