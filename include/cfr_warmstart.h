@@ -41,6 +41,18 @@ int cfr_mlp_forward(cfr_mlp* net, const void* x, int32_t batch, float* logits);
 int cfr_mlp_train_step(cfr_mlp* net, const void* x, const float* target, const float* mask,
                        int32_t batch, float lr, float* loss);
 int cfr_mlp_get_grads(cfr_mlp* net, float* grads, int64_t n);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the forward pass of cfr_mlp_forward, same kernels
+ * and the same logits bit for bit, with the two hidden activations in a file-scope device
+ * array of 16 MiB (one per GPU the library runs on, held until the process ends) instead of
+ * the network's workspace, and the logits written directly to `logits` (device FP32
+ * [batch x outputs]). batch x hidden may be at most 4,194,304 (CFR_EINVAL otherwise; e.g.
+ * 16,384 rows at hidden 256). No call allocates or frees memory; the array's address is
+ * looked up once per device, on the first call with that device current (call with the
+ * device of the network's stream current). Enqueued on the network's stream. Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams, other threads,
+ * other networks) race and must be ordered by the caller. */
+int cfr_mlp_forward_noalloc(cfr_mlp* net, const void* x, int32_t batch, float* logits);
 int cfr_mlp_destroy(cfr_mlp* net);
 
 /* Feature extractor for poker subgames: n descriptors (16 int16 fields each: player, own

@@ -8,37 +8,15 @@
 
 #include "../../include/cfr_warmstart.h"
 #include "mlp.hpp"
+#include "mlp_net.hpp"
 
 namespace cfr {
 int set_error(int code, const std::string& msg);  // solver.cpp
 }
 
-struct cfr_mlp {
-    int32_t F, H, A, maxB;
-    hipStream_t st;
-    int64_t n_params;
-    // [W1 | b1 | W2 | b2 | W3 | b3] blocks
-    float *w, *g, *m, *v;
-    __bf16* wb;
-    // activations
-    __bf16 *A1, *A2, *dZ3, *dZ2, *dZ1;
-    float *Z3, *loss;
-    float* part;  // split-K partials: kMaxSplits * max(F, H) * max(H, A) floats
-    int64_t step;
-};
-
 namespace {
 
-int64_t offsets(int32_t F, int32_t H, int32_t A, int64_t off[7]) {
-    off[0] = 0;                       // W1
-    off[1] = off[0] + int64_t{F} * H;  // b1
-    off[2] = off[1] + H;               // W2
-    off[3] = off[2] + int64_t{H} * H;  // b2
-    off[4] = off[3] + H;               // W3
-    off[5] = off[4] + int64_t{H} * A;  // b3
-    off[6] = off[5] + A;
-    return off[6];
-}
+using cfr::offsets;
 
 size_t layout(cfr_mlp& n, void* base, int32_t F, int32_t H, int32_t A, int32_t maxB) {
     uintptr_t p = reinterpret_cast<uintptr_t>(base);

@@ -39,6 +39,8 @@ def _lib():
                                                  ctypes.c_int64]),
             "cfr_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                ctypes.c_void_p]),
+            "cfr_mlp_forward_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                       ctypes.c_int32, ctypes.c_void_p]),
             "cfr_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                   ctypes.c_void_p, ctypes.c_int32, ctypes.c_float,
                                                   ctypes.POINTER(ctypes.c_float)]),
@@ -153,6 +155,13 @@ class WarmStartNet:
             N.check(self.lib.cfr_mlp_forward(self._h, ctypes.c_void_p(x[s:e].data_ptr()), e - s,
                                              ctypes.c_void_p(out[s:e].data_ptr())))
         return out
+
+    def forward_noalloc(self, x, out) -> None:
+        """The allocation-free forward pass into an existing fp32 device tensor out [B, outputs]
+        (activations in the library's own device array; see cfr_mlp_forward_noalloc)."""
+        assert out.dtype.itemsize == 4 and out.is_cuda and out.shape[0] == x.shape[0]
+        N.check(self.lib.cfr_mlp_forward_noalloc(self._h, ctypes.c_void_p(x.data_ptr()),
+                                                 int(x.shape[0]), ctypes.c_void_p(out.data_ptr())))
 
     def train_step(self, x, target, mask, lr: float) -> float:
         loss = ctypes.c_float()
