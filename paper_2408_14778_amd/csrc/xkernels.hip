@@ -64,8 +64,10 @@ __device__ __forceinline__ int32_t child_of(const int32_t* __restrict__ child_be
 // Reach of NPT nodes x = first + u * stride: the factor of whoever acted into the node (meta
 // bits 2-3) is multiplied by the edge probability (sigma or sigma_0). Terminal nodes need no
 // reach. All loads of the NPT nodes are issued before any of them is used, and a node's parent
-// and edge are loaded together with its kind.
-template <int NPT>
+// and edge are loaded together with its kind. The chance plane depends on sigma_0 alone: FULL
+// computes all three planes (once, when the solver is set up); otherwise only the two player
+// planes are written, a chance edge copies them and the chance plane is left as it is.
+template <int NPT, bool FULL>
 __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64_t hi, int64_t N,
                                             const int32_t* __restrict__ parent,
                                             const int32_t* __restrict__ edge,
@@ -93,8 +95,8 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
         if (kind[u] & 3) {
             r1[u] = reach[p[u]];
             r2[u] = reach[N + p[u]];
-            rc[u] = reach[2 * N + p[u]];
-            s[u] = prob[e[u]];
+            if (FULL) rc[u] = reach[2 * N + p[u]];
+            if (FULL || (kind[u] >> 2) != 1) s[u] = prob[e[u]];
         }
     }
 #pragma unroll
@@ -106,7 +108,7 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
         else rc[u] *= s[u];
         reach[xs[u]] = r1[u];
         reach[N + xs[u]] = r2[u];
-        reach[2 * N + xs[u]] = rc[u];
+        if (FULL) reach[2 * N + xs[u]] = rc[u];
     }
 }
 
@@ -124,8 +126,8 @@ __global__ void __launch_bounds__(1024) k_x_reach(int32_t t0, int64_t N,
                                                   float* __restrict__ reach) {
     const int32_t t = t0 + static_cast<int32_t>(xcd_tile());
     const int32_t lo = tile_lo[t], hi = tile_hi[t];
-    reach_nodes<NPT>(lo + static_cast<int64_t>(threadIdx.x), blockDim.x, hi, N, parent, edge, meta,
-                     prob, reach);
+    reach_nodes<NPT, false>(lo + static_cast<int64_t>(threadIdx.x), blockDim.x, hi, N, parent, edge,
+                            meta, prob, reach);
 }
 
 // Several small levels in one launch without a barrier between them: the node of each lane
@@ -150,19 +152,29 @@ __global__ void __launch_bounds__(256) k_x_reach_path(int32_t t0, int32_t stop, 
     int32_t y = x;
     while (y >= stop && n < kPathDepth) {
         actor[n] = (meta[y] >> 2) & 3;
-        s[n] = prob[edge[y]];
+        s[n] = actor[n] == 1 ? 1.0f : prob[edge[y]];
         y = parent[y];
         ++n;
     }
-    float r1 = reach[y], r2 = reach[N + y], rc = reach[2 * N + y];
+    float r1 = reach[y], r2 = reach[N + y];
     for (int i = n - 1; i >= 0; --i) {
         if (actor[i] == 2) r1 *= s[i];
         else if (actor[i] == 3) r2 *= s[i];
-        else rc *= s[i];
     }
     reach[x] = r1;
     reach[N + x] = r2;
-    reach[2 * N + x] = rc;
+}
+
+// All three planes of one level's nodes lo .. hi - 1 (grid-stride), the chance plane included:
+// run level by level when the solver is set up.
+__global__ void __launch_bounds__(256) k_x_reach_full(int32_t lo, int32_t hi, int64_t N,
+                                                      const int32_t* __restrict__ parent,
+                                                      const int32_t* __restrict__ edge,
+                                                      const int8_t* __restrict__ meta,
+                                                      const float* __restrict__ prob,
+                                                      float* __restrict__ reach) {
+    for (int64_t x = lo + gid(); x < hi; x += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        reach_nodes<1, true>(x, 1, hi, N, parent, edge, meta, prob, reach);
 }
 
 // The levels one single-workgroup kernel takes, in the order it takes them; entry i covers
@@ -197,8 +209,8 @@ __global__ void __launch_bounds__(kFuseThreads) k_x_reach_top(LevelTable t, Warm
                                                               float* __restrict__ reach) {
     warm_lines(w, threadIdx.x);
     for (int32_t i = 0; i < t.n; ++i) {
-        reach_nodes<2>(t.lo[i] + threadIdx.x, kFuseThreads, t.hi[i], N, parent, edge, meta, prob,
-                       reach);
+        reach_nodes<2, false>(t.lo[i] + threadIdx.x, kFuseThreads, t.hi[i], N, parent, edge, meta,
+                              prob, reach);
         __syncthreads();
     }
 }
@@ -226,37 +238,35 @@ struct UpArgs {
     int64_t* T;
     UpdateRule rule;
     // derive_reach != 0 (the deepest decision level, whose children are all terminal): the
-    // level had no top-down launch; a member's reach is its parent's times its edge probability
-    // on the factor of whoever acted (the top-down products), computed and stored here
+    // level had no top-down launch; a member's player planes are its parent's times its edge
+    // probability on the factor of whoever acted (the top-down products), computed and stored
+    // here
     int32_t derive_reach;
     const int32_t* parent;
     const int32_t* edge;
     const int8_t* meta;
 };
 
-// The three reach planes of member node x: loaded, or (derive_reach) computed from the
-// parent's as the top-down pass would and stored.
+// The three reach planes of member node x: loaded, or (derive_reach) the player planes computed
+// from the parent's as the top-down pass would and stored (the chance plane is constant).
 __device__ __forceinline__ void member_reach(const UpArgs& a, int32_t x, float& r1, float& r2,
                                              float& rc) {
+    rc = a.reach[2 * a.N + x];
     if (!a.derive_reach) {
         r1 = a.reach[x];
         r2 = a.reach[a.N + x];
-        rc = a.reach[2 * a.N + x];
         return;
     }
     const int kind = a.meta[x];
     const int32_t p = a.parent[x], e = a.edge[x];
     r1 = a.reach[p];
     r2 = a.reach[a.N + p];
-    rc = a.reach[2 * a.N + p];
-    const float s = a.prob[e];
     const int actor = kind >> 2;  // 1 chance, 2 player 1, 3 player 2
+    const float s = actor != 1 ? a.prob[e] : 1.0f;
     if (actor == 2) r1 *= s;
     else if (actor == 3) r2 *= s;
-    else rc *= s;
     a.reach[x] = r1;
     a.reach[a.N + x] = r2;
-    a.reach[2 * a.N + x] = rc;
 }
 
 // Chance node ci (if ok) on a group of 2^glog lanes: lane l sums children l, l + 2^glog, ...,
@@ -1129,6 +1139,14 @@ void launch_x_reset(const XDev& x, hipStream_t st) {
                        x.level_offset_host[1], x.meta, x.payoff, x.value, x.reach);
     hipLaunchKernelGGL(k_x_br_setup, dim3(blocks_for(x.N)), dim3(kBlock), 0, st, x.N,
                        x.level_offset_host[1], x.meta, x.payoff, x.br_value, x.br_reach);
+    // the chance plane of every upper node, level by level (constant from here on)
+    for (int32_t l = 1; l < x.D; ++l) {
+        const int32_t lo = x.level_offset_host[l], hi = x.up_end_host[l];
+        if (hi <= lo) continue;
+        const unsigned grid = std::min<unsigned>(blocks_for(hi - lo), 4096u);
+        hipLaunchKernelGGL(k_x_reach_full, dim3(grid), dim3(kBlock), 0, st, lo, hi, x.N, x.parent,
+                           x.edge, x.meta, x.prob, x.reach);
+    }
 }
 
 namespace {
@@ -1263,20 +1281,18 @@ void warm_fill(WarmTable& w, int n) {
     }
 }
 
-// What k_x_reach_top reads: parent, edge and kind of levels 1 .. fr, the reach planes of
-// levels 0 .. fr - 1 and sigma at those levels' pairs and chance probabilities.
+// What k_x_reach_top reads: parent, edge and kind of levels 1 .. fr, the player reach planes of
+// levels 0 .. fr - 1 and sigma at those levels' pairs.
 WarmTable reach_warm(const XDev& x, int32_t fr) {
     WarmTable w{};
     int n = 0;
     const int32_t* lo = x.level_offset_host;
     warm_add(w, n, x.reach, lo[0], lo[fr]);
     warm_add(w, n, x.reach + x.N, lo[0], lo[fr]);
-    warm_add(w, n, x.reach + 2 * x.N, lo[0], lo[fr]);
     warm_add(w, n, x.parent, lo[1], lo[1 + fr]);
     warm_add(w, n, x.edge, lo[1], lo[1 + fr]);
     warm_add(w, n, x.meta, lo[1], lo[1 + fr]);
     warm_add(w, n, x.prob, x.top_q_lo[0], x.top_q_hi[0]);
-    warm_add(w, n, x.prob, x.top_c_lo[0], x.top_c_hi[0]);
     warm_fill(w, n);
     return w;
 }

@@ -125,7 +125,7 @@ struct XDev {
     float* R;
     float* S;
     float* value;    // N (terminals hold the payoff)
-    float* reach;    // 3N planes
+    float* reach;    // 3N planes: pi_1, pi_2 (every iteration), pi_c (set up once, constant)
     int64_t* T;
     float* br_reach;  // 2N: pi_{-1}, pi_{-2}
     float* br_value;  // 2N: values under player 1's, player 2's best response
