@@ -97,7 +97,15 @@ enum { CFR_AVG_DEFAULT = -1, CFR_AVG_UNIFORM = 0, CFR_AVG_LINEAR = 1 };
 #define CFR_FLAG_SUBTREE_PACKS 16u /* the public-block engine with subtree packs (below): the
                                     highest blocks whose subtrees fit one workgroup's LDS, tier by
                                     tier, run in pack launches instead of the per-level launches
-                                    (at most 4 actions per infoset; otherwise ignored).
+                                    (at most 4 actions per infoset; otherwise ignored). */
+#define CFR_FLAG_FP64 32u          /* values, probabilities, reaches, R and S in double precision
+                                    (the paper's 64-bit GPU variant, Section 4.1): the node engine
+                                    with every kernel instantiated for double, payoffs and chance
+                                    probabilities taken from the input's doubles. Strategies, state
+                                    and node values are read and written with the _f64 calls (their
+                                    float twins return CFR_EINVAL on such a solver, and the _f64
+                                    calls on an FP32 one); exploitability as usual. Not with
+                                    CFR_FLAG_SUBTREE_PACKS, nor for a batch (CFR_EINVAL).
                                     Other flag bits: CFR_EINVAL */
 
 typedef struct cfr_config {
@@ -192,6 +200,10 @@ int cfr_average_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_devi
  * cfr_average_strategy. */
 int cfr_current_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device);
 
+/* The same two for a solver built with CFR_FLAG_FP64, in double precision. */
+int cfr_average_strategy_f64(cfr_solver* s, double* out, int64_t n_q, int out_on_device);
+int cfr_current_strategy_f64(cfr_solver* s, double* out, int64_t n_q, int out_on_device);
+
 /* Best-response values of both players against the average strategy and the
  * exploitability (BR_1 + BR_2) / 2 (Section 2.2). Synchronises. Needs level-pure
  * infosets (CFR_ELEVEL otherwise). br_value may be NULL. */
@@ -202,6 +214,9 @@ int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]);
  * average_counterfactual_regret). Host arrays; both calls synchronise. */
 int cfr_get_state(cfr_solver* s, int64_t* T, float* R, float* S, int64_t n_q);
 int cfr_set_state(cfr_solver* s, int64_t T, const float* R, const float* S, int64_t n_q);
+/* The same for a solver built with CFR_FLAG_FP64, in double precision. */
+int cfr_get_state_f64(cfr_solver* s, int64_t* T, double* R, double* S, int64_t n_q);
+int cfr_set_state_f64(cfr_solver* s, int64_t T, const double* R, const double* S, int64_t n_q);
 
 /* Canonical layout export for checking (host copy, synchronises). `name` is one of
  * level_offset, node_id, parent, child_begin, node_player, node_infoset, node_edge,
@@ -222,6 +237,8 @@ int cfr_get_layout(cfr_solver* s, const char* name, void* out, int64_t bytes);
  * probabilities from the root, for decision nodes (terminal entries are unspecified).
  * Either pointer may be NULL. */
 int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes);
+/* The same for a solver built with CFR_FLAG_FP64, in double precision. */
+int cfr_get_node_values_f64(cfr_solver* s, double* u1, double* reach, int64_t n_nodes);
 
 /* Host-only flattening, for checking the canonical layout without a GPU: build the layout
  * of `game` on the host (validation as in cfr_plan), then read arrays by the names listed for

@@ -23,6 +23,7 @@ CFR_FLAG_NODE_ENGINE = 2
 CFR_FLAG_ALTERNATING = 4
 CFR_FLAG_KEEP_NODE_VALUES = 8
 CFR_FLAG_SUBTREE_PACKS = 16
+CFR_FLAG_FP64 = 32
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i8p = ctypes.POINTER(ctypes.c_int8)
@@ -99,14 +100,22 @@ SIGNATURES = {
                                             ctypes.c_int]),
     "cfr_current_strategy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_int]),
+    "cfr_average_strategy_f64": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                ctypes.c_int]),
+    "cfr_current_strategy_f64": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                ctypes.c_int]),
     "cfr_exploitability": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
     "cfr_get_state": (ctypes.c_int, [ctypes.c_void_p, _i64p, _f32p, _f32p, ctypes.c_int64]),
     "cfr_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _f32p, _f32p,
                                      ctypes.c_int64]),
+    "cfr_get_state_f64": (ctypes.c_int, [ctypes.c_void_p, _i64p, _f64p, _f64p, ctypes.c_int64]),
+    "cfr_set_state_f64": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, _f64p, _f64p,
+                                         ctypes.c_int64]),
     "cfr_layout_bytes": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_char_p]),
     "cfr_get_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p,
                                       ctypes.c_int64]),
     "cfr_get_node_values": (ctypes.c_int, [ctypes.c_void_p, _f32p, _f32p, ctypes.c_int64]),
+    "cfr_get_node_values_f64": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int64]),
     "cfr_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "cfr_host_layout_create": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_uint32,
                                               ctypes.POINTER(ctypes.c_void_p)]),

@@ -176,7 +176,7 @@ int plan_sizes(const cfr_game& g, Layout& L, std::string& err) {
     return CFR_OK;
 }
 
-int flatten(const cfr_game& g, Layout& L, std::string& err) {
+int flatten(const cfr_game& g, Layout& L, std::string& err, bool f64) {
     Work w;
     int rc = validate_and_order(g, w, err);
     if (rc != CFR_OK) return rc;
@@ -233,10 +233,13 @@ int flatten(const cfr_game& g, Layout& L, std::string& err) {
         for (int32_t a = 0; a < L.q_offset[h + 1] - L.q_offset[h]; ++a)
             L.q_input[L.q_offset[h] + a] = static_cast<int32_t>(in_qoff[L.infoset_id[h]] + a);
     L.chance_prob.resize(L.Q0);
+    L.chance_prob64.resize(f64 ? L.Q0 : 0);
     for (int64_t c = 0; c < L.H0; ++c)
-        for (int32_t a = 0; a < L.cq_offset[c + 1] - L.cq_offset[c]; ++a)
-            L.chance_prob[L.cq_offset[c] + a] =
-                static_cast<float>(g.chance_prob[in_coff[L.chance_id[c]] + a]);
+        for (int32_t a = 0; a < L.cq_offset[c + 1] - L.cq_offset[c]; ++a) {
+            const double p = g.chance_prob[in_coff[L.chance_id[c]] + a];
+            L.chance_prob[L.cq_offset[c] + a] = static_cast<float>(p);
+            if (f64) L.chance_prob64[L.cq_offset[c] + a] = p;
+        }
 
     // per-node arrays
     L.parent.resize(n);
@@ -245,6 +248,7 @@ int flatten(const cfr_game& g, Layout& L, std::string& err) {
     L.node_infoset.resize(n);
     L.node_edge.resize(n);
     L.payoff.resize(n);
+    L.payoff64.assign(f64 ? n : 0, 0.0);
     int64_t next_child = 1;
     L.n_terminals = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -259,6 +263,7 @@ int flatten(const cfr_game& g, Layout& L, std::string& err) {
             L.node_player[i] = -1;
             L.node_infoset[i] = -1;
             L.payoff[i] = static_cast<float>(g.payoff_u1[v]);
+            if (f64) L.payoff64[i] = g.payoff_u1[v];
             ++L.n_terminals;
         } else {
             L.node_player[i] = g.infoset_player[h];

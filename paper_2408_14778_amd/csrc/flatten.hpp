@@ -43,11 +43,15 @@ struct Layout {
     std::vector<int32_t> members;        // member nodes per rational infoset, ascending
     std::vector<float> chance_prob;      // Q0
     std::vector<float> payoff;           // N, u_1 at terminals, 0 elsewhere
+    // the same two in double precision (filled only when flatten is asked for them)
+    std::vector<double> chance_prob64;   // Q0
+    std::vector<double> payoff64;        // N
     std::vector<int32_t> q_input;        // canonical pair -> input pair
 };
 
-// Validates and flattens. Returns CFR_OK or a CFR_E* code with a message in `err`.
-int flatten(const cfr_game& g, Layout& out, std::string& err);
+// Validates and flattens. Returns CFR_OK or a CFR_E* code with a message in `err`. f64: also
+// fill chance_prob64 and payoff64 with the input's double values.
+int flatten(const cfr_game& g, Layout& out, std::string& err, bool f64 = false);
 
 // Validation and sizes only (no layout arrays kept).
 int plan_sizes(const cfr_game& g, Layout& sizes, std::string& err);

@@ -24,50 +24,62 @@ __device__ __forceinline__ int64_t gid() {
     return static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
 }
 
+// Arithmetic of both real types: fp32 (the default path) and fp64.
+__device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float pos_(float a) { return fmaxf(a, 0.0f); }
+__device__ __forceinline__ double pos_(double a) { return fmax(a, 0.0); }
+
 // Regret matching of one infoset (Eq. next_strategy_profile): positive parts over their
 // sum, or uniform when the sum is exactly 0.
-__device__ __forceinline__ void regret_match(const float* R, float* sigma, int32_t o, int32_t k) {
-    float sum = 0.0f;
-    for (int32_t a = 0; a < k; ++a) sum += fmaxf(R[o + a], 0.0f);
-    if (sum > 0.0f) {
-        for (int32_t a = 0; a < k; ++a) sigma[o + a] = fmaxf(R[o + a], 0.0f) / sum;
+template <class F>
+__device__ __forceinline__ void regret_match(const F* R, F* sigma, int32_t o, int32_t k) {
+    F sum = F(0);
+    for (int32_t a = 0; a < k; ++a) sum += pos_(R[o + a]);
+    if (sum > F(0)) {
+        for (int32_t a = 0; a < k; ++a) sigma[o + a] = pos_(R[o + a]) / sum;
     } else {
-        const float u = 1.0f / static_cast<float>(k);
+        const F u = F(1) / static_cast<F>(k);
         for (int32_t a = 0; a < k; ++a) sigma[o + a] = u;
     }
 }
 
-__global__ void k_reset_q(int64_t Qp, float* R, float* S, float* rtilde) {
+template <class F>
+__global__ void k_reset_q(int64_t Qp, F* R, F* S, F* rtilde) {
     const int64_t q = gid();
     if (q >= Qp) return;
-    R[q] = 0.0f;
-    S[q] = 0.0f;
-    rtilde[q] = 0.0f;
+    R[q] = F(0);
+    S[q] = F(0);
+    rtilde[q] = F(0);
 }
 
-__global__ void k_reset_h(int64_t Hp, float* pibar) {
+template <class F>
+__global__ void k_reset_h(int64_t Hp, F* pibar) {
     const int64_t h = gid();
-    if (h < Hp) pibar[h] = 0.0f;
+    if (h < Hp) pibar[h] = F(0);
 }
 
-__global__ void k_reset_nodes(int64_t N, const int8_t* node_player, const float* payoff,
-                              float* value, float* reach) {
+template <class F>
+__global__ void k_reset_nodes(int64_t N, const int8_t* node_player, const F* payoff, F* value,
+                              F* reach) {
     const int64_t v = gid();
     if (v >= N) return;
-    value[v] = node_player[v] < 0 ? payoff[v] : 0.0f;
+    value[v] = node_player[v] < 0 ? payoff[v] : F(0);
     if (v == 0) {
-        reach[0] = 1.0f;
-        reach[N] = 1.0f;
-        reach[2 * N] = 1.0f;
+        reach[0] = F(1);
+        reach[N] = F(1);
+        reach[2 * N] = F(1);
     }
 }
 
-__global__ void k_copy_tail(int64_t Q0, const float* src, float* dst) {
+template <class F>
+__global__ void k_copy_tail(int64_t Q0, const F* src, F* dst) {
     const int64_t i = gid();
     if (i < Q0) dst[i] = src[i];
 }
 
-__global__ void k_regret_match(int64_t Hp, const int32_t* q_offset, const float* R, float* sigma) {
+template <class F>
+__global__ void k_regret_match(int64_t Hp, const int32_t* q_offset, const F* R, F* sigma) {
     const int64_t h = gid();
     if (h >= Hp) return;
     const int32_t o = q_offset[h];
@@ -86,17 +98,18 @@ __global__ void k_tick(int64_t* T) {
 // own-reach twin): a decision node takes its parent's (pi_1, pi_2, pi_c) and multiplies the
 // factor of whoever acted at the parent by the edge probability s_v = sigma or sigma_0.
 // Terminal nodes need no reach.
+template <class F>
 __global__ void k_reach_level(int32_t lo, int32_t hi, int64_t N, const int32_t* __restrict__ parent,
                               const int8_t* __restrict__ node_player,
-                              const int32_t* __restrict__ node_edge, const float* __restrict__ prob,
-                              float* __restrict__ reach) {
+                              const int32_t* __restrict__ node_edge, const F* __restrict__ prob,
+                              F* __restrict__ reach) {
     const int64_t v = lo + gid();
     if (v >= hi) return;
     if (node_player[v] < 0) return;
     const int32_t p = parent[v];
-    const float s = prob[node_edge[v]];
+    const F s = prob[node_edge[v]];
     const int8_t who = node_player[p];  // 0 chance, 1, 2
-    float r1 = reach[p], r2 = reach[N + p], rc = reach[2 * N + p];
+    F r1 = reach[p], r2 = reach[N + p], rc = reach[2 * N + p];
     if (who == 1) r1 *= s;
     else if (who == 2) r2 *= s;
     else rc *= s;
@@ -110,26 +123,27 @@ __global__ void k_reach_level(int32_t lo, int32_t hi, int64_t N, const int32_t* 
 // values w_a, r~(h, a) += sgn_i * pi_{-i}(d) * (w_a - u) (the multiplied-out form of
 // Eq. instantaneous_counterfactual_regret, with u_2 = -u_1) and pibar(h) += pi_i(d)
 // (Eq. player_reach_probability, own-reach reading).
+template <class F>
 __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
                               const int32_t* __restrict__ child_begin,
                               const int8_t* __restrict__ node_player,
                               const int32_t* __restrict__ node_infoset,
                               const int32_t* __restrict__ node_edge,
-                              const float* __restrict__ prob, float* __restrict__ value,
-                              const float* __restrict__ reach, float* __restrict__ rtilde,
-                              float* __restrict__ pibar) {
+                              const F* __restrict__ prob, F* __restrict__ value,
+                              const F* __restrict__ reach, F* __restrict__ rtilde,
+                              F* __restrict__ pibar) {
     const int64_t p = lo + gid();
     if (p >= hi) return;
     const int8_t who = node_player[p];
     if (who < 0) return;
     const int32_t c0 = child_begin[p], c1 = child_begin[p + 1];
-    float u = 0.0f;
-    for (int32_t c = c0; c < c1; ++c) u = fmaf(prob[node_edge[c]], value[c], u);
+    F u = F(0);
+    for (int32_t c = c0; c < c1; ++c) u = fma_(prob[node_edge[c]], value[c], u);
     value[p] = u;
     if (who == 0) return;
-    const float r1 = reach[p], r2 = reach[N + p], rc = reach[2 * N + p];
-    const float cf = (who == 1 ? r2 : r1) * rc;
-    const float w = who == 1 ? cf : -cf;
+    const F r1 = reach[p], r2 = reach[N + p], rc = reach[2 * N + p];
+    const F cf = (who == 1 ? r2 : r1) * rc;
+    const F w = who == 1 ? cf : -cf;
     for (int32_t c = c0; c < c1; ++c)
         unsafeAtomicAdd(&rtilde[node_edge[c]], w * (value[c] - u));
     unsafeAtomicAdd(&pibar[node_infoset[p]], who == 1 ? r1 : r2);
@@ -140,90 +154,95 @@ __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
 // average-strategy accumulation S += w_T * pibar * sigma (discounted: then S *= d_avg; Eq.
 // average_strategy_profile_vector in cumulative form), then regret matching for the next
 // strategy, for the infosets of the pass's players. Clears the accumulators of all.
+template <class F>
 __global__ void k_infoset_update(int64_t Hp, const int32_t* __restrict__ q_offset,
                                  const int8_t* __restrict__ infoset_player,
-                                 float* __restrict__ R, float* __restrict__ S,
-                                 float* __restrict__ sigma, float* __restrict__ rtilde,
-                                 float* __restrict__ pibar, const int64_t* __restrict__ T,
+                                 F* __restrict__ R, F* __restrict__ S,
+                                 F* __restrict__ sigma, F* __restrict__ rtilde,
+                                 F* __restrict__ pibar, const int64_t* __restrict__ T,
                                  UpdateRule rule) {
     const int64_t h = gid();
     if (h >= Hp) return;
     const int32_t o = q_offset[h], k = q_offset[h + 1] - o;
-    const float t = static_cast<float>(*T + 1);
-    float wt = rule.linear ? t : 1.0f;
-    float d_pos = 1.0f, d_neg = 1.0f, d_avg = 1.0f;
+    const F t = static_cast<F>(*T + 1);
+    F wt = rule.linear ? t : F(1);
+    F d_pos = F(1), d_neg = F(1), d_avg = F(1);
     if (rule.variant == 2) {
-        wt = 1.0f;
+        wt = F(1);
         dcfr_discounts(rule, t, d_pos, d_neg, d_avg);
     }
-    const float pb = pibar[h];
-    pibar[h] = 0.0f;
+    const F pb = pibar[h];
+    pibar[h] = F(0);
     if (!((rule.players >> (infoset_player[h] - 1)) & 1)) {
-        for (int32_t a = 0; a < k; ++a) rtilde[o + a] = 0.0f;
+        for (int32_t a = 0; a < k; ++a) rtilde[o + a] = F(0);
         return;
     }
     for (int32_t a = 0; a < k; ++a) {
         const int32_t q = o + a;
-        float r = R[q] + rtilde[q];
-        if (rule.variant == 1) r = fmaxf(r, 0.0f);
-        else if (rule.variant == 2) r *= r > 0.0f ? d_pos : d_neg;
+        F r = R[q] + rtilde[q];
+        if (rule.variant == 1) r = pos_(r);
+        else if (rule.variant == 2) r *= r > F(0) ? d_pos : d_neg;
         R[q] = r;
-        const float sn = fmaf(wt * pb, sigma[q], S[q]);
+        const F sn = fma_(wt * pb, sigma[q], S[q]);
         S[q] = rule.variant == 2 ? sn * d_avg : sn;
-        rtilde[q] = 0.0f;
+        rtilde[q] = F(0);
     }
     regret_match(R, sigma, o, k);
 }
 
 // Average strategy: S normalised per infoset, uniform where its sum is 0.
+template <class F>
 __global__ void k_average(int64_t Hp, const int32_t* __restrict__ q_offset,
-                          const float* __restrict__ S, float* __restrict__ avg) {
+                          const F* __restrict__ S, F* __restrict__ avg) {
     const int64_t h = gid();
     if (h >= Hp) return;
     const int32_t o = q_offset[h], k = q_offset[h + 1] - o;
-    float sum = 0.0f;
+    F sum = F(0);
     for (int32_t a = 0; a < k; ++a) sum += S[o + a];
-    if (sum > 0.0f) {
+    if (sum > F(0)) {
         for (int32_t a = 0; a < k; ++a) avg[o + a] = S[o + a] / sum;
     } else {
-        const float u = 1.0f / static_cast<float>(k);
+        const F u = F(1) / static_cast<F>(k);
         for (int32_t a = 0; a < k; ++a) avg[o + a] = u;
     }
 }
 
 // ---- best response (Section 2.2): the responder i maximises, everyone else plays avgprob
 
+template <class F>
 __global__ void k_br_terminal(int64_t N, const int8_t* __restrict__ node_player,
-                              const float* __restrict__ payoff, float sgn, float* __restrict__ br_value,
-                              float* __restrict__ br_reach) {
+                              const F* __restrict__ payoff, F sgn, F* __restrict__ br_value,
+                              F* __restrict__ br_reach) {
     const int64_t v = gid();
     if (v >= N) return;
-    br_value[v] = node_player[v] < 0 ? sgn * payoff[v] : 0.0f;
-    if (v == 0) br_reach[0] = 1.0f;
+    br_value[v] = node_player[v] < 0 ? sgn * payoff[v] : F(0);
+    if (v == 0) br_reach[0] = F(1);
 }
 
 // pi_{-i}: product of chance and opponent edge probabilities (decision nodes only).
+template <class F>
 __global__ void k_br_reach_level(int32_t lo, int32_t hi, int player,
                                  const int32_t* __restrict__ parent,
                                  const int8_t* __restrict__ node_player,
                                  const int32_t* __restrict__ node_edge,
-                                 const float* __restrict__ avgprob, float* __restrict__ br_reach) {
+                                 const F* __restrict__ avgprob, F* __restrict__ br_reach) {
     const int64_t v = lo + gid();
     if (v >= hi) return;
     if (node_player[v] < 0) return;
     const int32_t p = parent[v];
-    const float f = node_player[p] == player ? 1.0f : avgprob[node_edge[v]];
+    const F f = node_player[p] == player ? F(1) : avgprob[node_edge[v]];
     br_reach[v] = br_reach[p] * f;
 }
 
 // a*(h) = argmax_a sum_{d in h} pi_{-i}(d) V(child(d, a)), lowest index on ties.
+template <class F>
 __global__ void k_br_choose(int32_t hlo, int32_t hhi, int player,
                             const int8_t* __restrict__ infoset_player,
                             const int32_t* __restrict__ q_offset,
                             const int32_t* __restrict__ member_offset,
                             const int32_t* __restrict__ members,
                             const int32_t* __restrict__ child_begin,
-                            const float* __restrict__ br_reach, const float* __restrict__ br_value,
+                            const F* __restrict__ br_reach, const F* __restrict__ br_value,
                             int32_t* __restrict__ best) {
     const int64_t h = hlo + gid();
     if (h >= hhi) return;
@@ -231,12 +250,12 @@ __global__ void k_br_choose(int32_t hlo, int32_t hhi, int player,
     const int32_t k = q_offset[h + 1] - q_offset[h];
     const int32_t m0 = member_offset[h], m1 = member_offset[h + 1];
     int32_t a_star = 0;
-    float v_star = 0.0f;
+    F v_star = F(0);
     for (int32_t a = 0; a < k; ++a) {
-        float tot = 0.0f;
+        F tot = F(0);
         for (int32_t m = m0; m < m1; ++m) {
             const int32_t d = members[m];
-            tot = fmaf(br_reach[d], br_value[child_begin[d] + a], tot);
+            tot = fma_(br_reach[d], br_value[child_begin[d] + a], tot);
         }
         if (a == 0 || tot > v_star) {
             v_star = tot;
@@ -246,13 +265,14 @@ __global__ void k_br_choose(int32_t hlo, int32_t hhi, int player,
     best[h] = a_star;
 }
 
+template <class F>
 __global__ void k_br_value_level(int32_t lo, int32_t hi, int player,
                                  const int32_t* __restrict__ child_begin,
                                  const int8_t* __restrict__ node_player,
                                  const int32_t* __restrict__ node_infoset,
                                  const int32_t* __restrict__ node_edge,
-                                 const float* __restrict__ avgprob, const int32_t* __restrict__ best,
-                                 float* __restrict__ br_value) {
+                                 const F* __restrict__ avgprob, const int32_t* __restrict__ best,
+                                 F* __restrict__ br_value) {
     const int64_t p = lo + gid();
     if (p >= hi) return;
     const int8_t who = node_player[p];
@@ -262,51 +282,58 @@ __global__ void k_br_value_level(int32_t lo, int32_t hi, int player,
         br_value[p] = br_value[c0 + best[node_infoset[p]]];
         return;
     }
-    float u = 0.0f;
-    for (int32_t c = c0; c < c1; ++c) u = fmaf(avgprob[node_edge[c]], br_value[c], u);
+    F u = F(0);
+    for (int32_t c = c0; c < c1; ++c) u = fma_(avgprob[node_edge[c]], br_value[c], u);
     br_value[p] = u;
 }
 
-__global__ void k_br_store(const float* __restrict__ br_value, double* out) {
+template <class F>
+__global__ void k_br_store(const F* __restrict__ br_value, double* out) {
     if (gid() == 0) *out = static_cast<double>(br_value[0]);
 }
 
+template <class F>
 __global__ void k_scatter_q(int64_t Qp, const int32_t* __restrict__ q_input,
-                            const float* __restrict__ src, float* __restrict__ dst) {
+                            const F* __restrict__ src, F* __restrict__ dst) {
     const int64_t q = gid();
     if (q < Qp) dst[q_input[q]] = src[q];
 }
 
+template <class F>
 __global__ void k_gather_q(int64_t Qp, const int32_t* __restrict__ q_input,
-                           const float* __restrict__ src, float* __restrict__ dst) {
+                           const F* __restrict__ src, F* __restrict__ dst) {
     const int64_t q = gid();
     if (q < Qp) dst[q] = src[q_input[q]];
 }
 
 }  // namespace
 
-void launch_reset(const Dev& d, hipStream_t st, bool node_arrays) {
-    if (d.Qp > 0) hipLaunchKernelGGL(k_reset_q, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st, d.Qp,
-                                     d.R, d.S, node_arrays ? d.rtilde : d.stage);
+template <class F>
+void launch_reset(const DevT<F>& d, hipStream_t st, bool node_arrays) {
+    if (d.Qp > 0) hipLaunchKernelGGL(k_reset_q<F>, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st,
+                                     d.Qp, d.R, d.S, node_arrays ? d.rtilde : d.stage);
     if (d.Hp > 0 && node_arrays)
-        hipLaunchKernelGGL(k_reset_h, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp, d.pibar);
+        hipLaunchKernelGGL(k_reset_h<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
+                           d.pibar);
     if (node_arrays)
-        hipLaunchKernelGGL(k_reset_nodes, dim3(blocks_for(d.N)), dim3(kBlock), 0, st, d.N,
+        hipLaunchKernelGGL(k_reset_nodes<F>, dim3(blocks_for(d.N)), dim3(kBlock), 0, st, d.N,
                            d.node_player, d.payoff, d.value, d.reach);
     if (d.Q0 > 0)
-        hipLaunchKernelGGL(k_copy_tail, dim3(blocks_for(d.Q0)), dim3(kBlock), 0, st, d.Q0,
+        hipLaunchKernelGGL(k_copy_tail<F>, dim3(blocks_for(d.Q0)), dim3(kBlock), 0, st, d.Q0,
                            d.prob + d.Qp, d.avgprob + d.Qp);
     hipLaunchKernelGGL(k_set_T, dim3(1), dim3(64), 0, st, d.T, int64_t{0});
     launch_regret_match(d, st);
 }
 
-void launch_regret_match(const Dev& d, hipStream_t st) {
+template <class F>
+void launch_regret_match(const DevT<F>& d, hipStream_t st) {
     if (d.Hp > 0)
-        hipLaunchKernelGGL(k_regret_match, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
+        hipLaunchKernelGGL(k_regret_match<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
                            d.sq_offset, d.R, d.prob);
 }
 
-void launch_set_T(const Dev& d, int64_t value, hipStream_t st) {
+template <class F>
+void launch_set_T(const DevT<F>& d, int64_t value, hipStream_t st) {
     hipLaunchKernelGGL(k_set_T, dim3(1), dim3(64), 0, st, d.T, value);
 }
 
@@ -320,7 +347,8 @@ const char* kernel_kind_name(int kind) {
     }
 }
 
-void launch_iteration(const Dev& d, const int32_t* lo, const UpdateRule& rule, hipStream_t st,
+template <class F>
+void launch_iteration(const DevT<F>& d, const int32_t* lo, const UpdateRule& rule, hipStream_t st,
                       LaunchTimer* timer) {
     auto pre = [&](int k, int l, int64_t n) { if (timer) timer->before(k, l, n, st); };
     auto post = [&](int k) { if (timer) timer->after(k, st); };
@@ -328,22 +356,22 @@ void launch_iteration(const Dev& d, const int32_t* lo, const UpdateRule& rule, h
     for (int32_t l = 1; l < d.D; ++l) {
         const int32_t a = lo[l], b = lo[l + 1];
         pre(K_REACH, l, b - a);
-        hipLaunchKernelGGL(k_reach_level, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b, d.N,
-                           d.parent, d.node_player, d.node_edge, d.prob, d.reach);
+        hipLaunchKernelGGL(k_reach_level<F>, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b,
+                           d.N, d.parent, d.node_player, d.node_edge, d.prob, d.reach);
         post(K_REACH);
     }
     // bottom-up: levels D-1 .. 0
     for (int32_t l = d.D - 1; l >= 0; --l) {
         const int32_t a = lo[l], b = lo[l + 1];
         pre(K_VALUE, l, b - a);
-        hipLaunchKernelGGL(k_value_level, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b, d.N,
-                           d.child_begin, d.node_player, d.node_infoset, d.node_edge, d.prob,
+        hipLaunchKernelGGL(k_value_level<F>, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b,
+                           d.N, d.child_begin, d.node_player, d.node_infoset, d.node_edge, d.prob,
                            d.value, d.reach, d.rtilde, d.pibar);
         post(K_VALUE);
     }
     if (d.Hp > 0) {
         pre(K_INFOSET, -1, d.Hp);
-        hipLaunchKernelGGL(k_infoset_update, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
+        hipLaunchKernelGGL(k_infoset_update<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
                            d.q_offset, d.infoset_player, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T,
                            rule);
         post(K_INFOSET);
@@ -355,46 +383,67 @@ void launch_iteration(const Dev& d, const int32_t* lo, const UpdateRule& rule, h
     }
 }
 
-void launch_average(const Dev& d, hipStream_t st) {
+template <class F>
+void launch_average(const DevT<F>& d, hipStream_t st) {
     if (d.Hp > 0)
-        hipLaunchKernelGGL(k_average, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp, d.sq_offset,
-                           d.S, d.avgprob);
+        hipLaunchKernelGGL(k_average<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
+                           d.sq_offset, d.S, d.avgprob);
 }
 
-void launch_best_response(const Dev& d, const int32_t* lo, const int32_t* hlo, int player,
+template <class F>
+void launch_best_response(const DevT<F>& d, const int32_t* lo, const int32_t* hlo, int player,
                           hipStream_t st) {
-    const float sgn = player == 1 ? 1.0f : -1.0f;
-    hipLaunchKernelGGL(k_br_terminal, dim3(blocks_for(d.N)), dim3(kBlock), 0, st, d.N,
+    const F sgn = player == 1 ? F(1) : F(-1);
+    hipLaunchKernelGGL(k_br_terminal<F>, dim3(blocks_for(d.N)), dim3(kBlock), 0, st, d.N,
                        d.node_player, d.payoff, sgn, d.br_value, d.br_reach);
     for (int32_t l = 1; l < d.D; ++l) {
         const int32_t a = lo[l], b = lo[l + 1];
-        hipLaunchKernelGGL(k_br_reach_level, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b,
-                           player, d.parent, d.node_player, d.node_edge, d.avgprob, d.br_reach);
+        hipLaunchKernelGGL(k_br_reach_level<F>, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a,
+                           b, player, d.parent, d.node_player, d.node_edge, d.avgprob,
+                           d.br_reach);
     }
     for (int32_t l = d.D - 1; l >= 0; --l) {
         const int32_t ha = hlo[l], hb = hlo[l + 1];
         if (hb > ha)
-            hipLaunchKernelGGL(k_br_choose, dim3(blocks_for(hb - ha)), dim3(kBlock), 0, st, ha, hb,
-                               player, d.infoset_player, d.q_offset, d.member_offset, d.members,
-                               d.child_begin, d.br_reach, d.br_value, d.best);
+            hipLaunchKernelGGL(k_br_choose<F>, dim3(blocks_for(hb - ha)), dim3(kBlock), 0, st, ha,
+                               hb, player, d.infoset_player, d.q_offset, d.member_offset,
+                               d.members, d.child_begin, d.br_reach, d.br_value, d.best);
         const int32_t a = lo[l], b = lo[l + 1];
-        hipLaunchKernelGGL(k_br_value_level, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b,
-                           player, d.child_begin, d.node_player, d.node_infoset, d.node_edge,
+        hipLaunchKernelGGL(k_br_value_level<F>, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a,
+                           b, player, d.child_begin, d.node_player, d.node_infoset, d.node_edge,
                            d.avgprob, d.best, d.br_value);
     }
-    hipLaunchKernelGGL(k_br_store, dim3(1), dim3(64), 0, st, d.br_value, d.out2 + (player - 1));
+    hipLaunchKernelGGL(k_br_store<F>, dim3(1), dim3(64), 0, st, d.br_value,
+                       d.out2 + (player - 1));
 }
 
-void launch_scatter_q(const Dev& d, const float* src, float* dst, hipStream_t st) {
+template <class F>
+void launch_scatter_q(const DevT<F>& d, const F* src, F* dst, hipStream_t st) {
     if (d.Qp > 0)
-        hipLaunchKernelGGL(k_scatter_q, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st, d.Qp,
+        hipLaunchKernelGGL(k_scatter_q<F>, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st, d.Qp,
                            d.sq_input, src, dst);
 }
 
-void launch_gather_q(const Dev& d, const float* src, float* dst, hipStream_t st) {
+template <class F>
+void launch_gather_q(const DevT<F>& d, const F* src, F* dst, hipStream_t st) {
     if (d.Qp > 0)
-        hipLaunchKernelGGL(k_gather_q, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st, d.Qp,
+        hipLaunchKernelGGL(k_gather_q<F>, dim3(blocks_for(d.Qp)), dim3(kBlock), 0, st, d.Qp,
                            d.sq_input, src, dst);
 }
+
+#define CFR_INSTANTIATE(F)                                                                     \
+    template void launch_reset<F>(const DevT<F>&, hipStream_t, bool);                          \
+    template void launch_regret_match<F>(const DevT<F>&, hipStream_t);                         \
+    template void launch_set_T<F>(const DevT<F>&, int64_t, hipStream_t);                       \
+    template void launch_iteration<F>(const DevT<F>&, const int32_t*, const UpdateRule&,       \
+                                      hipStream_t, LaunchTimer*);                              \
+    template void launch_average<F>(const DevT<F>&, hipStream_t);                              \
+    template void launch_best_response<F>(const DevT<F>&, const int32_t*, const int32_t*, int, \
+                                          hipStream_t);                                        \
+    template void launch_scatter_q<F>(const DevT<F>&, const F*, F*, hipStream_t);              \
+    template void launch_gather_q<F>(const DevT<F>&, const F*, F*, hipStream_t);
+CFR_INSTANTIATE(float)
+CFR_INSTANTIATE(double)
+#undef CFR_INSTANTIATE
 
 }  // namespace cfr

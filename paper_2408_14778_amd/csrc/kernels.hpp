@@ -7,8 +7,11 @@
 
 namespace cfr {
 
-// All pointers are device memory inside the caller's workspace, canonical order.
-struct Dev {
+// All pointers are device memory inside the caller's workspace, canonical order. F is the
+// arithmetic type of the values, probabilities and state: float (the default path) or double
+// (the FP64 path of the node engine).
+template <class F>
+struct DevT {
     int64_t N, Hp, Qp, H0, Q0, M;
     int32_t D;
     // structure (constant after build)
@@ -27,34 +30,38 @@ struct Dev {
     int32_t* member_offset; // Hp + 1
     int32_t* members;       // M
     int32_t* q_input;       // Qp
-    float* payoff;          // N
+    F* payoff;              // N
     // iteration state
-    float* prob;            // Qp + Q0: current sigma, then sigma_0
-    float* R;               // Qp cumulative regret
-    float* S;               // Qp cumulative average-strategy weight
-    float* rtilde;          // Qp accumulator (zero between iterations)
-    float* pibar;           // Hp accumulator (zero between iterations)
-    float* value;           // N  expected payoff of player 1 (terminals hold the payoff)
-    float* reach;           // 3N (pi_1, pi_2, pi_c) planes
+    F* prob;                // Qp + Q0: current sigma, then sigma_0
+    F* R;                   // Qp cumulative regret
+    F* S;                   // Qp cumulative average-strategy weight
+    F* rtilde;              // Qp accumulator (zero between iterations)
+    F* pibar;               // Hp accumulator (zero between iterations)
+    F* value;               // N  expected payoff of player 1 (terminals hold the payoff)
+    F* reach;               // 3N (pi_1, pi_2, pi_c) planes
     int64_t* T;             // iterations done (device copy)
     // exploitability and staging
-    float* avgprob;         // Qp + Q0: average strategy, then sigma_0
-    float* br_reach;        // N
-    float* br_value;        // N
+    F* avgprob;             // Qp + Q0: average strategy, then sigma_0
+    F* br_reach;            // N
+    F* br_value;            // N
     int32_t* best;          // Hp
-    float* stage;           // 2 * Qp (state and average-strategy transfers)
+    F* stage;               // 2 * Qp (state and average-strategy transfers)
     double* out2;           // 2 best-response values
     // pair numbering of the state arrays (canonical for the node engine, exec for the
     // block engine)
     int32_t* sq_offset;     // Hp + 1
     int32_t* sq_input;      // Qp
 };
+using Dev = DevT<float>;
+using Dev64 = DevT<double>;
 
 // Zero R, S, accumulators and T; sigma uniform; values at terminals; root reach 1.
 // node_arrays = false skips the canonical per-node state (the block engine resets its own).
-void launch_reset(const Dev& d, hipStream_t st, bool node_arrays = true);
+template <class F>
+void launch_reset(const DevT<F>& d, hipStream_t st, bool node_arrays = true);
 // sigma = regret matching of R (all infosets).
-void launch_regret_match(const Dev& d, hipStream_t st);
+template <class F>
+void launch_regret_match(const DevT<F>& d, hipStream_t st);
 // Kernel kinds of one iteration, for per-kernel timing.
 enum KernelKind { K_REACH = 0, K_VALUE = 1, K_INFOSET = 2, K_TICK = 3, K_NUM_KINDS = 4 };
 const char* kernel_kind_name(int kind);
@@ -97,20 +104,34 @@ __device__ __forceinline__ void dcfr_discounts(const UpdateRule& u, float t, flo
     neg = 1.0f / (1.0f + exp2f(-u.beta * lt));
     avg = exp2f(u.gamma * log2f(t / (t + 1.0f)));
 }
+// The same factors in double precision (the FP64 path), from the same exponents.
+__device__ __forceinline__ void dcfr_discounts(const UpdateRule& u, double t, double& pos,
+                                               double& neg, double& avg) {
+    const double lt = log2(t);
+    pos = 1.0 / (1.0 + exp2(-static_cast<double>(u.alpha) * lt));
+    neg = 1.0 / (1.0 + exp2(-static_cast<double>(u.beta) * lt));
+    avg = exp2(static_cast<double>(u.gamma) * log2(t / (t + 1.0)));
+}
 
 // One iteration (Section 3.2): top-down reach, bottom-up values + regrets, infoset update.
-void launch_iteration(const Dev& d, const int32_t* level_offset_host, const UpdateRule& rule,
+template <class F>
+void launch_iteration(const DevT<F>& d, const int32_t* level_offset_host, const UpdateRule& rule,
                       hipStream_t st, LaunchTimer* timer = nullptr);
 // Average strategy into d.avgprob (canonical order; chance tail copied at reset).
-void launch_average(const Dev& d, hipStream_t st);
+template <class F>
+void launch_average(const DevT<F>& d, hipStream_t st);
 // Best response of player i against d.avgprob; value lands in d.out2[i - 1].
-void launch_best_response(const Dev& d, const int32_t* level_offset_host,
+template <class F>
+void launch_best_response(const DevT<F>& d, const int32_t* level_offset_host,
                           const int32_t* infoset_level_offset_host, int player, hipStream_t st);
 // dst[q_input[q]] = src[q]  (canonical -> input order)
-void launch_scatter_q(const Dev& d, const float* src, float* dst, hipStream_t st);
+template <class F>
+void launch_scatter_q(const DevT<F>& d, const F* src, F* dst, hipStream_t st);
 // dst[q] = src[q_input[q]]  (input -> canonical order)
-void launch_gather_q(const Dev& d, const float* src, float* dst, hipStream_t st);
+template <class F>
+void launch_gather_q(const DevT<F>& d, const F* src, F* dst, hipStream_t st);
 // *T = value
-void launch_set_T(const Dev& d, int64_t value, hipStream_t st);
+template <class F>
+void launch_set_T(const DevT<F>& d, int64_t value, hipStream_t st);
 
 }  // namespace cfr

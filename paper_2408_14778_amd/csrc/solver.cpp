@@ -23,6 +23,9 @@ enum { ENGINE_NODE = 0, ENGINE_BLOCK = 1 };
 
 struct cfr_solver {
     cfr::Dev dev{};
+    cfr::Dev64 dev64{};  // fp64: the node engine's arrays in double precision (dev keeps the
+                         // structure arrays, its real-valued pointers are null)
+    bool fp64 = false;
     cfr::XDev xdev{};
     int engine = ENGINE_NODE;
     int32_t n_games = 1;       // > 1: a batch (forest); canonical exports are unavailable
@@ -105,6 +108,7 @@ struct Sizes {
     bool canonical = true;   // false for a batch: only the execution plan is on the device
     int32_t n_games = 1;
     bool packs = false;      // subtree packs (their records are on the device)
+    bool fp64 = false;       // values, probabilities and state in double precision
 };
 
 // Bounds on the subtree packs of a plan over N nodes, M members, Hp infosets and C chance nodes
@@ -122,17 +126,19 @@ int64_t max_pack_words(int64_t N, int64_t M, int64_t Hp, int64_t C, int32_t D) {
 }
 
 int choose_engine(bool level_pure, int32_t max_actions, uint32_t flags) {
-    if ((flags & CFR_FLAG_NODE_ENGINE) != 0 || !level_pure || max_actions > 16) return ENGINE_NODE;
+    if ((flags & (CFR_FLAG_NODE_ENGINE | CFR_FLAG_FP64)) != 0 || !level_pure || max_actions > 16)
+        return ENGINE_NODE;
     return ENGINE_BLOCK;
 }
 
 // Lays out every device array; with base = nullptr it only measures. Canonical layout
 // arrays are always present (they are exported); per-iteration state follows the engine.
-size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
+size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes& z) {
     Carve c(base);
     const int64_t N = z.N, Hp = z.Hp, Qp = z.Qp, H0 = z.H0, Q0 = z.Q0, M = z.M;
     const int32_t D = z.D;
     d = cfr::Dev{};
+    d64 = cfr::Dev64{};
     d.N = N; d.Hp = Hp; d.Qp = Qp; d.H0 = H0; d.Q0 = Q0; d.M = M; d.D = D;
     if (z.canonical) {
         d.parent = c.take<int32_t>(N);
@@ -150,6 +156,37 @@ size_t carve(cfr::Dev& d, cfr::XDev& x, void* base, const Sizes& z) {
         d.member_offset = c.take<int32_t>(Hp + 1);
         d.members = c.take<int32_t>(M);
         d.q_input = c.take<int32_t>(Qp);
+    }
+    if (z.fp64) {
+        // the node engine in double precision: structure shared with d, values here
+        d.T = c.take<int64_t>(1);
+        d.best = c.take<int32_t>(Hp);
+        d.out2 = c.take<double>(2 * static_cast<int64_t>(z.n_games));
+        d.sq_offset = d.q_offset;
+        d.sq_input = d.q_input;
+        d64.N = N; d64.Hp = Hp; d64.Qp = Qp; d64.H0 = H0; d64.Q0 = Q0; d64.M = M; d64.D = D;
+        d64.parent = d.parent; d64.child_begin = d.child_begin; d64.node_player = d.node_player;
+        d64.node_infoset = d.node_infoset; d64.node_edge = d.node_edge; d64.node_id = d.node_id;
+        d64.level_offset = d.level_offset; d64.infoset_id = d.infoset_id;
+        d64.infoset_player = d.infoset_player; d64.q_offset = d.q_offset;
+        d64.chance_id = d.chance_id; d64.cq_offset = d.cq_offset;
+        d64.member_offset = d.member_offset; d64.members = d.members; d64.q_input = d.q_input;
+        d64.T = d.T; d64.best = d.best; d64.out2 = d.out2;
+        d64.sq_offset = d.sq_offset; d64.sq_input = d.sq_input;
+        d64.payoff = c.take<double>(N);
+        d64.prob = c.take<double>(Qp + Q0);
+        d64.R = c.take<double>(Qp);
+        d64.S = c.take<double>(Qp);
+        d64.value = c.take<double>(N);
+        d64.reach = c.take<double>(3 * N);
+        d64.avgprob = c.take<double>(Qp + Q0);
+        d64.br_reach = c.take<double>(N);
+        d64.br_value = c.take<double>(N);
+        d64.stage = c.take<double>(2 * Qp);
+        d64.rtilde = c.take<double>(Qp);
+        d64.pibar = c.take<double>(Hp);
+        x = cfr::XDev{};
+        return (c.off + 255) & ~size_t{255};
     }
     d.payoff = c.take<float>(N);
     d.prob = c.take<float>(Qp + Q0);
@@ -235,6 +272,8 @@ void launch_one_iteration(cfr_solver* s, hipStream_t st, cfr::LaunchTimer* timer
     auto pass = [&](const cfr::UpdateRule& r) {
         if (s->engine == ENGINE_BLOCK)
             cfr::launch_x_iteration(s->xdev, r, st, timer);
+        else if (s->fp64)
+            cfr::launch_iteration(s->dev64, s->level_offset.data(), r, st, timer);
         else
             cfr::launch_iteration(s->dev, s->level_offset.data(), r, st, timer);
     };
@@ -279,8 +318,11 @@ int check_config(const cfr_config* c) {
     if (c == nullptr) return CFR_OK;
     if (c->variant < CFR_VANILLA || c->variant > CFR_DCFR) return set_err(CFR_EINVAL, "bad variant");
     if (c->flags & ~(CFR_FLAG_NO_GRAPH | CFR_FLAG_NODE_ENGINE | CFR_FLAG_ALTERNATING |
-                     CFR_FLAG_KEEP_NODE_VALUES | CFR_FLAG_SUBTREE_PACKS))
+                     CFR_FLAG_KEEP_NODE_VALUES | CFR_FLAG_SUBTREE_PACKS | CFR_FLAG_FP64))
         return set_err(CFR_EINVAL, "unknown flag bits");
+    if ((c->flags & CFR_FLAG_FP64) && (c->flags & CFR_FLAG_SUBTREE_PACKS))
+        return set_err(CFR_EINVAL, "CFR_FLAG_FP64 runs on the node engine; subtree packs belong "
+                                   "to the public-block engine");
     if (c->averaging < CFR_AVG_DEFAULT || c->averaging > CFR_AVG_LINEAR)
         return set_err(CFR_EINVAL, "bad averaging");
     if (c->variant == CFR_DCFR) {
@@ -355,7 +397,9 @@ int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out)
     z.engine = choose_engine(L.level_pure, L.max_actions, config ? config->flags : 0u);
     z.packs = z.engine == ENGINE_BLOCK && L.max_actions <= 4 && config != nullptr &&
               (config->flags & CFR_FLAG_SUBTREE_PACKS) != 0;
+    z.fp64 = config != nullptr && (config->flags & CFR_FLAG_FP64) != 0;
     cfr::Dev d{};
+    cfr::Dev64 d64{};
     cfr::XDev x{};
     std::memset(out, 0, sizeof *out);
     out->n_nodes = L.N;
@@ -368,7 +412,7 @@ int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out)
     out->depth = L.D;
     out->level_pure = L.level_pure ? 1 : 0;
     out->engine = z.engine;
-    out->workspace_bytes = static_cast<int64_t>(carve(d, x, nullptr, z));
+    out->workspace_bytes = static_cast<int64_t>(carve(d, d64, x, nullptr, z));
     return CFR_OK;
 }
 
@@ -575,7 +619,8 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     if (const int rc = check_config(&cfg); rc != CFR_OK) return rc;
     cfr::Layout L;
     std::string err;
-    int rc = cfr::flatten(*game, L, err);
+    const bool fp64 = (cfg.flags & CFR_FLAG_FP64) != 0;
+    int rc = cfr::flatten(*game, L, err, fp64);
     if (rc != CFR_OK) return set_err(rc, err);
     Sizes z;
     z.N = L.N; z.Hp = L.Hp; z.Qp = L.Qp; z.H0 = L.H0; z.Q0 = L.Q0; z.M = L.n_members;
@@ -583,6 +628,7 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
     z.engine = choose_engine(L.level_pure, L.max_actions, cfg.flags);
     z.packs = z.engine == ENGINE_BLOCK && L.max_actions <= 4 && (cfg.flags & CFR_FLAG_SUBTREE_PACKS);
+    z.fp64 = fp64;
     cfr::ExecPlan P;
     if (z.engine == ENGINE_BLOCK) {
         // subtree packs are instantiated for at most 4 actions per infoset
@@ -591,15 +637,18 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         if (rc != CFR_OK) return set_err(rc, err);
     }
     cfr::Dev d{};
+    cfr::Dev64 d64{};
     cfr::XDev x{};
-    const size_t need = carve(d, x, nullptr, z);
+    const size_t need = carve(d, d64, x, nullptr, z);
     if (bytes < need)
         return set_err(CFR_ENOMEM, "workspace has " + std::to_string(bytes) + " bytes, needs " +
                                        std::to_string(need));
-    carve(d, x, workspace, z);
+    carve(d, d64, x, workspace, z);
 
     auto* s = new cfr_solver();
     s->dev = d;
+    s->dev64 = d64;
+    s->fp64 = fp64;
     s->xdev = x;
     s->engine = z.engine;
     s->rule = rule_of(cfg);
@@ -623,8 +672,17 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         s->infoset_level_offset[L.D + 1] = static_cast<int32_t>(L.Hp);
     }
     hipStream_t st = s->stream;
-    std::vector<float> prob_tail(L.Qp + L.Q0, 0.0f);
-    for (int64_t i = 0; i < L.Q0; ++i) prob_tail[L.Qp + i] = L.chance_prob[i];
+    std::vector<float> prob_tail(fp64 ? 0 : L.Qp + L.Q0, 0.0f);
+    std::vector<double> prob_tail64(fp64 ? L.Qp + L.Q0 : 0, 0.0);
+    for (int64_t i = 0; i < L.Q0; ++i) {
+        if (fp64) prob_tail64[L.Qp + i] = L.chance_prob64[i];
+        else prob_tail[L.Qp + i] = L.chance_prob[i];
+    }
+    if (fp64 && ((rc = upload(d64.payoff, L.payoff64, st)) ||
+                 (rc = upload(d64.prob, prob_tail64, st)))) {
+        discard(s);
+        return rc;
+    }
     if ((rc = upload(d.parent, L.parent, st)) || (rc = upload(d.child_begin, L.child_begin, st)) ||
         (rc = upload(d.node_player, L.node_player, st)) ||
         (rc = upload(d.node_infoset, L.node_infoset, st)) ||
@@ -636,7 +694,7 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         (rc = upload(d.cq_offset, L.cq_offset, st)) ||
         (rc = upload(d.member_offset, L.member_offset, st)) ||
         (rc = upload(d.members, L.members, st)) || (rc = upload(d.q_input, L.q_input, st)) ||
-        (rc = upload(d.payoff, L.payoff, st)) || (rc = upload(d.prob, prob_tail, st))) {
+        (!fp64 && ((rc = upload(d.payoff, L.payoff, st)) || (rc = upload(d.prob, prob_tail, st))))) {
         discard(s);
         return rc;
     }
@@ -647,7 +705,8 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
             return rc;
         }
     }
-    cfr::launch_reset(d, st, s->engine == ENGINE_NODE);
+    if (fp64) cfr::launch_reset(d64, st, true);
+    else cfr::launch_reset(d, st, s->engine == ENGINE_NODE);
     if (s->engine == ENGINE_BLOCK) cfr::launch_x_reset(s->xdev, st);
     if ((rc = check_hip("reset")) != CFR_OK) {
         discard(s);
@@ -829,46 +888,132 @@ int cfr_set_launch_shape(cfr_solver* s, const cfr_launch_shape* shape) {
     return CFR_OK;
 }
 
-int cfr_average_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device) {
-    if (s == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
-    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
-    cfr::launch_average(s->dev, s->stream);
+}  // extern "C"
+
+namespace {
+
+// The precision a call asks for against the solver's: the float calls serve FP32 solvers, the
+// _f64 calls FP64 solvers.
+int check_precision(const cfr_solver* s, bool f64) {
+    if (s->fp64 == f64) return CFR_OK;
+    return set_err(CFR_EINVAL, f64 ? "an _f64 call needs a solver built with CFR_FLAG_FP64"
+                                   : "this solver was built with CFR_FLAG_FP64: use the _f64 call");
+}
+
+template <class F>
+int strategy_out(cfr_solver* s, const cfr::DevT<F>& d, const F* src, F* out, int64_t n_q,
+                 int out_on_device, const char* what) {
     if (out_on_device) {
-        cfr::launch_scatter_q(s->dev, s->dev.avgprob, out, s->stream);
-        return check_hip("average strategy");
+        cfr::launch_scatter_q(d, src, out, s->stream);
+        return check_hip(what);
     }
-    cfr::launch_scatter_q(s->dev, s->dev.avgprob, s->dev.stage, s->stream);
-    HIP_TRY(hipMemcpyAsync(out, s->dev.stage, n_q * sizeof(float), hipMemcpyDeviceToHost, s->stream),
-            "average strategy copy");
-    HIP_TRY(hipStreamSynchronize(s->stream), "average strategy synchronise");
+    cfr::launch_scatter_q(d, src, d.stage, s->stream);
+    HIP_TRY(hipMemcpyAsync(out, d.stage, n_q * sizeof(F), hipMemcpyDeviceToHost, s->stream), what);
+    HIP_TRY(hipStreamSynchronize(s->stream), what);
     return CFR_OK;
 }
 
-int cfr_current_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device) {
-    if (s == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
-    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
-    if (out_on_device) {
-        cfr::launch_scatter_q(s->dev, s->dev.prob, out, s->stream);
-        return check_hip("current strategy");
+template <class F>
+int average_strategy_t(cfr_solver* s, const cfr::DevT<F>& d, F* out, int64_t n_q,
+                       int out_on_device) {
+    if (out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (n_q != d.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    cfr::launch_average(d, s->stream);
+    return strategy_out(s, d, d.avgprob, out, n_q, out_on_device, "average strategy");
+}
+
+template <class F>
+int current_strategy_t(cfr_solver* s, const cfr::DevT<F>& d, F* out, int64_t n_q,
+                       int out_on_device) {
+    if (out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (n_q != d.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    return strategy_out(s, d, d.prob, out, n_q, out_on_device, "current strategy");
+}
+
+template <class F>
+int get_state_t(cfr_solver* s, const cfr::DevT<F>& d, int64_t* T, F* R, F* S, int64_t n_q) {
+    if (n_q != d.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    if (T != nullptr) *T = s->T;
+    const F* srcs[2] = {d.R, d.S};
+    F* dsts[2] = {R, S};
+    for (int k = 0; k < 2; ++k) {
+        if (dsts[k] == nullptr) continue;
+        cfr::launch_scatter_q(d, srcs[k], d.stage, s->stream);
+        HIP_TRY(hipMemcpyAsync(dsts[k], d.stage, n_q * sizeof(F), hipMemcpyDeviceToHost,
+                               s->stream), "state copy");
+        HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
     }
-    cfr::launch_scatter_q(s->dev, s->dev.prob, s->dev.stage, s->stream);
-    HIP_TRY(hipMemcpyAsync(out, s->dev.stage, n_q * sizeof(float), hipMemcpyDeviceToHost, s->stream),
-            "current strategy copy");
-    HIP_TRY(hipStreamSynchronize(s->stream), "current strategy synchronise");
     return CFR_OK;
+}
+
+template <class F>
+int set_state_t(cfr_solver* s, const cfr::DevT<F>& d, int64_t T, const F* R, const F* S,
+                int64_t n_q) {
+    if (R == nullptr || S == nullptr || T < 0)
+        return set_err(CFR_EINVAL, "null argument or negative T");
+    if (n_q != d.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
+    const F* srcs[2] = {R, S};
+    F* dsts[2] = {d.R, d.S};
+    for (int k = 0; k < 2; ++k) {
+        HIP_TRY(hipMemcpyAsync(d.stage, srcs[k], n_q * sizeof(F), hipMemcpyHostToDevice,
+                               s->stream), "state copy");
+        cfr::launch_gather_q(d, d.stage, dsts[k], s->stream);
+        // the staging buffer is reused: keep the two transfers apart
+        HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
+    }
+    cfr::launch_regret_match(d, s->stream);
+    cfr::launch_set_T(d, T, s->stream);
+    HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
+    s->T = T;
+    return check_hip("set state");
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfr_average_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (const int rc = check_precision(s, false); rc != CFR_OK) return rc;
+    return average_strategy_t(s, s->dev, out, n_q, out_on_device);
+}
+
+int cfr_average_strategy_f64(cfr_solver* s, double* out, int64_t n_q, int out_on_device) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (const int rc = check_precision(s, true); rc != CFR_OK) return rc;
+    return average_strategy_t(s, s->dev64, out, n_q, out_on_device);
+}
+
+int cfr_current_strategy(cfr_solver* s, float* out, int64_t n_q, int out_on_device) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (const int rc = check_precision(s, false); rc != CFR_OK) return rc;
+    return current_strategy_t(s, s->dev, out, n_q, out_on_device);
+}
+
+int cfr_current_strategy_f64(cfr_solver* s, double* out, int64_t n_q, int out_on_device) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (const int rc = check_precision(s, true); rc != CFR_OK) return rc;
+    return current_strategy_t(s, s->dev64, out, n_q, out_on_device);
 }
 
 int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]) {
     if (s == nullptr || expl == nullptr) return set_err(CFR_EINVAL, "null argument");
     if (s->n_games != 1) return set_err(CFR_EINVAL, "a batch reports cfr_exploitability_batch");
     if (!s->level_pure) return set_err(CFR_ELEVEL, "an infoset spans several levels");
-    cfr::launch_average(s->dev, s->stream);
-    if (s->engine == ENGINE_BLOCK) {
-        cfr::launch_x_best_response(s->xdev, s->dev.avgprob, s->stream);
-    } else {
+    if (s->fp64) {
+        cfr::launch_average(s->dev64, s->stream);
         for (int player = 1; player <= 2; ++player)
-            cfr::launch_best_response(s->dev, s->level_offset.data(), s->infoset_level_offset.data(),
-                                      player, s->stream);
+            cfr::launch_best_response(s->dev64, s->level_offset.data(),
+                                      s->infoset_level_offset.data(), player, s->stream);
+    } else {
+        cfr::launch_average(s->dev, s->stream);
+        if (s->engine == ENGINE_BLOCK) {
+            cfr::launch_x_best_response(s->xdev, s->dev.avgprob, s->stream);
+        } else {
+            for (int player = 1; player <= 2; ++player)
+                cfr::launch_best_response(s->dev, s->level_offset.data(),
+                                          s->infoset_level_offset.data(), player, s->stream);
+        }
     }
     int rc = check_hip("best response launch");
     if (rc != CFR_OK) return rc;
@@ -885,38 +1030,26 @@ int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]) {
 
 int cfr_get_state(cfr_solver* s, int64_t* T, float* R, float* S, int64_t n_q) {
     if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
-    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
-    if (T != nullptr) *T = s->T;
-    const float* srcs[2] = {s->dev.R, s->dev.S};
-    float* dsts[2] = {R, S};
-    for (int k = 0; k < 2; ++k) {
-        if (dsts[k] == nullptr) continue;
-        cfr::launch_scatter_q(s->dev, srcs[k], s->dev.stage, s->stream);
-        HIP_TRY(hipMemcpyAsync(dsts[k], s->dev.stage, n_q * sizeof(float), hipMemcpyDeviceToHost,
-                               s->stream), "state copy");
-        HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
-    }
-    return CFR_OK;
+    if (const int rc = check_precision(s, false); rc != CFR_OK) return rc;
+    return get_state_t(s, s->dev, T, R, S, n_q);
+}
+
+int cfr_get_state_f64(cfr_solver* s, int64_t* T, double* R, double* S, int64_t n_q) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (const int rc = check_precision(s, true); rc != CFR_OK) return rc;
+    return get_state_t(s, s->dev64, T, R, S, n_q);
 }
 
 int cfr_set_state(cfr_solver* s, int64_t T, const float* R, const float* S, int64_t n_q) {
-    if (s == nullptr || R == nullptr || S == nullptr || T < 0)
-        return set_err(CFR_EINVAL, "null argument or negative T");
-    if (n_q != s->dev.Qp) return set_err(CFR_ESTATE, "n_q does not match the game");
-    const float* srcs[2] = {R, S};
-    float* dsts[2] = {s->dev.R, s->dev.S};
-    for (int k = 0; k < 2; ++k) {
-        HIP_TRY(hipMemcpyAsync(s->dev.stage, srcs[k], n_q * sizeof(float), hipMemcpyHostToDevice,
-                               s->stream), "state copy");
-        cfr::launch_gather_q(s->dev, s->dev.stage, dsts[k], s->stream);
-        // the staging buffer is reused: keep the two transfers apart
-        HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
-    }
-    cfr::launch_regret_match(s->dev, s->stream);
-    cfr::launch_set_T(s->dev, T, s->stream);
-    HIP_TRY(hipStreamSynchronize(s->stream), "state synchronise");
-    s->T = T;
-    return check_hip("set state");
+    if (s == nullptr) return set_err(CFR_EINVAL, "null argument or negative T");
+    if (const int rc = check_precision(s, false); rc != CFR_OK) return rc;
+    return set_state_t(s, s->dev, T, R, S, n_q);
+}
+
+int cfr_set_state_f64(cfr_solver* s, int64_t T, const double* R, const double* S, int64_t n_q) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null argument or negative T");
+    if (const int rc = check_precision(s, true); rc != CFR_OK) return rc;
+    return set_state_t(s, s->dev64, T, R, S, n_q);
 }
 
 int64_t cfr_layout_bytes(cfr_solver* s, const char* name) {
@@ -972,26 +1105,43 @@ int cfr_get_layout(cfr_solver* s, const char* name, void* out, int64_t bytes) {
     else if (n == "payoff") src = d.payoff;
     else if (n == "q_input") src = d.q_input;
     if (bytes == 0) return CFR_OK;
+    if (s->fp64 && (n == "chance_prob" || n == "payoff")) {
+        // the FP64 solver holds these in double precision: exported rounded to float
+        const int64_t count = bytes / 4;
+        std::vector<double> tmp(count);
+        const double* src64 = n == "payoff" ? s->dev64.payoff : s->dev64.prob + d.Qp;
+        HIP_TRY(hipMemcpyAsync(tmp.data(), src64, count * sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream), "layout copy");
+        HIP_TRY(hipStreamSynchronize(s->stream), "layout synchronise");
+        float* o = static_cast<float*>(out);
+        for (int64_t i = 0; i < count; ++i) o[i] = static_cast<float>(tmp[i]);
+        return CFR_OK;
+    }
     HIP_TRY(hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, s->stream), "layout copy");
     HIP_TRY(hipStreamSynchronize(s->stream), "layout synchronise");
     return CFR_OK;
 }
 
-int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes) {
-    if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+}  // extern "C"
+
+namespace {
+
+template <class F>
+int node_values_t(cfr_solver* s, const F* value, const F* reach_planes, F* u1, F* reach,
+                  int64_t n_nodes) {
     if (!s->canonical) return set_err(CFR_EINVAL, "node values are not exported for a batch");
     if (n_nodes != s->dev.N) return set_err(CFR_EINVAL, "n_nodes does not match the game");
     if (s->engine == ENGINE_BLOCK && s->xdev.n_tiers > 0 && !s->keep_nodes)
         return set_err(CFR_EINVAL, "the subtree packs keep node values on chip: build with "
                                    "CFR_FLAG_KEEP_NODE_VALUES to read them");
     const int64_t N = s->dev.N;
-    std::vector<float> val(u1 != nullptr ? N : 0), planes(reach != nullptr ? 3 * N : 0);
+    std::vector<F> val(u1 != nullptr ? N : 0), planes(reach != nullptr ? 3 * N : 0);
     std::vector<int32_t> canon(s->engine == ENGINE_BLOCK ? N : 0);
     if (u1 != nullptr)
-        HIP_TRY(hipMemcpyAsync(val.data(), s->dev.value, N * sizeof(float), hipMemcpyDeviceToHost,
+        HIP_TRY(hipMemcpyAsync(val.data(), value, N * sizeof(F), hipMemcpyDeviceToHost,
                                s->stream), "value copy");
     if (reach != nullptr)
-        HIP_TRY(hipMemcpyAsync(planes.data(), s->dev.reach, 3 * N * sizeof(float),
+        HIP_TRY(hipMemcpyAsync(planes.data(), reach_planes, 3 * N * sizeof(F),
                                hipMemcpyDeviceToHost, s->stream), "reach copy");
     if (s->engine == ENGINE_BLOCK)
         HIP_TRY(hipMemcpyAsync(canon.data(), s->xdev.canon_of, N * sizeof(int32_t),
@@ -1004,6 +1154,22 @@ int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes)
             for (int k = 0; k < 3; ++k) reach[3 * v + k] = planes[k * N + x];
     }
     return CFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (const int rc = check_precision(s, false); rc != CFR_OK) return rc;
+    return node_values_t(s, s->dev.value, s->dev.reach, u1, reach, n_nodes);
+}
+
+int cfr_get_node_values_f64(cfr_solver* s, double* u1, double* reach, int64_t n_nodes) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (const int rc = check_precision(s, true); rc != CFR_OK) return rc;
+    return node_values_t(s, s->dev64.value, s->dev64.reach, u1, reach, n_nodes);
 }
 
 int cfr_destroy(cfr_solver* s) {
@@ -1028,6 +1194,9 @@ int cfr_plan_batch(const cfr_game* games, int32_t n_games, const cfr_config* con
                    cfr_plan_info* out) {
     if (games == nullptr || out == nullptr || n_games < 1) return set_err(CFR_EINVAL, "bad argument");
     if (const int rc = check_config(config); rc != CFR_OK) return rc;
+    if (config != nullptr && (config->flags & CFR_FLAG_FP64))
+        return set_err(CFR_EINVAL, "a batch runs on the public-block engine in FP32: "
+                                   "CFR_FLAG_FP64 is for single games");
     Sizes z;
     z.engine = ENGINE_BLOCK;
     z.canonical = false;
@@ -1049,6 +1218,7 @@ int cfr_plan_batch(const cfr_game* games, int32_t n_games, const cfr_config* con
     }
     z.packs = z.max_actions <= 4 && config != nullptr && (config->flags & CFR_FLAG_SUBTREE_PACKS);
     cfr::Dev d{};
+    cfr::Dev64 d64{};
     cfr::XDev x{};
     std::memset(out, 0, sizeof *out);
     out->n_nodes = z.N;
@@ -1061,7 +1231,7 @@ int cfr_plan_batch(const cfr_game* games, int32_t n_games, const cfr_config* con
     out->depth = z.D;
     out->level_pure = 1;
     out->engine = ENGINE_BLOCK;
-    out->workspace_bytes = static_cast<int64_t>(carve(d, x, nullptr, z));
+    out->workspace_bytes = static_cast<int64_t>(carve(d, d64, x, nullptr, z));
     return CFR_OK;
 }
 
@@ -1074,6 +1244,9 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     cfg.averaging = CFR_AVG_DEFAULT;
     if (config != nullptr) cfg = *config;
     if (const int rc = check_config(&cfg); rc != CFR_OK) return rc;
+    if (cfg.flags & CFR_FLAG_FP64)
+        return set_err(CFR_EINVAL, "a batch runs on the public-block engine in FP32: "
+                                   "CFR_FLAG_FP64 is for single games");
     std::string err;
     std::vector<cfr::ExecPlan> plans;
     int32_t max_actions = 0;
@@ -1094,14 +1267,15 @@ int cfr_build_batch(const cfr_game* games, int32_t n_games, const cfr_config* co
     z.n_games = n_games;
     z.packs = max_actions <= 4 && (cfg.flags & CFR_FLAG_SUBTREE_PACKS);
     cfr::Dev d{};
+    cfr::Dev64 d64{};
     cfr::XDev x{};
     // cfr_plan_batch bounds the explicit child lists by the node count, so a workspace of the
     // planned size always covers the exact need
-    const size_t need = carve(d, x, nullptr, z);
+    const size_t need = carve(d, d64, x, nullptr, z);
     if (bytes < need)
         return set_err(CFR_ENOMEM, "workspace has " + std::to_string(bytes) + " bytes, needs " +
                                        std::to_string(need));
-    carve(d, x, workspace, z);
+    carve(d, d64, x, workspace, z);
     auto* s = new cfr_solver();
     s->dev = d;
     s->xdev = x;

@@ -62,7 +62,7 @@ class GameArgs:
 
 def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
                 engine: str = "auto", dcfr=None, schedule: str = "simultaneous",
-                keep_node_values: bool = False) -> N.CfrConfig:
+                keep_node_values: bool = False, precision: str = "f32") -> N.CfrConfig:
     if variant not in VARIANTS:
         raise ValueError(f"variant must be one of {list(VARIANTS)}")
     if engine not in ("auto", "packs", "node"):
@@ -76,7 +76,10 @@ def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
     cfg.dcfr_alpha, cfg.dcfr_beta, cfg.dcfr_gamma = (dcfr if dcfr is not None else DCFR_DEFAULT)
     if schedule not in ("simultaneous", "alternating"):
         raise ValueError("schedule must be 'simultaneous' or 'alternating'")
+    if precision not in ("f32", "f64"):
+        raise ValueError("precision must be 'f32' or 'f64'")
     cfg.flags = ((0 if graph else N.CFR_FLAG_NO_GRAPH) |
+                 (N.CFR_FLAG_FP64 if precision == "f64" else 0) |
                  (N.CFR_FLAG_NODE_ENGINE if engine == "node" else 0) |
                  (N.CFR_FLAG_SUBTREE_PACKS if engine == "packs" else 0) |
                  (N.CFR_FLAG_ALTERNATING if schedule == "alternating" else 0) |
@@ -85,10 +88,11 @@ def make_config(variant: str = "vanilla", averaging=None, graph: bool = True,
 
 
 def plan(game, variant: str = "vanilla", averaging=None, engine: str = "auto", dcfr=None,
-         schedule: str = "simultaneous") -> dict:
+         schedule: str = "simultaneous", precision: str = "f32") -> dict:
     lib = N.load()
     args = GameArgs(game)
-    cfg = make_config(variant, averaging, engine=engine, dcfr=dcfr, schedule=schedule)
+    cfg = make_config(variant, averaging, engine=engine, dcfr=dcfr, schedule=schedule,
+                      precision=precision)
     info = N.CfrPlanInfo()
     N.check(lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg), ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
@@ -174,17 +178,22 @@ class Solver:
     (alpha, beta, gamma) of variant 'dcfr' (default (1.5, 0, 2)); ``schedule``: 'simultaneous'
     (both players' updates in one pass) or 'alternating' (player 1's pass, then player 2's);
     ``keep_node_values``: the subtree-pack launch also stores every node's value and reach, so
-    that node_values() can read them (off by default: the packs keep them on chip)."""
+    that node_values() can read them (off by default: the packs keep them on chip);
+    ``precision``: 'f32' (default) or 'f64' (the node engine in double precision: strategies,
+    state and node values come back as float64)."""
 
     def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
                  graph: bool = True, stream=None, engine: str = "auto", tuned: bool = True,
-                 dcfr=None, schedule: str = "simultaneous", keep_node_values: bool = False):
+                 dcfr=None, schedule: str = "simultaneous", keep_node_values: bool = False,
+                 precision: str = "f32"):
         import torch
 
         self._lib = N.load()
         self.variant = variant
+        self.precision = precision
         args = GameArgs(game)
-        cfg = make_config(variant, averaging, graph, engine, dcfr, schedule, keep_node_values)
+        cfg = make_config(variant, averaging, graph, engine, dcfr, schedule, keep_node_values,
+                          precision)
         info = N.CfrPlanInfo()
         N.check(self._lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg),
                                    ctypes.byref(info)))
@@ -202,7 +211,10 @@ class Solver:
         self._h = handle
         self.n_q = int(info.n_q)
         self.n_nodes = int(info.n_nodes)
-        if tuned:
+        self._f64 = precision == "f64"
+        self._rdt = np.float64 if self._f64 else np.float32
+        self._sfx = "_f64" if self._f64 else ""
+        if tuned and not self._f64:
             from . import autotune
             autotune.apply(self, autotune.load())
 
@@ -261,24 +273,29 @@ class Solver:
         self.stream.synchronize()
 
     # -- results --------------------------------------------------------------------
+    def _call(self, name: str):
+        return getattr(self._lib, name + self._sfx)
+
     def average_strategy(self) -> np.ndarray:
-        out = np.empty(self.n_q, dtype=np.float32)
-        N.check(self._lib.cfr_average_strategy(self._h, out.ctypes.data_as(ctypes.c_void_p),
-                                               self.n_q, 0))
+        out = np.empty(self.n_q, dtype=self._rdt)
+        N.check(self._call("cfr_average_strategy")(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                                   self.n_q, 0))
         return out
 
     def current_strategy(self) -> np.ndarray:
         """sigma^(T+1): the strategy the next iteration plays (input pair order)."""
-        out = np.empty(self.n_q, dtype=np.float32)
-        N.check(self._lib.cfr_current_strategy(self._h, out.ctypes.data_as(ctypes.c_void_p),
-                                               self.n_q, 0))
+        out = np.empty(self.n_q, dtype=self._rdt)
+        N.check(self._call("cfr_current_strategy")(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                                   self.n_q, 0))
         return out
 
     def average_strategy_device(self, out) -> None:
-        """Write the average strategy into a float32 device tensor of n_q elements."""
-        assert out.dtype.itemsize == 4 and out.numel() == self.n_q and out.is_cuda
-        N.check(self._lib.cfr_average_strategy(self._h, ctypes.c_void_p(out.data_ptr()),
-                                               self.n_q, 1))
+        """Write the average strategy into a device tensor of n_q elements (float32, or
+        float64 for precision 'f64')."""
+        assert out.dtype.itemsize == np.dtype(self._rdt).itemsize
+        assert out.numel() == self.n_q and out.is_cuda
+        N.check(self._call("cfr_average_strategy")(self._h, ctypes.c_void_p(out.data_ptr()),
+                                                   self.n_q, 1))
 
     def exploitability(self) -> dict:
         expl = ctypes.c_double()
@@ -286,19 +303,22 @@ class Solver:
         N.check(self._lib.cfr_exploitability(self._h, ctypes.byref(expl), br))
         return {"expl": expl.value, "br1": br[0], "br2": br[1], "nash_conv": br[0] + br[1]}
 
+    def _cty(self):
+        return ctypes.c_double if self._f64 else ctypes.c_float
+
     def get_state(self):
         T = ctypes.c_int64()
-        R = np.empty(self.n_q, dtype=np.float32)
-        S = np.empty(self.n_q, dtype=np.float32)
-        N.check(self._lib.cfr_get_state(self._h, ctypes.byref(T), _ptr(R, ctypes.c_float),
-                                        _ptr(S, ctypes.c_float), self.n_q))
+        R = np.empty(self.n_q, dtype=self._rdt)
+        S = np.empty(self.n_q, dtype=self._rdt)
+        N.check(self._call("cfr_get_state")(self._h, ctypes.byref(T), _ptr(R, self._cty()),
+                                            _ptr(S, self._cty()), self.n_q))
         return int(T.value), R, S
 
     def set_state(self, T: int, R, S) -> None:
-        R = np.ascontiguousarray(R, dtype=np.float32)
-        S = np.ascontiguousarray(S, dtype=np.float32)
-        N.check(self._lib.cfr_set_state(self._h, int(T), _ptr(R, ctypes.c_float),
-                                        _ptr(S, ctypes.c_float), R.shape[0]))
+        R = np.ascontiguousarray(R, dtype=self._rdt)
+        S = np.ascontiguousarray(S, dtype=self._rdt)
+        N.check(self._call("cfr_set_state")(self._h, int(T), _ptr(R, self._cty()),
+                                            _ptr(S, self._cty()), R.shape[0]))
 
     def layout(self, name: str) -> np.ndarray:
         nbytes = self._lib.cfr_layout_bytes(self._h, name.encode())
@@ -312,10 +332,10 @@ class Solver:
 
     def node_values(self):
         """(u1[N], reach[N, 3]) of the last iteration, canonical node order."""
-        u1 = np.empty(self.n_nodes, dtype=np.float32)
-        reach = np.empty((self.n_nodes, 3), dtype=np.float32)
-        N.check(self._lib.cfr_get_node_values(self._h, _ptr(u1, ctypes.c_float),
-                                              _ptr(reach, ctypes.c_float), self.n_nodes))
+        u1 = np.empty(self.n_nodes, dtype=self._rdt)
+        reach = np.empty((self.n_nodes, 3), dtype=self._rdt)
+        N.check(self._call("cfr_get_node_values")(self._h, _ptr(u1, self._cty()),
+                                                  _ptr(reach, self._cty()), self.n_nodes))
         return u1, reach
 
     def close(self) -> None:
@@ -364,6 +384,10 @@ class BatchSolver(Solver):
                                           ctypes.byref(handle)))
         self._args = None
         self._h = handle
+        self.precision = "f32"
+        self._f64 = False
+        self._rdt = np.float32
+        self._sfx = ""
         self.n_games = n
         self.n_q = int(info.n_q)
         self.n_nodes = int(info.n_nodes)

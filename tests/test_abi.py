@@ -116,6 +116,33 @@ def test_unknown_flag_bits_rejected():
     assert lib.cfr_plan(ctypes.byref(args.struct), ctypes.byref(cfg), ctypes.byref(info)) != 0
 
 
+def test_fp64_plan_and_flag_validation():
+    """CFR_FLAG_FP64: the node engine with double-precision state (a larger workspace than the
+    FP32 node engine's); not with subtree packs, nor for a batch."""
+    import ctypes
+
+    from paper_2408_14778_amd import CfrError, plan
+    from paper_2408_14778_amd import _native as N
+    from paper_2408_14778_amd.solver import GameArgs, make_config
+    g = games.leduc_like(3, 2, deal="sequential")
+    p64 = plan(g, "cfr+", precision="f64")
+    p32 = plan(g, "cfr+", engine="node")
+    assert p64["engine"] == 0 and plan(g, "cfr+")["engine"] == 1
+    # per node 7 doubles instead of 7 floats, per pair 6 instead of 6 (R, S, r~, sigma, average,
+    # two staging): at least 28 bytes per node more
+    assert p64["workspace_bytes"] >= p32["workspace_bytes"] + 28 * p64["n_nodes"]
+    with pytest.raises(CfrError, match="CFR_EINVAL"):
+        plan(g, "cfr+", engine="packs", precision="f64")
+    with pytest.raises(ValueError):
+        plan(g, "cfr+", precision="f16")
+    lib = N.load()
+    args = GameArgs(g)
+    arr = (N.CfrGame * 1)(args.struct)
+    cfg = make_config("cfr+", precision="f64")
+    info = N.CfrPlanInfo()
+    assert N.ERRORS[lib.cfr_plan_batch(arr, 1, ctypes.byref(cfg), ctypes.byref(info))] == "CFR_EINVAL"
+
+
 def test_terminal_with_infoset_rejected():
     from paper_2408_14778_amd import CfrError, plan
     g = _copy(games.kuhn_like(3, "joint"))
