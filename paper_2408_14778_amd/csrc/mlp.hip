@@ -83,6 +83,274 @@ __global__ void __launch_bounds__(64) k_gemm(int M, int N, int K, const __bf16* 
     }
 }
 
+// The same product on TM x TM output tiles (TM = 128 or 64) staged through LDS, for operands of
+// at least 64 rows and columns. Workgroup of 256 threads = 4 wavefronts in 2 x 2, each a
+// TM/2 x TM/2 quarter (TM/64 x TM/64 MFMA tiles of 32 x 32); the K loop steps by 32, two
+// 16-wide MFMA steps per slice. Both operands sit in LDS k-contiguous (A as [m][k], B transposed
+// as [n][k]) with rows padded to 40 elements (80 bytes: eight lanes reading or writing 16 bytes
+// each cover the 32 banks once), so every fragment read and every slice write is a 16-byte LDS
+// access. The next slice is loaded from memory into registers while the current one is
+// multiplied (two LDS buffers, one barrier per slice). An operand is loaded along k when it is
+// k-contiguous (AKC / BKC: 16-byte loads of 8-element granules) and otherwise one element per k
+// with the wavefront's lanes on consecutive rows (each load instruction reads one contiguous run
+// of the row dimension). The loads are branch-free: addresses are clamped into the operand and
+// out-of-range values replaced by zero, so that the loads of the next slice stay in flight
+// while the current one is multiplied. Epilogue and split K as in k_gemm.
+constexpr int kTK = 32, kTPad = 40;
+
+__device__ __forceinline__ uint32_t bf16_bits(__bf16 x) {
+    return __builtin_bit_cast(unsigned short, x);
+}
+
+// EPT bf16 values of one thread's share of a slice, packed two to a 32-bit word.
+template <int EPT>
+struct Slice {
+    uint4 w[EPT / 8];
+};
+
+// One operand's slice (TM rows: m, or n for B; kTK k-values) into registers. x_r, x_k: the
+// operand's strides along its rows and along k; r0: the tile's first row; k0: the slice's first
+// k; rows and kend bound the operand. KC: k-contiguous (x_k == 1, x_r and kend multiples of 8,
+// 16-byte aligned base); otherwise x_r == 1.
+template <int TM, bool KC>
+__device__ __forceinline__ void load_slice(const __bf16* __restrict__ X, int64_t x_r, int64_t x_k,
+                                           int r0, int rows, int k0, int kend, int tid,
+                                           Slice<TM / 8>& sl) {
+    constexpr int EPT = TM / 8;           // elements per thread
+    constexpr int TPR = kTK / EPT;        // threads per row (k-contiguous mapping)
+    if constexpr (KC) {
+        const int r = r0 + tid / TPR, k = k0 + EPT * (tid % TPR);
+        const __bf16* row = X + static_cast<int64_t>(min(r, rows - 1)) * x_r;
+#pragma unroll
+        for (int g = 0; g < EPT / 8; ++g) {
+            const int kg = k + 8 * g;
+            const uint4 v = *reinterpret_cast<const uint4*>(row + min(kg, kend - 8));
+            const bool ok = r < rows && kg < kend;
+            sl.w[g].x = ok ? v.x : 0u;
+            sl.w[g].y = ok ? v.y : 0u;
+            sl.w[g].z = ok ? v.z : 0u;
+            sl.w[g].w = ok ? v.w : 0u;
+        }
+    } else {
+        // one row per thread, EPT consecutive k; consecutive lanes take consecutive rows
+        const int r = r0 + tid % TM, k = k0 + EPT * (tid / TM);
+        const __bf16* col = X + min(r, rows - 1);
+        uint32_t h[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const uint32_t v = bf16_bits(col[static_cast<int64_t>(min(k + e, kend - 1)) * x_k]);
+            h[e] = (r < rows && k + e < kend) ? v : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < EPT / 8; ++q) {
+            sl.w[q].x = h[8 * q + 0] | (h[8 * q + 1] << 16);
+            sl.w[q].y = h[8 * q + 2] | (h[8 * q + 3] << 16);
+            sl.w[q].z = h[8 * q + 4] | (h[8 * q + 5] << 16);
+            sl.w[q].w = h[8 * q + 6] | (h[8 * q + 7] << 16);
+        }
+    }
+}
+
+// Writes a slice loaded by load_slice into the LDS tile T[row][k] (row stride kTPad).
+template <int TM, bool KC>
+__device__ __forceinline__ void store_slice(__bf16 (*T)[kTPad], int tid, const Slice<TM / 8>& sl) {
+    constexpr int EPT = TM / 8, TPR = kTK / EPT;
+    const int r = KC ? tid / TPR : tid % TM;
+    const int k = KC ? EPT * (tid % TPR) : EPT * (tid / TM);
+    uint4* d = reinterpret_cast<uint4*>(&T[r][k]);
+#pragma unroll
+    for (int q = 0; q < EPT / 8; ++q) d[q] = sl.w[q];
+}
+
+template <int TM, bool AKC, bool BKC>
+__global__ void __launch_bounds__(256) k_gemm_tile(int M, int N, int K, const __bf16* __restrict__ A,
+                                                   int64_t a_i, int64_t a_k,
+                                                   const __bf16* __restrict__ B, int64_t b_k,
+                                                   int64_t b_j, const float* __restrict__ bias,
+                                                   int mode, const __bf16* __restrict__ gate,
+                                                   float* __restrict__ Cf, __bf16* __restrict__ Cb,
+                                                   int64_t ldc, int kps, float* __restrict__ part) {
+    constexpr int NT = TM / 64;  // MFMA tiles per wavefront along each dimension
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][TM][kTPad];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][TM][kTPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+    const int kbeg = blockIdx.z * kps, kend = min(K, kbeg + kps);
+    // B is addressed as [n][k]: its row stride is b_j, its k stride b_k
+    Slice<TM / 8> sa, sb;
+    load_slice<TM, AKC>(A, a_i, a_k, m0, M, kbeg, kend, tid, sa);
+    load_slice<TM, BKC>(B, b_j, b_k, n0, N, kbeg, kend, tid, sb);
+    store_slice<TM, AKC>(As[0], tid, sa);
+    store_slice<TM, BKC>(Bs[0], tid, sb);
+    __syncthreads();
+    floatx16 acc[NT][NT] = {};
+    const int r = lane & 31, half = lane >> 5;
+    int buf = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += kTK) {
+        // the last slice reloads itself (in range, unused): no branch around the loads
+        const int kn = k0 + kTK < kend ? k0 + kTK : k0;
+        load_slice<TM, AKC>(A, a_i, a_k, m0, M, kn, kend, tid, sa);
+        load_slice<TM, BKC>(B, b_j, b_k, n0, N, kn, kend, tid, sb);
+#pragma unroll
+        for (int ks = 0; ks < kTK / 16; ++ks) {
+            bf16x8 fa[NT], fb[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                fa[t] = *reinterpret_cast<const bf16x8*>(
+                    &As[buf][wm * (TM / 2) + t * 32 + r][ks * 16 + 8 * half]);
+                fb[t] = *reinterpret_cast<const bf16x8*>(
+                    &Bs[buf][wn * (TM / 2) + t * 32 + r][ks * 16 + 8 * half]);
+            }
+#pragma unroll
+            for (int tm = 0; tm < NT; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < NT; ++tn)
+                    acc[tm][tn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[tm], fb[tn],
+                                                                          acc[tm][tn], 0, 0, 0);
+        }
+        // unconditional (the other buffer was last read before the previous barrier), so that
+        // the loads above are issued before the multiplies rather than sunk into a branch
+        store_slice<TM, AKC>(As[buf ^ 1], tid, sa);
+        store_slice<TM, BKC>(Bs[buf ^ 1], tid, sb);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int tm = 0; tm < NT; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < NT; ++tn)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int i = m0 + wm * (TM / 2) + tm * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+                const int j = n0 + wn * (TM / 2) + tn * 32 + r;
+                if (i >= M || j >= N) continue;
+                const float a = acc[tm][tn][e];
+                if (gridDim.z > 1) {
+                    part[(static_cast<int64_t>(blockIdx.z) * M + i) * N + j] = a;
+                    continue;
+                }
+                float v = a;
+                if (bias != nullptr) v += bias[j];
+                const int64_t o = static_cast<int64_t>(i) * ldc + j;
+                if (mode == 0) {
+                    Cf[o] = v;
+                } else if (mode == 1) {
+                    Cb[o] = static_cast<__bf16>(fmaxf(v, 0.0f));
+                } else {
+                    const float g = static_cast<float>(gate[o]);
+                    Cb[o] = static_cast<__bf16>(g > 0.0f ? v : 0.0f);
+                }
+            }
+}
+
+// Products with at most kNarrow output columns and a k-contiguous A (the action-slot layer):
+// half a wavefront per row, lane l taking k = c + 8 l' .. + 7 of every 256-wide chunk c (l' =
+// l % 32: one 16-byte load per lane, so the half-wavefront reads one contiguous 512-byte run of
+// the row), each lane accumulating all N columns in FP32, then a butterfly over the 32 lanes in
+// a fixed order. B is staged once per workgroup in LDS as FP32, ordered [chunk][e][lane][n] so
+// that for each e the 32 lanes read consecutive N-float groups (no bank conflicts). Each
+// wavefront takes kNarrowRows rows: the loads of all of them are issued before the first
+// multiply. Epilogue as k_gemm (no split K). Needs ceil(K / 256) * 256 * N <= kNarrowLds, a row
+// stride a multiple of 8 and a 16-byte aligned A.
+constexpr int kNarrow = 8;
+constexpr int kNarrowRows = 8;
+constexpr int kNarrowLds = 8192;
+
+__global__ void __launch_bounds__(256) k_gemm_narrow(int M, int N, int K,
+                                                     const __bf16* __restrict__ A, int64_t a_i,
+                                                     const __bf16* __restrict__ B, int64_t b_k,
+                                                     int64_t b_j, const float* __restrict__ bias,
+                                                     int mode, const __bf16* __restrict__ gate,
+                                                     float* __restrict__ Cf,
+                                                     __bf16* __restrict__ Cb, int64_t ldc) {
+    extern __shared__ float Wl[];
+    const int Kp = (K + 255) / 256 * 256;
+    for (int t = threadIdx.x; t < Kp * N; t += blockDim.x) {
+        const int n = t % N, q = t / N;
+        const int l = q % 32, e = (q / 32) % 8, c = q / 256;
+        const int k = 256 * c + 8 * l + e;
+        Wl[t] = k < K ? static_cast<float>(B[static_cast<int64_t>(k) * b_k + n * b_j]) : 0.0f;
+    }
+    __syncthreads();
+    constexpr int P = kNarrowRows / 2;  // row pairs per wavefront
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int l = lane & 31, half = lane >> 5;
+    const int base = (blockIdx.x * 4 + wave) * kNarrowRows + half;
+    float acc[P][kNarrow];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int n = 0; n < kNarrow; ++n) acc[p][n] = 0.0f;
+#pragma unroll 1
+    for (int c = 0; c < K; c += 256) {
+        const int k = c + 8 * l;
+        uint4 xw[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int i = min(base + 2 * p, M - 1);
+            const uint4 v = *reinterpret_cast<const uint4*>(A + static_cast<int64_t>(i) * a_i +
+                                                            min(k, K - 8));
+            const bool ok = k < K;  // K is a multiple of 8
+            xw[p].x = ok ? v.x : 0u;
+            xw[p].y = ok ? v.y : 0u;
+            xw[p].z = ok ? v.z : 0u;
+            xw[p].w = ok ? v.w : 0u;
+        }
+        const float* wl = Wl + (c / 256) * 256 * N;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            float w[kNarrow];
+#pragma unroll
+            for (int n = 0; n < kNarrow; ++n) w[n] = n < N ? wl[(e * 32 + l) * N + n] : 0.0f;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const uint32_t wd = e / 2 == 0 ? xw[p].x : e / 2 == 1 ? xw[p].y
+                                    : e / 2 == 2 ? xw[p].z : xw[p].w;
+                const float x = static_cast<float>(__builtin_bit_cast(
+                    __bf16, static_cast<unsigned short>(wd >> (16 * (e % 2)))));
+#pragma unroll
+                for (int n = 0; n < kNarrow; ++n) acc[p][n] = fmaf(x, w[n], acc[p][n]);
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int n = 0; n < kNarrow; ++n)
+            for (int off = 16; off > 0; off >>= 1) acc[p][n] += __shfl_xor(acc[p][n], off, 32);
+    if (l != 0) return;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int i = base + 2 * p;
+        if (i >= M) break;
+#pragma unroll
+        for (int n = 0; n < kNarrow; ++n) {
+            if (n >= N) break;
+            float v = acc[p][n];
+            if (bias != nullptr) v += bias[n];
+            const int64_t o = static_cast<int64_t>(i) * ldc + n;
+            if (mode == 0) {
+                Cf[o] = v;
+            } else if (mode == 1) {
+                Cb[o] = static_cast<__bf16>(fmaxf(v, 0.0f));
+            } else {
+                const float g = static_cast<float>(gate[o]);
+                Cb[o] = static_cast<__bf16>(g > 0.0f ? v : 0.0f);
+            }
+        }
+    }
+}
+
+// dst[c][r] = src[r][c] for a rows x cols BF16 matrix (the transposed weight copies).
+__global__ void k_transpose_bf16(int rows, int cols, const __bf16* __restrict__ src,
+                                 __bf16* __restrict__ dst) {
+    const int64_t t = gid();
+    if (t >= static_cast<int64_t>(rows) * cols) return;
+    const int64_t r = t / cols, c = t % cols;
+    dst[c * rows + r] = src[t];
+}
+
 // Masked softmax cross-entropy per row: loss += -(1/B) sum_a mask t log p, and
 // dZ[b, a] = mask (p tsum - t) / B in BF16.
 __global__ void k_softmax_xent(int B, int A, const float* __restrict__ Z,
@@ -130,6 +398,19 @@ __global__ void k_sum_splits(int M, int N, int splits, const float* __restrict__
     float s = 0.0f;
     for (int z = 0; z < splits; ++z) s += part[(static_cast<int64_t>(z) * M + i) * N + j];
     C[i * ldc + j] = s;
+}
+
+// Sums `splits` partials part[z][cols] per column: one wavefront per column, lane l adding
+// partials l, l + 64, ... in order, then a butterfly over the 64 lanes in a fixed order.
+__global__ void __launch_bounds__(256) k_sum_cols(int cols, int splits,
+                                                  const float* __restrict__ part,
+                                                  float* __restrict__ out) {
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (c >= cols) return;
+    float s = 0.0f;
+    for (int z = lane; z < splits; z += 64) s += part[static_cast<int64_t>(z) * cols + c];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[c] = s;
 }
 
 // Column sums of a BF16 [rows x cols] matrix (bias gradients), split over rows: workgroup
@@ -278,17 +559,60 @@ __global__ void k_warm_start(int64_t Hp, const int32_t* __restrict__ q_offset,
 void launch_gemm(int M, int N, int K, const void* A, int64_t a_i, int64_t a_k, const void* B,
                  int64_t b_k, int64_t b_j, const float* bias, int mode, const void* gate, float* Cf,
                  void* Cb, int64_t ldc, hipStream_t st, float* part) {
+    const auto* a = static_cast<const __bf16*>(A);
+    const auto* b = static_cast<const __bf16*>(B);
+    const auto* g = static_cast<const __bf16*>(gate);
+    auto* cb = static_cast<__bf16*>(Cb);
+    // a few output columns from a k-contiguous A: half a wavefront per row
+    const int Kp = (K + 255) / 256 * 256;
+    if (N <= kNarrow && a_k == 1 && a_i % 8 == 0 && K % 8 == 0 && Kp * N <= kNarrowLds &&
+        (reinterpret_cast<uintptr_t>(a) % 16) == 0 &&
+        (part == nullptr || mode != 0 || bias != nullptr || K < 2 * kSplitK)) {
+        const int rows_per_wg = 4 * kNarrowRows;
+        hipLaunchKernelGGL(k_gemm_narrow, dim3((M + rows_per_wg - 1) / rows_per_wg), dim3(256),
+                           static_cast<size_t>(Kp) * N * sizeof(float), st, M, N, K, a, a_i, b, b_k,
+                           b_j, bias, mode, g, Cf, cb, ldc);
+        return;
+    }
+    // LDS tiles where both output dimensions fill them and each operand is k-contiguous (rows
+    // of 8-element granules, 16-byte aligned) or row-contiguous; the other skinny products stay
+    // on one wavefront per 32 x 32 tile
+    auto aligned16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) % 16) == 0; };
+    const bool akc = a_k == 1 && a_i % 8 == 0 && K % 8 == 0 && aligned16(a);
+    const bool bkc = b_k == 1 && b_j % 8 == 0 && K % 8 == 0 && aligned16(b);
+    const bool tiled = M >= 64 && N >= 64 && K >= kTK && (akc || a_i == 1) && (bkc || b_j == 1);
+    const int step = tiled ? kTK : 16;
     // split K only for FP32 outputs without bias (weight gradients) when K is long
     int splits = 1;
     if (part != nullptr && mode == 0 && bias == nullptr && K >= 2 * kSplitK)
         splits = min(kMaxSplits, K / kSplitK);
-    const int kps = ((K + splits - 1) / splits + 15) / 16 * 16;
+    const int kps = ((K + splits - 1) / splits + step - 1) / step * step;
     splits = (K + kps - 1) / kps;
-    dim3 grid((N + 31) / 32, (M + 31) / 32, splits);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(64), 0, st, M, N, K, static_cast<const __bf16*>(A), a_i,
-                       a_k, static_cast<const __bf16*>(B), b_k, b_j, bias, mode,
-                       static_cast<const __bf16*>(gate), Cf, static_cast<__bf16*>(Cb), ldc, kps,
-                       part);
+    if (tiled) {
+        // 128 x 128 tiles when they alone give the chip a few workgroups per CU, else 64 x 64
+        const int64_t big = int64_t{(N + 127) / 128} * ((M + 127) / 128) * splits;
+        const int tm = big >= 512 ? 128 : 64;
+        dim3 grid((N + tm - 1) / tm, (M + tm - 1) / tm, splits);
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, grid, dim3(256), 0, st, M, N, K, a, a_i, a_k, b, b_k, b_j,
+                               bias, mode, g, Cf, cb, ldc, kps, part);
+        };
+        if (tm == 128) {
+            if (akc && bkc) go(k_gemm_tile<128, true, true>);
+            else if (akc) go(k_gemm_tile<128, true, false>);
+            else if (bkc) go(k_gemm_tile<128, false, true>);
+            else go(k_gemm_tile<128, false, false>);
+        } else {
+            if (akc && bkc) go(k_gemm_tile<64, true, true>);
+            else if (akc) go(k_gemm_tile<64, true, false>);
+            else if (bkc) go(k_gemm_tile<64, false, true>);
+            else go(k_gemm_tile<64, false, false>);
+        }
+    } else {
+        dim3 grid((N + 31) / 32, (M + 31) / 32, splits);
+        hipLaunchKernelGGL(k_gemm, grid, dim3(64), 0, st, M, N, K, a, a_i, a_k, b, b_k, b_j, bias,
+                           mode, g, Cf, cb, ldc, kps, part);
+    }
     if (splits > 1)
         hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for(int64_t{M} * N, 256)), dim3(256), 0, st, M,
                            N, splits, part, Cf, ldc);
@@ -300,13 +624,20 @@ void launch_softmax_xent(int B, int A, const float* Z, const float* target, cons
                        mask, static_cast<__bf16*>(dZ), loss);
 }
 
+void launch_transpose_bf16(int rows, int cols, const void* src, void* dst, hipStream_t st) {
+    const int64_t n = int64_t{rows} * cols;
+    if (n > 0)
+        hipLaunchKernelGGL(k_transpose_bf16, dim3(blocks_for(n, 256)), dim3(256), 0, st, rows, cols,
+                           static_cast<const __bf16*>(src), static_cast<__bf16*>(dst));
+}
+
 void launch_colsum(int rows, int cols, const void* G, float* out, hipStream_t st, float* part) {
-    const int splits = max(1, min(kMaxSplits, rows / kSplitK));
+    // 32 rows per split, at most kColsumMaxSplits partials
+    const int splits = max(1, min(kColsumMaxSplits, rows / 32));
     const int rps = (rows + splits - 1) / splits;
     hipLaunchKernelGGL(k_colsum_part, dim3((cols + 63) / 64, splits), dim3(64), 0, st, rows, cols,
                        rps, static_cast<const __bf16*>(G), part);
-    hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for(cols, 256)), dim3(256), 0, st, 1, cols, splits,
-                       part, out, int64_t{cols});
+    hipLaunchKernelGGL(k_sum_cols, dim3((cols + 3) / 4), dim3(256), 0, st, cols, splits, part, out);
 }
 
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, void* wb, float lr,

@@ -32,12 +32,17 @@ constexpr int kSlots = 4;      // action slots: fold, call, pot-raise, all-in
 // the partials need kMaxSplits * M * N floats at `part` (nullptr: no split).
 constexpr int kSplitK = 256;
 constexpr int kMaxSplits = 32;
+// Column sums (bias gradients) split the rows 32 at a time into at most this many partials of
+// `cols` floats each at `part`.
+constexpr int kColsumMaxSplits = 1024;
 void launch_gemm(int M, int N, int K, const void* A, int64_t a_i, int64_t a_k, const void* B,
                  int64_t b_k, int64_t b_j, const float* bias, int mode, const void* gate, float* Cf,
                  void* Cb, int64_t ldc, hipStream_t st, float* part = nullptr);
 void launch_softmax_xent(int B, int A, const float* Z, const float* target, const float* mask,
                          void* dZ, float* loss, hipStream_t st);
 void launch_colsum(int rows, int cols, const void* G, float* out, hipStream_t st, float* part);
+// dst = src transposed, src a rows x cols BF16 matrix
+void launch_transpose_bf16(int rows, int cols, const void* src, void* dst, hipStream_t st);
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, void* wb, float lr,
                  float b1, float b2, float eps, float c1, float c2, hipStream_t st);
 void launch_to_bf16(int64_t n, const float* src, void* dst, hipStream_t st);

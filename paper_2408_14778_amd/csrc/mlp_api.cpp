@@ -35,6 +35,7 @@ size_t layout(cfr_mlp& n, void* base, int32_t F, int32_t H, int32_t A, int32_t m
     n.m = static_cast<float*>(take(P * 4));
     n.v = static_cast<float*>(take(P * 4));
     n.wb = static_cast<__bf16*>(take(P * 2));
+    n.wbT = static_cast<__bf16*>(take(P * 2));
     n.A1 = static_cast<__bf16*>(take(int64_t{maxB} * H * 2));
     n.A2 = static_cast<__bf16*>(take(int64_t{maxB} * H * 2));
     n.dZ2 = static_cast<__bf16*>(take(int64_t{maxB} * H * 2));
@@ -42,8 +43,10 @@ size_t layout(cfr_mlp& n, void* base, int32_t F, int32_t H, int32_t A, int32_t m
     n.dZ3 = static_cast<__bf16*>(take(int64_t{maxB} * A * 2));
     n.Z3 = static_cast<float*>(take(int64_t{maxB} * A * 4));
     n.loss = static_cast<float*>(take(4));
+    // split-K partials of the weight gradients, or the column-sum partials of the bias gradients
     n.part = static_cast<float*>(
-        take(int64_t{cfr::kMaxSplits} * std::max(F, H) * std::max(H, A) * 4));
+        take(std::max(int64_t{cfr::kMaxSplits} * std::max(F, H) * std::max(H, A),
+                      int64_t{cfr::kColsumMaxSplits} * std::max(H, A)) * 4));
     return (off + 255) & ~size_t{255};
 }
 
@@ -58,15 +61,27 @@ int hip_fail(hipError_t e, const char* what) {
     } while (0)
 
 void forward(cfr_mlp* n, const void* x, int32_t B) {
-    int64_t o[7];
+    int64_t o[7], t[3];
     offsets(n->F, n->H, n->A, o);
+    cfr::transposed_offsets(n->F, n->H, n->A, t);
     const int F = n->F, H = n->H, A = n->A;
-    cfr::launch_gemm(B, H, F, x, F, 1, n->wb + o[0], H, 1, n->w + o[1], 1, nullptr, nullptr, n->A1,
+    // B(k, j) = W[k][j] = W^T[j][k]: the transposed copies are k-contiguous
+    cfr::launch_gemm(B, H, F, x, F, 1, n->wbT + t[0], 1, F, n->w + o[1], 1, nullptr, nullptr, n->A1,
                      H, n->st);
-    cfr::launch_gemm(B, H, H, n->A1, H, 1, n->wb + o[2], H, 1, n->w + o[3], 1, nullptr, nullptr,
+    cfr::launch_gemm(B, H, H, n->A1, H, 1, n->wbT + t[1], 1, H, n->w + o[3], 1, nullptr, nullptr,
                      n->A2, H, n->st);
-    cfr::launch_gemm(B, A, H, n->A2, H, 1, n->wb + o[4], A, 1, n->w + o[5], 0, nullptr, n->Z3,
+    cfr::launch_gemm(B, A, H, n->A2, H, 1, n->wbT + t[2], 1, H, n->w + o[5], 0, nullptr, n->Z3,
                      nullptr, A, n->st);
+}
+
+// Refreshes the transposed weight copies from wb.
+void transpose_weights(cfr_mlp* n) {
+    int64_t o[7], t[3];
+    offsets(n->F, n->H, n->A, o);
+    cfr::transposed_offsets(n->F, n->H, n->A, t);
+    cfr::launch_transpose_bf16(n->F, n->H, n->wb + o[0], n->wbT + t[0], n->st);
+    cfr::launch_transpose_bf16(n->H, n->H, n->wb + o[2], n->wbT + t[1], n->st);
+    cfr::launch_transpose_bf16(n->H, n->A, n->wb + o[4], n->wbT + t[2], n->st);
 }
 
 }  // namespace
@@ -108,6 +123,7 @@ int cfr_mlp_set_params(cfr_mlp* n, const float* params, int64_t count) {
         return cfr::set_error(CFR_EINVAL, "parameter count mismatch");
     MLP_TRY(hipMemcpyAsync(n->w, params, count * 4, hipMemcpyHostToDevice, n->st), "params copy");
     cfr::launch_to_bf16(count, n->w, n->wb, n->st);
+    transpose_weights(n);
     std::vector<float> zeros(count, 0.0f);
     MLP_TRY(hipMemcpyAsync(n->m, zeros.data(), count * 4, hipMemcpyHostToDevice, n->st), "moments");
     MLP_TRY(hipMemcpyAsync(n->v, zeros.data(), count * 4, hipMemcpyHostToDevice, n->st), "moments");
@@ -175,6 +191,7 @@ int cfr_mlp_train_step(cfr_mlp* n, const void* x, const float* target, const flo
     const float c1 = 1.0f - std::pow(b1, static_cast<float>(n->step));
     const float c2 = 1.0f - std::pow(b2, static_cast<float>(n->step));
     cfr::launch_adam(n->n_params, n->w, n->g, n->m, n->v, n->wb, lr, b1, b2, 1e-8f, c1, c2, n->st);
+    transpose_weights(n);
     MLP_TRY(hipGetLastError(), "train launch");
     if (loss != nullptr) {
         MLP_TRY(hipMemcpyAsync(loss, n->loss, 4, hipMemcpyDeviceToHost, n->st), "loss copy");

@@ -14,6 +14,9 @@ struct cfr_mlp {
     // [W1 | b1 | W2 | b2 | W3 | b3] blocks
     float *w, *g, *m, *v;
     __bf16* wb;
+    // the weight matrices transposed, [W1^T (H x F) | W2^T (H x H) | W3^T (A x H)], refreshed
+    // with wb: the forward pass reads both GEMM operands along k
+    __bf16* wbT;
     // activations
     __bf16 *A1, *A2, *dZ3, *dZ2, *dZ1;
     float *Z3, *loss;
@@ -33,6 +36,14 @@ inline int64_t offsets(int32_t F, int32_t H, int32_t A, int64_t off[7]) {
     off[5] = off[4] + int64_t{H} * A;  // b3
     off[6] = off[5] + A;
     return off[6];
+}
+
+// Offsets of W1^T, W2^T, W3^T in the transposed copy.
+inline void transposed_offsets(int32_t F, int32_t H, int32_t A, int64_t t[3]) {
+    (void)A;
+    t[0] = 0;
+    t[1] = int64_t{F} * H;
+    t[2] = t[1] + int64_t{H} * H;
 }
 
 }  // namespace cfr

@@ -65,14 +65,16 @@ extern "C" int cfr_mlp_forward_noalloc(cfr_mlp* n, const void* x, int32_t batch,
     if (const int rc = scratch_of_current_device(&base); rc != CFR_OK) return rc;
     __bf16* A1 = static_cast<__bf16*>(base);
     __bf16* A2 = reinterpret_cast<__bf16*>(static_cast<unsigned char*>(base) + act);
-    int64_t o[7];
+    int64_t o[7], t[3];
     cfr::offsets(n->F, n->H, n->A, o);
+    cfr::transposed_offsets(n->F, n->H, n->A, t);
     const int F = n->F, H = n->H, A = n->A;
-    cfr::launch_gemm(batch, H, F, x, F, 1, n->wb + o[0], H, 1, n->w + o[1], 1, nullptr, nullptr, A1,
+    // the weights' transposed copies, k-contiguous, as in cfr_mlp_forward
+    cfr::launch_gemm(batch, H, F, x, F, 1, n->wbT + t[0], 1, F, n->w + o[1], 1, nullptr, nullptr, A1,
                      H, n->st);
-    cfr::launch_gemm(batch, H, H, A1, H, 1, n->wb + o[2], H, 1, n->w + o[3], 1, nullptr, nullptr, A2,
+    cfr::launch_gemm(batch, H, H, A1, H, 1, n->wbT + t[1], 1, H, n->w + o[3], 1, nullptr, nullptr, A2,
                      H, n->st);
-    cfr::launch_gemm(batch, A, H, A2, H, 1, n->wb + o[4], A, 1, n->w + o[5], 0, nullptr, logits,
+    cfr::launch_gemm(batch, A, H, A2, H, 1, n->wbT + t[2], 1, H, n->w + o[5], 0, nullptr, logits,
                      nullptr, A, n->st);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -339,7 +339,18 @@ def main() -> int:
     ap.add_argument("--select-only", action="store_true",
                     help="choose the weight of the stored network again on the validation games "
                          "(--weights, --val-games), then evaluate it on the held-out games")
+    ap.add_argument("--throughput-only", action="store_true",
+                    help="time the network's forward pass (65,536 rows) and one training step "
+                         "(4,096 rows) with random weights and print them as JSON")
     args = ap.parse_args()
+    if args.throughput_only:
+        import torch
+        from . import warmstart as ws
+        torch.cuda.set_device(0)
+        net = ws.WarmStartNet(max_batch=4096, seed=1)
+        infer = ws.WarmStartNet(max_batch=65536, seed=1)
+        print(json.dumps(mlp_throughput(infer, net)), flush=True)
+        return 0
     if args.eval_only:
         return eval_only(args)
     if args.select_only:

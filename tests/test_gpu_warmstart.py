@@ -39,7 +39,8 @@ def _net(F, H, A, B, seed):
     return WarmStartNet(F, H, A, max_batch=B, seed=seed)
 
 
-@pytest.mark.parametrize("F,H,A,B", [(96, 256, 4, 300), (40, 64, 4, 77), (96, 256, 4, 4096)])
+@pytest.mark.parametrize("F,H,A,B", [(96, 256, 4, 300), (40, 64, 4, 77), (96, 256, 4, 4096),
+                                     (72, 128, 4, 333), (96, 256, 4, 65536)])
 def test_forward_matches_bf16_emulation(F, H, A, B):
     import torch
     rng = np.random.default_rng(F + H + B)
