@@ -342,6 +342,134 @@ __global__ void __launch_bounds__(256) k_gemm_narrow(int M, int N, int K,
     }
 }
 
+// The whole forward pass in one kernel (inference): one wavefront per 32 rows, its rows' input,
+// then its hidden activations, in a private LDS region; the weights come from their transposed
+// BF16 copies (k-contiguous, L2-resident), one 16-byte load per lane per MFMA B fragment.
+// Layer 1: A fragments from the staged input rows, H / 32 output tiles of 32 x 32 in FP32
+// accumulators; bias and ReLU, rounded to BF16 into LDS (over the input, which is no longer
+// needed). Layer 2: the same from the first hidden layer, written back over it. Layer 3 as
+// k_gemm_narrow does it, from LDS, FP32 logits to memory. Every element is computed as by the
+// per-layer kernels (k_gemm_tile, k_gemm_narrow), bit for bit: the same BF16 operands, FP32
+// accumulation over k in the same 16-wide MFMA steps, the same rounding of the hidden layers,
+// the same order of the last layer's sums. F: a multiple of 16 up to kFusedMaxF; A <= kNarrow.
+constexpr int kFusedMaxF = 128;
+
+template <int H>
+__global__ void __launch_bounds__(64, 2) k_mlp_forward(int M, int F, int A,
+                                                    const __bf16* __restrict__ X,
+                                                    const __bf16* __restrict__ W1T,
+                                                    const float* __restrict__ b1,
+                                                    const __bf16* __restrict__ W2T,
+                                                    const float* __restrict__ b2,
+                                                    const __bf16* __restrict__ W3T,
+                                                    const float* __restrict__ b3,
+                                                    float* __restrict__ Z) {
+    constexpr int LD = H + 8;  // row stride of the LDS tile (elements): 16-byte aligned rows
+    constexpr int NT = H / 32;
+    __shared__ __attribute__((aligned(16))) __bf16 T[32][LD];
+    const int lane = threadIdx.x, r = lane & 31, half = lane >> 5;
+    const int m0 = blockIdx.x * 32;
+    // stage the 32 input rows (zero past M): 8-element granules, 16-byte loads
+    const int gpr = F / 8;  // granules per row
+    for (int q = lane; q < 32 * gpr; q += 64) {
+        const int row = q / gpr, c = 8 * (q % gpr);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (m0 + row < M) v = *reinterpret_cast<const uint4*>(X + static_cast<int64_t>(m0 + row) * F + c);
+        *reinterpret_cast<uint4*>(&T[row][c]) = v;
+    }
+    __syncthreads();
+    floatx16 acc[NT];
+    // layer 1: [32 x F] . W1 -> [32 x H]
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = floatx16{};
+    for (int k = 0; k < F; k += 16) {
+        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&T[r][k + 8 * half]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8 fb = *reinterpret_cast<const bf16x8*>(
+                W1T + static_cast<int64_t>(t * 32 + r) * F + k + 8 * half);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[t], 0, 0, 0);
+        }
+    }
+    __syncthreads();  // every lane's reads of the input rows are done before they are overwritten
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int col = t * 32 + r;
+        const float bias = b1[col];
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            T[8 * (e >> 2) + 4 * half + (e & 3)][col] =
+                static_cast<__bf16>(fmaxf(acc[t][e] + bias, 0.0f));
+    }
+    __syncthreads();
+    // layer 2: [32 x H] . W2 -> [32 x H]
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = floatx16{};
+#pragma unroll 1
+    for (int k = 0; k < H; k += 16) {
+        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&T[r][k + 8 * half]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8 fb = *reinterpret_cast<const bf16x8*>(
+                W2T + static_cast<int64_t>(t * 32 + r) * H + k + 8 * half);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[t], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int col = t * 32 + r;
+        const float bias = b2[col];
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            T[8 * (e >> 2) + 4 * half + (e & 3)][col] =
+                static_cast<__bf16>(fmaxf(acc[t][e] + bias, 0.0f));
+    }
+    __syncthreads();
+    // layer 3: [32 x H] . W3 -> [32 x A], A <= kNarrow, in the order of k_gemm_narrow: half a
+    // wavefront per row, lane l' taking k = 8 l' .. + 7 (zero past H), FMAs over e in order,
+    // then the butterfly over the 32 lanes
+    float w[8][kNarrow];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int n = 0; n < kNarrow; ++n)
+            w[e][n] = (n < A && 8 * r + e < H)
+                          ? static_cast<float>(W3T[static_cast<int64_t>(n) * H + 8 * r + e])
+                          : 0.0f;
+#pragma unroll 1
+    for (int p = 0; p < 16; ++p) {
+        const int row = 2 * p + half;
+        float x[8];
+        if (8 * r < H) {
+            const uint4 v = *reinterpret_cast<const uint4*>(&T[row][8 * r]);
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                x[e] = static_cast<float>(__builtin_bit_cast(
+                    __bf16, static_cast<unsigned short>(wd[e / 2] >> (16 * (e % 2)))));
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+        }
+        float z[kNarrow];
+#pragma unroll
+        for (int n = 0; n < kNarrow; ++n) z[n] = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+            for (int n = 0; n < kNarrow; ++n) z[n] = fmaf(x[e], w[e][n], z[n]);
+#pragma unroll
+        for (int n = 0; n < kNarrow; ++n)
+            for (int off = 16; off > 0; off >>= 1) z[n] += __shfl_xor(z[n], off, 32);
+        if (r == 0 && m0 + row < M) {
+#pragma unroll
+            for (int n = 0; n < kNarrow; ++n)
+                if (n < A) Z[static_cast<int64_t>(m0 + row) * A + n] = z[n] + b3[n];
+        }
+    }
+}
+
 // dst[c][r] = src[r][c] for a rows x cols BF16 matrix (the transposed weight copies).
 __global__ void k_transpose_bf16(int rows, int cols, const __bf16* __restrict__ src,
                                  __bf16* __restrict__ dst) {
@@ -622,6 +750,35 @@ void launch_softmax_xent(int B, int A, const float* Z, const float* target, cons
                          void* dZ, float* loss, hipStream_t st) {
     hipLaunchKernelGGL(k_softmax_xent, dim3(blocks_for(B, 256)), dim3(256), 0, st, B, A, Z, target,
                        mask, static_cast<__bf16*>(dZ), loss);
+}
+
+bool launch_mlp_forward(int M, int F, int H, int A, const void* X, const void* W1T, const float* b1,
+                        const void* W2T, const float* b2, const void* W3T, const float* b3,
+                        float* Z, hipStream_t st) {
+    if (F % 16 != 0 || F > kFusedMaxF || A > kNarrow ||
+        (reinterpret_cast<uintptr_t>(X) % 16) != 0)
+        return false;
+    const auto* x = static_cast<const __bf16*>(X);
+    const auto* w1 = static_cast<const __bf16*>(W1T);
+    const auto* w2 = static_cast<const __bf16*>(W2T);
+    const auto* w3 = static_cast<const __bf16*>(W3T);
+    const dim3 grid((M + 31) / 32);
+    switch (H) {
+        case 64:
+            hipLaunchKernelGGL(k_mlp_forward<64>, grid, dim3(64), 0, st, M, F, A, x, w1, b1, w2, b2,
+                               w3, b3, Z);
+            return true;
+        case 128:
+            hipLaunchKernelGGL(k_mlp_forward<128>, grid, dim3(64), 0, st, M, F, A, x, w1, b1, w2,
+                               b2, w3, b3, Z);
+            return true;
+        case 256:
+            hipLaunchKernelGGL(k_mlp_forward<256>, grid, dim3(64), 0, st, M, F, A, x, w1, b1, w2,
+                               b2, w3, b3, Z);
+            return true;
+        default:
+            return false;
+    }
 }
 
 void launch_transpose_bf16(int rows, int cols, const void* src, void* dst, hipStream_t st) {

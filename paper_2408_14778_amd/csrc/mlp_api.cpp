@@ -152,9 +152,19 @@ int cfr_mlp_get_grads(cfr_mlp* n, float* grads, int64_t count) {
 int cfr_mlp_forward(cfr_mlp* n, const void* x, int32_t batch, float* logits) {
     if (n == nullptr || x == nullptr || logits == nullptr || batch < 1 || batch > n->maxB)
         return cfr::set_error(CFR_EINVAL, "bad batch or null argument");
-    forward(n, x, batch);
-    MLP_TRY(hipMemcpyAsync(logits, n->Z3, int64_t{batch} * n->A * 4, hipMemcpyDeviceToDevice, n->st),
-            "logits copy");
+    // the three layers in one kernel where the shape allows (the same logits, bit for bit),
+    // else layer by layer through the activation buffers
+    int64_t o[7], t[3];
+    offsets(n->F, n->H, n->A, o);
+    cfr::transposed_offsets(n->F, n->H, n->A, t);
+    if (!cfr::launch_mlp_forward(batch, n->F, n->H, n->A, x, n->wbT + t[0], n->w + o[1],
+                                 n->wbT + t[1], n->w + o[3], n->wbT + t[2], n->w + o[5], logits,
+                                 n->st)) {
+        forward(n, x, batch);
+        MLP_TRY(hipMemcpyAsync(logits, n->Z3, int64_t{batch} * n->A * 4, hipMemcpyDeviceToDevice,
+                               n->st),
+                "logits copy");
+    }
     MLP_TRY(hipGetLastError(), "forward launch");
     return CFR_OK;
 }

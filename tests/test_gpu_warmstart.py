@@ -40,7 +40,8 @@ def _net(F, H, A, B, seed):
 
 
 @pytest.mark.parametrize("F,H,A,B", [(96, 256, 4, 300), (40, 64, 4, 77), (96, 256, 4, 4096),
-                                     (72, 128, 4, 333), (96, 256, 4, 65536)])
+                                     (72, 128, 4, 333), (96, 256, 4, 65536), (48, 128, 4, 333),
+                                     (64, 64, 8, 100)])
 def test_forward_matches_bf16_emulation(F, H, A, B):
     import torch
     rng = np.random.default_rng(F + H + B)
@@ -59,6 +60,32 @@ def test_forward_matches_bf16_emulation(F, H, A, B):
     Zref = A2 @ W3 + b3
     err = np.abs(Z - Zref).max() / np.abs(Zref).max()
     assert err < 2e-3, err
+
+
+@pytest.mark.parametrize("F,H,A,B", [(96, 256, 4, 16384), (96, 256, 4, 37), (48, 128, 4, 1000),
+                                     (64, 64, 8, 333), (32, 256, 1, 4097)])
+def test_fused_forward_equals_per_layer_gemms(F, H, A, B):
+    """cfr_mlp_forward runs the three layers in one kernel for these shapes; the allocation-free
+    entry point runs them as three GEMMs through its device array. Every element is computed in
+    the same order (the same BF16 operands, the same 16-wide MFMA steps, the same rounding of the
+    hidden layers, the same order of the last layer's sums), so the logits agree bit for bit;
+    ragged last tiles included."""
+    import torch
+    net = _net(F, H, A, B, 7)
+    rng = np.random.default_rng(F * H + B)
+    p = mlp.init(F, H, A, seed=9)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.standard_normal(p[k].shape) * 0.1
+    net.set_params(_flat(p))
+    x = torch.from_numpy(rng.standard_normal((B, F)).astype(np.float32)).to("cuda")
+    x = x.to(torch.bfloat16)
+    ref = net.forward(x)
+    out = torch.full((B, A), float("nan"), dtype=torch.float32, device="cuda")
+    net.forward_noalloc(x, out)
+    torch.cuda.synchronize()
+    a, b = ref.cpu().numpy(), out.cpu().numpy()
+    assert np.isfinite(a).all()
+    assert np.array_equal(a, b), float(np.abs(a - b).max())
 
 
 def test_gradients_match_fp64_reference():

@@ -1,7 +1,9 @@
 """The allocation-free forward pass (cfr_mlp_forward_noalloc) against cfr_mlp_forward, through
-the C ABI: same kernels, so the logits must agree bit for bit, on two calls in a row (the
-second with a smaller batch, over the first call's leftovers in the shared device array), and
-a batch past the array's limit is refused with CFR_EINVAL."""
+the C ABI: the per-layer GEMMs through the shared device array against (for this shape) the
+fused three-layer kernel, which computes every element in the same order, so the logits must
+agree bit for bit, on two calls in a row (the second with a smaller batch, over the first
+call's leftovers in the shared device array), and a batch past the array's limit is refused
+with CFR_EINVAL."""
 import numpy as np
 import pytest
 
