@@ -63,30 +63,56 @@ def level_counts(lay: dict) -> list:
     return out
 
 
-def algorithmic_bytes(kernel: str, counts: list, reach_launch=None) -> float:
-    """Bytes `kernel` must move per iteration under the two-sweep streaming model (fp32 values,
-    int32 indices; N_int = internal nodes, chance included; only internal nodes need reach):
-    top-down, per internal non-root node, parent index and edge label 8, parent reach 8 and
-    its own reach 8 (24 B); bottom-up, per node read as a child its value 12 with its
-    structure, per internal node its value write and the acting player's reach 8, per pair
-    36 (R and S read and written, the instantaneous regret, sigma read and written, sigma
-    gathers) and per infoset 8. A level whose reach its bottom-up launch computes
-    (reach_launch[l] == 4, the solver's reach_launch layout) needs no reach written and read
-    back: its bottom-up launch moves 12 B more per internal node (parent index, edge label and
-    parent reach, less the reach read) and the top-down pass nothing for it. A kernel's
-    launches over one iteration move the sum of the levels they process; the per-launch figure
-    is that sum divided by the launches. block_reach / reach_level: top-down; block_up:
-    bottom-up (values, regrets and the infoset update fused); value_level and infoset_update:
-    the node engine's split of the bottom-up terms.
+def algorithmic_bytes(kernel: str, counts: list, reach_launch=None, real: int = 4) -> float:
+    """Bytes `kernel` must move per iteration under the two-sweep streaming model (values of
+    `real` bytes, 4 or 8; int32 indices; N_int = internal nodes, chance included; only internal
+    nodes need reach). With r = real: top-down, per internal non-root node, parent index and
+    edge label 8, the parent's two reach factors 2r and its own 2r (24 B in fp32); bottom-up,
+    per node read as a child its value r with its structure 8, per internal node its value write
+    and the acting player's reach 2r, per pair 9r (R and S read and written, the instantaneous
+    regret, sigma read and written, sigma gathers: 36 B in fp32) and per infoset 2r. A level
+    whose reach its bottom-up launch computes (reach_launch[l] == 4, the solver's reach_launch
+    layout) needs no reach written and read back: its bottom-up launch moves 8 + r more per
+    internal node (parent index, edge label and parent reach, less the reach read) and the
+    top-down pass nothing for it. A kernel's launches over one iteration move the sum of the
+    levels they process; the per-launch figure is that sum divided by the launches.
+    block_reach / reach_level: top-down; block_up: bottom-up (values, regrets and the infoset
+    update fused); value_level and infoset_update: the node engine's split of the bottom-up
+    terms.
     """
+    r = real
     D = len(counts) - 1
     fused = [l for l in range(D + 1) if reach_launch is not None and reach_launch[l] == 4]
-    reach = sum(24 * counts[l]["decision"] for l in range(1, D) if l not in fused)
-    values = sum(12 * counts[l + 1]["nodes"] + 8 * counts[l]["decision"] for l in range(D))
-    values += sum(12 * counts[l]["decision"] for l in fused)
-    infoset = sum(36 * c["q"] + 8 * c["infosets"] for c in counts)
+    reach = sum((8 + 4 * r) * counts[l]["decision"] for l in range(1, D) if l not in fused)
+    values = sum((8 + r) * counts[l + 1]["nodes"] + 2 * r * counts[l]["decision"]
+                 for l in range(D))
+    values += sum((8 + r) * counts[l]["decision"] for l in fused)
+    infoset = sum(9 * r * c["q"] + 2 * r * c["infosets"] for c in counts)
     return float({"block_reach": reach, "reach_level": reach, "block_up": values + infoset,
                   "value_level": values, "infoset_update": infoset}.get(kernel, 0.0))
+
+
+LAYOUT_FOR_COUNTS = ["level_offset", "node_player", "parent", "q_offset", "child_begin",
+                     "member_offset", "members"]
+
+
+def game_level_counts(game) -> list:
+    """level_counts of one game from its canonical layout, flattened on the host."""
+    from paper_2408_14778_amd.solver import host_layout
+    return level_counts(host_layout(game, LAYOUT_FOR_COUNTS))
+
+
+def forest_level_counts(game_list) -> list:
+    """level_counts of a batch's forest: level l of the forest is level l of every game, so the
+    counts add up level by level."""
+    total: list = []
+    for g in game_list:
+        for l, c in enumerate(game_level_counts(g)):
+            if l == len(total):
+                total.append({k: 0 for k in c})
+            for k, v in c.items():
+                total[l][k] += v
+    return total
 
 
 def measured_traffic(kernel: str):
@@ -128,20 +154,37 @@ def copy_bandwidth(mbytes: int = 1024, copies: int = 3, reps: int = 12) -> float
 
 
 def bench_batch(args, gl) -> dict:
-    """The batched workload: 512 subgames (seeds 100-611) as one forest, CFR+."""
+    """The batched workload: 512 subgames (seeds 100-611) as one forest, CFR+, with the
+    roofline of its dominant kernel measured as for the large game."""
     import torch
 
     from paper_2408_14778_amd import BatchSolver
 
     nodes = sum(g.n_nodes for g in gl)
+    t0 = time.perf_counter()
+    counts = forest_level_counts(gl)
+    log(f"forest level counts from the host layouts in {time.perf_counter() - t0:.1f}s")
     b = BatchSolver(gl, "cfr+")
     b.iterate(args.warmup)
     torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    assert b.stream == torch.cuda.current_stream()
     t0 = time.perf_counter()
+    ev0.record(b.stream)
     b.iterate(args.steps)
+    ev1.record(b.stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gpu_iter_s = ev0.elapsed_time(ev1) * 1e-3 / args.steps
     kt = b.iterate_timed(args.timed_kernel_steps)
+    rl = b.layout("reach_launch")
+    dom = max(kt, key=lambda k: kt[k][1])
+    launches, total_ms = kt[dom]
+    share = total_ms / sum(v[1] for v in kt.values())
+    avg_s = gpu_iter_s * share / (launches / args.timed_kernel_steps)
+    bytes_per_launch = algorithmic_bytes(dom, counts, rl) * args.timed_kernel_steps / launches
+    achieved = bytes_per_launch / avg_s / 1e9
+    iter_bytes = float(sum(algorithmic_bytes(k, counts, rl) for k in ("block_reach", "block_up")))
     br_s = []  # the first best response also writes the terminal values once
     for _ in range(3):
         t1 = time.perf_counter()
@@ -154,6 +197,12 @@ def bench_batch(args, gl) -> dict:
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "batch of 512 subgames (seeds 100-611), CFR+, one forest",
                        "nodes": nodes},
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": None, "bytes_per_launch": bytes_per_launch,
+                         "avg_launch_us": avg_s * 1e6, "iteration_us_events": gpu_iter_s * 1e6,
+                         "iteration_bytes": iter_bytes,
+                         "iteration_gbs": iter_bytes / gpu_iter_s / 1e9},
             "kernels": {k: {"launches": n, "avg_us": ms / n * 1e3} for k, (n, ms) in kt.items()},
             "exploitability": {"max": float(np.max(e["expl"])), "median": float(np.median(e["expl"])),
                                "seconds_first": br_s[0], "seconds": min(br_s[1:])}}
@@ -187,6 +236,18 @@ def warm_start_eval(game_list) -> dict:
     return res
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), else what platform reports."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(seconds_min: float = 10.0) -> dict:
     """The FP64 oracle (single-threaded Python) on the first 16 of the 156 deals: whole CFR+
     iterations until at least `seconds_min` of them have run (about 10-15 s)."""
@@ -204,11 +265,10 @@ def cpu_baseline(seconds_min: float = 10.0) -> dict:
         iters += 1
     dt = time.perf_counter() - t0
     return {"value": g.n_nodes * iters / dt, "unit": "node-updates/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"{iters} CFR+ iterations of the recursive FP64 oracle on the first 16 of "
-                      f"156 deals of the same game ({g.n_nodes} nodes); host "
-                      f"{platform.processor() or platform.machine()}, os.cpu_count()="
-                      f"{os.cpu_count()}"}
+                      f"156 deals of the same game ({g.n_nodes} nodes); host {cpu_model()}, "
+                      f"os.cpu_count()={os.cpu_count()}"}
 
 
 def main() -> int:
@@ -219,7 +279,11 @@ def main() -> int:
     ap.add_argument("--timed-kernel-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exploitability", action="store_true")
-    ap.add_argument("--engine", choices=["auto", "node"], default="auto")
+    ap.add_argument("--engine", choices=["auto", "packs", "node"], default="auto",
+                    help="auto: the public-block engine (the reported line); packs: the same with "
+                         "subtree packs; node: the breadth-first node engine")
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32",
+                    help="f64: the node engine in double precision (CFR_FLAG_FP64)")
     ap.add_argument("--variant", choices=["cfr+", "vanilla", "dcfr"], default="cfr+",
                     help="update rule of the large-game line (the reported workload is CFR+; "
                          "dcfr: discounted CFR with exponents 1.5, 0, 2)")
@@ -279,7 +343,9 @@ def main() -> int:
     g = games.large_game()
     log(f"game built: {g.n_nodes} nodes in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    s = Solver(g, args.variant, device="cuda:0", engine=args.engine, schedule=args.schedule)
+    s = Solver(g, args.variant, device="cuda:0", engine=args.engine, schedule=args.schedule,
+               precision=args.precision)
+    real = 8 if args.precision == "f64" else 4
     torch.cuda.synchronize()
     log(f"solver built (flatten + upload + graph capture) in {time.perf_counter() - t0:.1f}s; "
         f"workspace {s.info['workspace_bytes'] / 2**30:.2f} GiB")
@@ -331,11 +397,15 @@ def main() -> int:
     share = total_ms / sum(v[1] for v in kt.values())
     avg_s = gpu_iter_s * share / (launches / args.timed_kernel_steps)
     avg_direct_s = total_ms / launches * 1e-3
-    bytes_per_launch = algorithmic_bytes(dom, counts, rl) * passes * args.timed_kernel_steps / launches
+    bytes_per_launch = (algorithmic_bytes(dom, counts, rl, real) * passes * args.timed_kernel_steps /
+                        launches)
     achieved = bytes_per_launch / avg_s / 1e9
-    iter_bytes = passes * float(sum(algorithmic_bytes(k, counts, rl) for k in ("block_reach", "block_up")))
+    iter_bytes = passes * float(sum(algorithmic_bytes(k, counts, rl, real) for k in (
+        ("block_reach", "block_up") if s.info["engine"] == 1 else
+        ("reach_level", "value_level", "infoset_update"))))
     attainable = copy_bandwidth()
-    traffic = measured_traffic(dom)  # rocprofv3 HBM bytes per launch of the same kernel
+    # rocprofv3 HBM bytes per launch of the same kernel (taken on the default FP32 line)
+    traffic = measured_traffic(dom) if (args.precision, args.engine) == ("f32", "auto") else None
     log(f"plain copy: {attainable:.0f} GB/s")
     kernels = {k: {"launches": n, "avg_us": ms / n * 1e3,
                    "share": ms / sum(v[1] for v in kt.values())} for k, (n, ms) in kt.items()}
@@ -353,7 +423,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": "large poker game: 13 ranks, 3 rounds, fold/call/pot/all-in, "
                                "cap 3, stack 400, " + {
@@ -363,7 +433,8 @@ def main() -> int:
                                ", seed 2",
                    "nodes": g.n_nodes, "infosets": s.info["n_infosets"], "q": s.info["n_q"],
                    "depth": s.info["depth"],
-                   "engine": ["node", "public-block"][s.info["engine"]],
+                   "engine": ["node", "public-block"][s.info["engine"]] +
+                             (" with subtree packs" if args.engine == "packs" else ""),
                    "passes_per_iteration": passes},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

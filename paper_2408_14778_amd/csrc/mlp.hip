@@ -343,8 +343,9 @@ __global__ void __launch_bounds__(256) k_gemm_narrow(int M, int N, int K,
 }
 
 // The whole forward pass in one kernel (inference): one wavefront per 32 rows, its rows' input,
-// then its hidden activations, in a private LDS region; the weights come from their transposed
-// BF16 copies (k-contiguous, L2-resident), one 16-byte load per lane per MFMA B fragment.
+// then its hidden activations, in a private LDS region; the hidden layers' weights come from
+// BF16 copies packed in MFMA fragment order (L2-resident), one coalesced kilobyte per B
+// fragment, the last layer's from its transposed copy.
 // Layer 1: A fragments from the staged input rows, H / 32 output tiles of 32 x 32 in FP32
 // accumulators; bias and ReLU, rounded to BF16 into LDS (over the input, which is no longer
 // needed). Layer 2: the same from the first hidden layer, written back over it. Layer 3 as
@@ -354,12 +355,44 @@ __global__ void __launch_bounds__(256) k_gemm_narrow(int M, int N, int K,
 // the same order of the last layer's sums. F: a multiple of 16 up to kFusedMaxF; A <= kNarrow.
 constexpr int kFusedMaxF = 128;
 
+// One layer of a wavefront's 32 rows: acc[t] = sum over k-steps of A(k) . B_t(k), A fragments
+// at a[k] (LDS), K a multiple of 16. B: the layer's weights packed in fragment order (see
+// launch_pack_fragments): fragment (t, k-step s) is 64 lanes x 8 consecutive elements at
+// wp[((t * K / 16 + s) * 64 + lane) * 8], so that each load instruction reads one contiguous
+// kilobyte. The B fragments of the next k-step are loaded before the multiplies of the
+// current one.
+template <int NT>
+__device__ __forceinline__ void wave_layer(const __bf16* a, const __bf16* __restrict__ wp, int K,
+                                           int lane, floatx16 (&acc)[NT]) {
+    const int KS = K / 16;
+    const __bf16* w = wp + lane * 8;
+    bf16x8 fb[NT], nb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        acc[t] = floatx16{};
+        fb[t] = *reinterpret_cast<const bf16x8*>(w + static_cast<int64_t>(t) * KS * 512);
+    }
+#pragma unroll 1
+    for (int s = 0; s < KS; ++s) {
+        const int sn = s + 1 < KS ? s + 1 : s;  // the last step reloads itself, unused
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            nb[t] = *reinterpret_cast<const bf16x8*>(w + (static_cast<int64_t>(t) * KS + sn) * 512);
+        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(a + 16 * s);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb[t], acc[t], 0, 0, 0);
+            fb[t] = nb[t];
+        }
+    }
+}
+
 template <int H>
 __global__ void __launch_bounds__(64, 2) k_mlp_forward(int M, int F, int A,
                                                     const __bf16* __restrict__ X,
-                                                    const __bf16* __restrict__ W1T,
+                                                    const __bf16* __restrict__ W1P,
                                                     const float* __restrict__ b1,
-                                                    const __bf16* __restrict__ W2T,
+                                                    const __bf16* __restrict__ W2P,
                                                     const float* __restrict__ b2,
                                                     const __bf16* __restrict__ W3T,
                                                     const float* __restrict__ b3,
@@ -380,17 +413,7 @@ __global__ void __launch_bounds__(64, 2) k_mlp_forward(int M, int F, int A,
     __syncthreads();
     floatx16 acc[NT];
     // layer 1: [32 x F] . W1 -> [32 x H]
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = floatx16{};
-    for (int k = 0; k < F; k += 16) {
-        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&T[r][k + 8 * half]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x8 fb = *reinterpret_cast<const bf16x8*>(
-                W1T + static_cast<int64_t>(t * 32 + r) * F + k + 8 * half);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[t], 0, 0, 0);
-        }
-    }
+    wave_layer<NT>(&T[r][8 * half], W1P, F, lane, acc);
     __syncthreads();  // every lane's reads of the input rows are done before they are overwritten
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -403,18 +426,7 @@ __global__ void __launch_bounds__(64, 2) k_mlp_forward(int M, int F, int A,
     }
     __syncthreads();
     // layer 2: [32 x H] . W2 -> [32 x H]
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = floatx16{};
-#pragma unroll 1
-    for (int k = 0; k < H; k += 16) {
-        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&T[r][k + 8 * half]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x8 fb = *reinterpret_cast<const bf16x8*>(
-                W2T + static_cast<int64_t>(t * 32 + r) * H + k + 8 * half);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc[t], 0, 0, 0);
-        }
-    }
+    wave_layer<NT>(&T[r][8 * half], W2P, H, lane, acc);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -468,6 +480,18 @@ __global__ void __launch_bounds__(64, 2) k_mlp_forward(int M, int F, int A,
                 if (n < A) Z[static_cast<int64_t>(m0 + row) * A + n] = z[n] + b3[n];
         }
     }
+}
+
+// Packs the K x H weight matrix W (given transposed, WT[j][k]) in MFMA fragment order: element
+// j8 of lane l of fragment (t, s) is W[16 s + 8 (l / 32) + j8][32 t + l % 32].
+__global__ void k_pack_fragments(int K, int H, const __bf16* __restrict__ WT,
+                                 __bf16* __restrict__ dst) {
+    const int64_t i = gid();
+    if (i >= static_cast<int64_t>(K) * H) return;
+    const int j8 = static_cast<int>(i % 8), l = static_cast<int>((i / 8) % 64);
+    const int64_t f = i / 512;
+    const int KS = K / 16, s = static_cast<int>(f % KS), t = static_cast<int>(f / KS);
+    dst[i] = WT[static_cast<int64_t>(32 * t + l % 32) * K + 16 * s + 8 * (l / 32) + j8];
 }
 
 // dst[c][r] = src[r][c] for a rows x cols BF16 matrix (the transposed weight copies).
@@ -752,15 +776,15 @@ void launch_softmax_xent(int B, int A, const float* Z, const float* target, cons
                        mask, static_cast<__bf16*>(dZ), loss);
 }
 
-bool launch_mlp_forward(int M, int F, int H, int A, const void* X, const void* W1T, const float* b1,
-                        const void* W2T, const float* b2, const void* W3T, const float* b3,
+bool launch_mlp_forward(int M, int F, int H, int A, const void* X, const void* W1P, const float* b1,
+                        const void* W2P, const float* b2, const void* W3T, const float* b3,
                         float* Z, hipStream_t st) {
     if (F % 16 != 0 || F > kFusedMaxF || A > kNarrow ||
         (reinterpret_cast<uintptr_t>(X) % 16) != 0)
         return false;
     const auto* x = static_cast<const __bf16*>(X);
-    const auto* w1 = static_cast<const __bf16*>(W1T);
-    const auto* w2 = static_cast<const __bf16*>(W2T);
+    const auto* w1 = static_cast<const __bf16*>(W1P);
+    const auto* w2 = static_cast<const __bf16*>(W2P);
     const auto* w3 = static_cast<const __bf16*>(W3T);
     const dim3 grid((M + 31) / 32);
     switch (H) {
@@ -779,6 +803,13 @@ bool launch_mlp_forward(int M, int F, int H, int A, const void* X, const void* W
         default:
             return false;
     }
+}
+
+void launch_pack_fragments(int K, int H, const void* WT, void* dst, hipStream_t st) {
+    const int64_t n = int64_t{K} * H;
+    if (n > 0 && K % 16 == 0 && H % 32 == 0)
+        hipLaunchKernelGGL(k_pack_fragments, dim3(blocks_for(n, 256)), dim3(256), 0, st, K, H,
+                           static_cast<const __bf16*>(WT), static_cast<__bf16*>(dst));
 }
 
 void launch_transpose_bf16(int rows, int cols, const void* src, void* dst, hipStream_t st) {

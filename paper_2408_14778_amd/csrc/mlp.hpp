@@ -41,12 +41,16 @@ void launch_gemm(int M, int N, int K, const void* A, int64_t a_i, int64_t a_k, c
 void launch_softmax_xent(int B, int A, const float* Z, const float* target, const float* mask,
                          void* dZ, float* loss, hipStream_t st);
 void launch_colsum(int rows, int cols, const void* G, float* out, hipStream_t st, float* part);
-// The three layers in one kernel from the transposed BF16 weights (F a multiple of 16 up to 128,
-// H 64, 128 or 256, A <= 8, X 16-byte aligned); false (nothing launched) for other shapes. The
-// logits equal those of the three per-layer launch_gemm calls bit for bit.
-bool launch_mlp_forward(int M, int F, int H, int A, const void* X, const void* W1T, const float* b1,
-                        const void* W2T, const float* b2, const void* W3T, const float* b3,
+// The three layers in one kernel (F a multiple of 16 up to 128, H 64, 128 or 256, A <= 8, X
+// 16-byte aligned): W1P, W2P the hidden layers' weights packed by launch_pack_fragments, W3T the
+// last layer's transposed; false (nothing launched) for other shapes. The logits equal those of
+// the three per-layer launch_gemm calls bit for bit.
+bool launch_mlp_forward(int M, int F, int H, int A, const void* X, const void* W1P, const float* b1,
+                        const void* W2P, const float* b2, const void* W3T, const float* b3,
                         float* Z, hipStream_t st);
+// The K x H weights W, given transposed (WT, H x K), packed in MFMA B-fragment order for
+// launch_mlp_forward (K a multiple of 16, H of 32; otherwise nothing is written).
+void launch_pack_fragments(int K, int H, const void* WT, void* dst, hipStream_t st);
 // dst = src transposed, src a rows x cols BF16 matrix
 void launch_transpose_bf16(int rows, int cols, const void* src, void* dst, hipStream_t st);
 void launch_adam(int64_t n, float* w, const float* g, float* m, float* v, void* wb, float lr,

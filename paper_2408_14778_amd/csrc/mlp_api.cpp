@@ -36,6 +36,7 @@ size_t layout(cfr_mlp& n, void* base, int32_t F, int32_t H, int32_t A, int32_t m
     n.v = static_cast<float*>(take(P * 4));
     n.wb = static_cast<__bf16*>(take(P * 2));
     n.wbT = static_cast<__bf16*>(take(P * 2));
+    n.wbP = static_cast<__bf16*>(take(P * 2));
     n.A1 = static_cast<__bf16*>(take(int64_t{maxB} * H * 2));
     n.A2 = static_cast<__bf16*>(take(int64_t{maxB} * H * 2));
     n.dZ2 = static_cast<__bf16*>(take(int64_t{maxB} * H * 2));
@@ -82,6 +83,8 @@ void transpose_weights(cfr_mlp* n) {
     cfr::launch_transpose_bf16(n->F, n->H, n->wb + o[0], n->wbT + t[0], n->st);
     cfr::launch_transpose_bf16(n->H, n->H, n->wb + o[2], n->wbT + t[1], n->st);
     cfr::launch_transpose_bf16(n->H, n->A, n->wb + o[4], n->wbT + t[2], n->st);
+    cfr::launch_pack_fragments(n->F, n->H, n->wbT + t[0], n->wbP, n->st);
+    cfr::launch_pack_fragments(n->H, n->H, n->wbT + t[1], n->wbP + int64_t{n->F} * n->H, n->st);
 }
 
 }  // namespace
@@ -157,9 +160,9 @@ int cfr_mlp_forward(cfr_mlp* n, const void* x, int32_t batch, float* logits) {
     int64_t o[7], t[3];
     offsets(n->F, n->H, n->A, o);
     cfr::transposed_offsets(n->F, n->H, n->A, t);
-    if (!cfr::launch_mlp_forward(batch, n->F, n->H, n->A, x, n->wbT + t[0], n->w + o[1],
-                                 n->wbT + t[1], n->w + o[3], n->wbT + t[2], n->w + o[5], logits,
-                                 n->st)) {
+    if (!cfr::launch_mlp_forward(batch, n->F, n->H, n->A, x, n->wbP, n->w + o[1],
+                                 n->wbP + int64_t{n->F} * n->H, n->w + o[3], n->wbT + t[2],
+                                 n->w + o[5], logits, n->st)) {
         forward(n, x, batch);
         MLP_TRY(hipMemcpyAsync(logits, n->Z3, int64_t{batch} * n->A * 4, hipMemcpyDeviceToDevice,
                                n->st),

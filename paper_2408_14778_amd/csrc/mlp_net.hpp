@@ -17,6 +17,8 @@ struct cfr_mlp {
     // the weight matrices transposed, [W1^T (H x F) | W2^T (H x H) | W3^T (A x H)], refreshed
     // with wb: the forward pass reads both GEMM operands along k
     __bf16* wbT;
+    // W1 and W2 packed in MFMA fragment order for the fused forward pass, [W1 | W2]
+    __bf16* wbP;
     // activations
     __bf16 *A1, *A2, *dZ3, *dZ2, *dZ1;
     float *Z3, *loss;

@@ -32,3 +32,27 @@ def test_streaming_model_of_the_large_game(large_game):
     # the node engine's split of the bottom-up terms adds up to the fused kernel's
     assert np.isclose(bench.algorithmic_bytes("value_level", counts) +
                       bench.algorithmic_bytes("infoset_update", counts), up)
+    # FP64 values: the top-down term scales as 8 + 4r (24 -> 40 B per internal node), the pair
+    # and infoset terms as r, the per-child term as 8 + r
+    r64 = bench.algorithmic_bytes("block_reach", counts, rl, 8)
+    assert r64 * 24 == bench.algorithmic_bytes("block_reach", counts, rl) * 40
+    inf32 = bench.algorithmic_bytes("infoset_update", counts)
+    assert np.isclose(bench.algorithmic_bytes("infoset_update", counts, None, 8), 2 * inf32)
+    child = sum(c["nodes"] for c in counts[1:])
+    dec = sum(c["decision"] for c in counts[:-1])
+    assert np.isclose(bench.algorithmic_bytes("value_level", counts, None, 8),
+                      16 * child + 16 * dec)
+
+
+def test_forest_level_counts_add_up():
+    """The batch roofline's per-level counts of a forest are the games' counts summed level by
+    level (deeper games past the others' depth)."""
+    import games
+    gl = [games.subgame(s) for s in (101, 102, 103)]
+    each = [bench.game_level_counts(g) for g in gl]
+    forest = bench.forest_level_counts(gl)
+    assert len(forest) == max(len(c) for c in each)
+    for key in ("nodes", "decision", "infosets", "q", "player_children"):
+        for l in range(len(forest)):
+            assert forest[l][key] == sum(c[l][key] for c in each if l < len(c)), (key, l)
+    assert sum(c["nodes"] for c in forest) == sum(g.n_nodes for g in gl)
