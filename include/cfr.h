@@ -240,6 +240,32 @@ int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes)
 /* The same for a solver built with CFR_FLAG_FP64, in double precision. */
 int cfr_get_node_values_f64(cfr_solver* s, double* u1, double* reach, int64_t n_nodes);
 
+/* Subtree-partitioned, out-of-core iteration (the memory relief the paper's discussion, Section 5,
+ * proposes: the iteration computed over root-to-leaf partitions of the tree instead of all of it
+ * at once). Levels 0 .. cut_level stay resident on the device; the subtrees hanging from the
+ * level-cut nodes are grouped, in canonical order, into partitions of at most max_window_nodes
+ * nodes below the cut (a larger subtree is a partition of its own), kept in pinned host memory
+ * and streamed through one device window every iteration: the resident top-down pass, then per
+ * partition its window copied in, its top-down and bottom-up passes (values, regrets and own
+ * reaches added into the resident per-pair accumulators) and the bottom-up of its level-cut
+ * nodes; the resident bottom-up; the infoset update. The arithmetic is the node engine's (FP32,
+ * or FP64 with CFR_FLAG_FP64); device memory holds the resident levels, one window and the
+ * per-pair state. cut_level in 1 .. depth - 1, max_window_nodes >= 1 (CFR_EINVAL otherwise);
+ * flags: CFR_FLAG_ALTERNATING, CFR_FLAG_FP64 (CFR_FLAG_NO_GRAPH and CFR_FLAG_NODE_ENGINE are
+ * implied; others CFR_EINVAL).
+ * cfr_plan_partitioned reports the sizes as cfr_plan does (workspace_bytes: this solver's device
+ * workspace), the number of partitions and the pinned host bytes the build allocates (either
+ * pointer may be NULL). The solver takes cfr_iterate, cfr_iterate_timed (no per-kernel times),
+ * the strategy and state calls (float or _f64 by precision) and cfr_destroy; cfr_exploitability,
+ * cfr_get_node_values and the layout exports return CFR_EINVAL (the device never holds the whole
+ * tree: move the state into an in-core solver of the same game to evaluate it). */
+int cfr_plan_partitioned(const cfr_game* game, const cfr_config* config, int32_t cut_level,
+                         int64_t max_window_nodes, cfr_plan_info* out, int32_t* n_partitions,
+                         int64_t* host_bytes);
+int cfr_build_partitioned(const cfr_game* game, const cfr_config* config, int32_t cut_level,
+                          int64_t max_window_nodes, void* workspace, size_t bytes, void* stream,
+                          cfr_solver** out);
+
 /* Host-only flattening, for checking the canonical layout without a GPU: build the layout
  * of `game` on the host (validation as in cfr_plan), then read arrays by the names listed for
  * cfr_get_layout. For level-pure games the public-block execution plan is built too (with

@@ -132,6 +132,13 @@ SIGNATURES = {
                                        ctypes.POINTER(CfrConfig), ctypes.c_void_p, ctypes.c_size_t,
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "cfr_exploitability_batch": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int32]),
+    "cfr_plan_partitioned": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.POINTER(CfrConfig),
+                                            ctypes.c_int32, ctypes.c_int64,
+                                            ctypes.POINTER(CfrPlanInfo), _i32p, _i64p]),
+    "cfr_build_partitioned": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.POINTER(CfrConfig),
+                                             ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p,
+                                             ctypes.POINTER(ctypes.c_void_p)]),
     "cfr_last_error": (ctypes.c_char_p, []),
 }
 
@@ -146,6 +153,13 @@ def load():
             raise ImportError(
                 f"{LIB_PATH} is missing: build it with paper_2408_14778_amd.build.build() "
                 "(hipcc, gfx950). There is no fallback path.")
+        # torch's HIP runtime first: the library then binds to that same runtime (both carry
+        # the soname libamdhip64.so.7) instead of loading a second one that the device memory
+        # torch allocates is foreign to
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -8,8 +8,8 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcfr_mi355x.so")
-SOURCES = ["flatten.cpp", "xplan.cpp", "host_layout.cpp", "solver.cpp", "mlp_api.cpp", "kernels.hip", "xkernels.hip",
-           "mlp.hip", "mlp_noalloc.hip"]
+SOURCES = ["flatten.cpp", "xplan.cpp", "host_layout.cpp", "partition_plan.cpp", "partition.cpp",
+           "solver.cpp", "mlp_api.cpp", "kernels.hip", "xkernels.hip", "mlp.hip", "mlp_noalloc.hip"]
 
 # Packed-fp32 instructions stay off: plain float code only.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

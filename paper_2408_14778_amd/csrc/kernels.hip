@@ -384,6 +384,30 @@ void launch_iteration(const DevT<F>& d, const int32_t* lo, const UpdateRule& rul
 }
 
 template <class F>
+void launch_reach_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st) {
+    if (hi > lo)
+        hipLaunchKernelGGL(k_reach_level<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo, hi,
+                           d.N, d.parent, d.node_player, d.node_edge, d.prob, d.reach);
+}
+
+template <class F>
+void launch_value_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st) {
+    if (hi > lo)
+        hipLaunchKernelGGL(k_value_level<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo, hi,
+                           d.N, d.child_begin, d.node_player, d.node_infoset, d.node_edge, d.prob,
+                           d.value, d.reach, d.rtilde, d.pibar);
+}
+
+template <class F>
+void launch_infoset_pass(const DevT<F>& d, const UpdateRule& rule, hipStream_t st) {
+    if (d.Hp > 0)
+        hipLaunchKernelGGL(k_infoset_update<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
+                           d.q_offset, d.infoset_player, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T,
+                           rule);
+    if (rule.count) hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, d.T);
+}
+
+template <class F>
 void launch_average(const DevT<F>& d, hipStream_t st) {
     if (d.Hp > 0)
         hipLaunchKernelGGL(k_average<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
@@ -438,6 +462,9 @@ void launch_gather_q(const DevT<F>& d, const F* src, F* dst, hipStream_t st) {
     template void launch_iteration<F>(const DevT<F>&, const int32_t*, const UpdateRule&,       \
                                       hipStream_t, LaunchTimer*);                              \
     template void launch_average<F>(const DevT<F>&, hipStream_t);                              \
+    template void launch_reach_range<F>(const DevT<F>&, int32_t, int32_t, hipStream_t);        \
+    template void launch_value_range<F>(const DevT<F>&, int32_t, int32_t, hipStream_t);        \
+    template void launch_infoset_pass<F>(const DevT<F>&, const UpdateRule&, hipStream_t);      \
     template void launch_best_response<F>(const DevT<F>&, const int32_t*, const int32_t*, int, \
                                           hipStream_t);                                        \
     template void launch_scatter_q<F>(const DevT<F>&, const F*, F*, hipStream_t);              \

@@ -117,6 +117,15 @@ __device__ __forceinline__ void dcfr_discounts(const UpdateRule& u, double t, do
 template <class F>
 void launch_iteration(const DevT<F>& d, const int32_t* level_offset_host, const UpdateRule& rule,
                       hipStream_t st, LaunchTimer* timer = nullptr);
+// The parts of one iteration on a node range [lo, hi) of one level (the partitioned iteration
+// composes them): top-down reach, bottom-up values with the regret and own-reach accumulation;
+// then the infoset pass over every infoset (and T += 1 if rule.count).
+template <class F>
+void launch_reach_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st);
+template <class F>
+void launch_value_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st);
+template <class F>
+void launch_infoset_pass(const DevT<F>& d, const UpdateRule& rule, hipStream_t st);
 // Average strategy into d.avgprob (canonical order; chance tail copied at reset).
 template <class F>
 void launch_average(const DevT<F>& d, hipStream_t st);

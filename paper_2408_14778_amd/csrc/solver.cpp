@@ -3,9 +3,11 @@
 
 #include <algorithm>
 #include <atomic>
+#include <memory>
 #include <cmath>
 #include <cstring>
 #include <thread>
+#include <type_traits>
 #include <utility>
 #include <string>
 #include <vector>
@@ -16,6 +18,7 @@
 #include "host_plan.hpp"
 #include "mlp.hpp"
 #include "kernels.hpp"
+#include "partition.hpp"
 #include "xkernels.hpp"
 #include "xplan.hpp"
 
@@ -26,6 +29,15 @@ struct cfr_solver {
     cfr::Dev64 dev64{};  // fp64: the node engine's arrays in double precision (dev keeps the
                          // structure arrays, its real-valued pointers are null)
     bool fp64 = false;
+    // subtree-partitioned, out-of-core solver (cfr_build_partitioned): the partitions' pinned
+    // host windows (one of the two, by precision)
+    std::unique_ptr<cfr::PartDev<float>> part32;
+    std::unique_ptr<cfr::PartDev<double>> part64;
+    bool partitioned() const { return part32 != nullptr || part64 != nullptr; }
+    ~cfr_solver() {
+        if (part32) part32->release();
+        if (part64) part64->release();
+    }
     cfr::XDev xdev{};
     int engine = ENGINE_NODE;
     int32_t n_games = 1;       // > 1: a batch (forest); canonical exports are unavailable
@@ -270,7 +282,11 @@ int upload(T* dst, const std::vector<T>& src, hipStream_t st) {
 
 void launch_one_iteration(cfr_solver* s, hipStream_t st, cfr::LaunchTimer* timer) {
     auto pass = [&](const cfr::UpdateRule& r) {
-        if (s->engine == ENGINE_BLOCK)
+        if (s->part32)
+            cfr::launch_partitioned_pass(s->dev, *s->part32, r, st);
+        else if (s->part64)
+            cfr::launch_partitioned_pass(s->dev64, *s->part64, r, st);
+        else if (s->engine == ENGINE_BLOCK)
             cfr::launch_x_iteration(s->xdev, r, st, timer);
         else if (s->fp64)
             cfr::launch_iteration(s->dev64, s->level_offset.data(), r, st, timer);
@@ -726,6 +742,188 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     return CFR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Flags a partitioned solver takes: the schedule and the precision (it always enqueues its
+// kernels and copies directly and runs the node engine's kernels).
+int check_partitioned_config(const cfr_config& c) {
+    if (const int rc = check_config(&c); rc != CFR_OK) return rc;
+    if (c.flags & (CFR_FLAG_SUBTREE_PACKS | CFR_FLAG_KEEP_NODE_VALUES))
+        return set_err(CFR_EINVAL, "a partitioned solver takes CFR_FLAG_ALTERNATING, CFR_FLAG_FP64, "
+                                   "CFR_FLAG_NO_GRAPH and CFR_FLAG_NODE_ENGINE only");
+    return CFR_OK;
+}
+
+// Device sizes of a partitioned solver: the resident levels and one window, every pair.
+Sizes partitioned_sizes(const cfr::Layout& L, const cfr::PartPlan& P, bool fp64) {
+    Sizes z;
+    z.N = P.base + P.window;
+    z.Hp = L.Hp; z.Qp = L.Qp; z.H0 = L.H0; z.Q0 = L.Q0; z.M = 0;
+    z.terminals = 0; z.C = 0; z.L = z.N; z.D = L.D; z.max_actions = L.max_actions;
+    z.engine = ENGINE_NODE;
+    z.fp64 = fp64;
+    return z;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfr_plan_partitioned(const cfr_game* game, const cfr_config* config, int32_t cut_level,
+                         int64_t max_window_nodes, cfr_plan_info* out, int32_t* n_partitions,
+                         int64_t* host_bytes) {
+    if (game == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    cfr_config cfg{};
+    cfg.variant = CFR_VANILLA;
+    cfg.averaging = CFR_AVG_DEFAULT;
+    if (config != nullptr) cfg = *config;
+    if (const int rc = check_partitioned_config(cfg); rc != CFR_OK) return rc;
+    const bool fp64 = (cfg.flags & CFR_FLAG_FP64) != 0;
+    cfr::Layout L;
+    std::string err;
+    int rc = cfr::flatten(*game, L, err, fp64);
+    if (rc != CFR_OK) return set_err(rc, err);
+    cfr::PartPlan P;
+    if ((rc = cfr::plan_partitions(L, cut_level, max_window_nodes, P, err)) != CFR_OK)
+        return set_err(rc, err);
+    const Sizes z = partitioned_sizes(L, P, fp64);
+    cfr::Dev d{};
+    cfr::Dev64 d64{};
+    cfr::XDev x{};
+    std::memset(out, 0, sizeof *out);
+    out->n_nodes = L.N;
+    out->n_terminals = L.n_terminals;
+    out->n_infosets = L.Hp;
+    out->n_q = L.Qp;
+    out->n_chance_infosets = L.H0;
+    out->n_chance_q = L.Q0;
+    out->max_actions = L.max_actions;
+    out->depth = L.D;
+    out->level_pure = L.level_pure ? 1 : 0;
+    out->engine = ENGINE_NODE;
+    out->workspace_bytes = static_cast<int64_t>(carve(d, d64, x, nullptr, z));
+    if (n_partitions != nullptr) *n_partitions = P.parts;
+    if (host_bytes != nullptr)
+        *host_bytes = P.total * (4 * 3 + 1 + (fp64 ? 8 : 4)) + (P.total + P.parts) * 4 +
+                      static_cast<int64_t>(P.patch.size()) * 4;
+    return CFR_OK;
+}
+
+int cfr_build_partitioned(const cfr_game* game, const cfr_config* config, int32_t cut_level,
+                          int64_t max_window_nodes, void* workspace, size_t bytes, void* stream,
+                          cfr_solver** out) {
+    if (game == nullptr || workspace == nullptr || out == nullptr)
+        return set_err(CFR_EINVAL, "null argument");
+    cfr_config cfg{};
+    cfg.variant = CFR_VANILLA;
+    cfg.averaging = CFR_AVG_DEFAULT;
+    if (config != nullptr) cfg = *config;
+    if (const int rc = check_partitioned_config(cfg); rc != CFR_OK) return rc;
+    const bool fp64 = (cfg.flags & CFR_FLAG_FP64) != 0;
+    cfr::Layout L;
+    std::string err;
+    int rc = cfr::flatten(*game, L, err, fp64);
+    if (rc != CFR_OK) return set_err(rc, err);
+    cfr::PartPlan P;
+    if ((rc = cfr::plan_partitions(L, cut_level, max_window_nodes, P, err)) != CFR_OK)
+        return set_err(rc, err);
+    const Sizes z = partitioned_sizes(L, P, fp64);
+    cfr::Dev d{};
+    cfr::Dev64 d64{};
+    cfr::XDev x{};
+    const size_t need = carve(d, d64, x, nullptr, z);
+    if (bytes < need)
+        return set_err(CFR_ENOMEM, "workspace has " + std::to_string(bytes) + " bytes, needs " +
+                                       std::to_string(need));
+    carve(d, d64, x, workspace, z);
+    auto* s = new cfr_solver();
+    s->dev = d;
+    s->dev64 = d64;
+    s->fp64 = fp64;
+    s->engine = ENGINE_NODE;
+    s->canonical = false;  // the device holds the resident levels and a window, not the tree
+    s->rule = rule_of(cfg);
+    s->alternating = (cfg.flags & CFR_FLAG_ALTERNATING) != 0;
+    s->use_graph = false;  // each pass streams host memory through the window
+    s->level_pure = L.level_pure;
+    s->n_terminals = L.n_terminals;
+    s->max_actions = L.max_actions;
+    s->stream = static_cast<hipStream_t>(stream);
+    s->level_offset = L.level_offset;
+    hipStream_t st = s->stream;
+    const int64_t base = P.base, Nloc = z.N;
+    // the resident levels 0 .. cut keep their canonical ids; the window's ids start at base
+    auto head = [&](const auto& v, int64_t n) {
+        using T = typename std::decay_t<decltype(v)>::value_type;
+        return std::vector<T>(v.begin(), v.begin() + n);
+    };
+    std::vector<float> prob_tail(fp64 ? 0 : L.Qp + L.Q0, 0.0f);
+    std::vector<double> prob_tail64(fp64 ? L.Qp + L.Q0 : 0, 0.0);
+    for (int64_t i = 0; i < L.Q0; ++i) {
+        if (fp64) prob_tail64[L.Qp + i] = L.chance_prob64[i];
+        else prob_tail[L.Qp + i] = L.chance_prob[i];
+    }
+    // (named: the copies must find them alive until the synchronisation below)
+    const std::vector<int32_t> cb = head(L.child_begin, base + 1), par = head(L.parent, base),
+                               inf = head(L.node_infoset, base), edg = head(L.node_edge, base);
+    std::vector<int8_t> player(Nloc, -1);
+    std::copy(L.node_player.begin(), L.node_player.begin() + base, player.begin());
+    std::vector<double> pay64(fp64 ? Nloc : 0, 0.0);
+    std::vector<float> pay32(fp64 ? 0 : Nloc, 0.0f);
+    if (fp64) std::copy(L.payoff64.begin(), L.payoff64.begin() + base, pay64.begin());
+    else std::copy(L.payoff.begin(), L.payoff.begin() + base, pay32.begin());
+    if ((rc = upload(d.parent, par, st)) || (rc = upload(d.child_begin, cb, st)) ||
+        (rc = upload(d.node_player, player, st)) || (rc = upload(d.node_infoset, inf, st)) ||
+        (rc = upload(d.node_edge, edg, st)) ||
+        (rc = upload(d.level_offset, L.level_offset, st)) ||
+        (rc = upload(d.infoset_id, L.infoset_id, st)) ||
+        (rc = upload(d.infoset_player, L.infoset_player, st)) ||
+        (rc = upload(d.q_offset, L.q_offset, st)) || (rc = upload(d.chance_id, L.chance_id, st)) ||
+        (rc = upload(d.cq_offset, L.cq_offset, st)) || (rc = upload(d.q_input, L.q_input, st))) {
+        discard(s);
+        return rc;
+    }
+    if (fp64) {
+        if ((rc = upload(d64.payoff, pay64, st)) || (rc = upload(d64.prob, prob_tail64, st))) {
+            discard(s);
+            return rc;
+        }
+        s->part64 = std::make_unique<cfr::PartDev<double>>();
+        s->part64->plan = std::move(P);
+        s->part64->level_offset = L.level_offset;
+        rc = s->part64->upload(st);
+    } else {
+        if ((rc = upload(d.payoff, pay32, st)) || (rc = upload(d.prob, prob_tail, st))) {
+            discard(s);
+            return rc;
+        }
+        s->part32 = std::make_unique<cfr::PartDev<float>>();
+        s->part32->plan = std::move(P);
+        s->part32->level_offset = L.level_offset;
+        rc = s->part32->upload(st);
+    }
+    if (rc != 0) {
+        discard(s);
+        return set_err(CFR_ENOMEM, "pinned host memory for the partition windows");
+    }
+    if (fp64) cfr::launch_reset(d64, st, true);
+    else cfr::launch_reset(d, st, true);
+    if ((rc = check_hip("reset")) != CFR_OK) {
+        discard(s);
+        return rc;
+    }
+    // host vectors are released when L goes out of scope: wait for the copies first
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        discard(s);
+        return hip_err(e, "build synchronise");
+    }
+    *out = s;
+    return CFR_OK;
+}
+
 int cfr_iterate(cfr_solver* s, int32_t n) {
     if (s == nullptr || n < 0) return set_err(CFR_EINVAL, "bad solver or count");
     for (int32_t i = 0; i < n; ++i) {
@@ -999,6 +1197,9 @@ int cfr_current_strategy_f64(cfr_solver* s, double* out, int64_t n_q, int out_on
 int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]) {
     if (s == nullptr || expl == nullptr) return set_err(CFR_EINVAL, "null argument");
     if (s->n_games != 1) return set_err(CFR_EINVAL, "a batch reports cfr_exploitability_batch");
+    if (s->partitioned())
+        return set_err(CFR_EINVAL, "a partitioned solver keeps no whole tree on the device: read its "
+                                   "state (cfr_get_state) into an in-core solver of the same game");
     if (!s->level_pure) return set_err(CFR_ELEVEL, "an infoset spans several levels");
     if (s->fp64) {
         cfr::launch_average(s->dev64, s->stream);
@@ -1055,6 +1256,7 @@ int cfr_set_state_f64(cfr_solver* s, int64_t T, const double* R, const double* S
 int64_t cfr_layout_bytes(cfr_solver* s, const char* name) {
     if (s == nullptr || name == nullptr) return CFR_EINVAL;
     const std::string n(name);
+    if (s->partitioned()) return CFR_EINVAL;  // no canonical arrays on the device
     if (n == "reach_launch") return (launch_depth(s) + 1) * 4;  // batches too
     if (!s->canonical) return CFR_EINVAL;
     const cfr::Dev& d = s->dev;

@@ -350,6 +350,72 @@ class Solver:
             pass
 
 
+class PartitionedSolver(Solver):
+    """The subtree-partitioned, out-of-core iteration (cfr_build_partitioned): levels
+    0 .. cut_level resident on the device, the subtrees below grouped into partitions of at most
+    max_window_nodes nodes held in pinned host memory and streamed through one device window per
+    iteration. Same update rules, schedules and precisions as Solver (node engine arithmetic);
+    exploitability and node values are not available (the device never holds the whole tree):
+    move the state into a Solver of the same game to evaluate it."""
+
+    def __init__(self, game, variant: str = "vanilla", cut_level: int = 1,
+                 max_window_nodes: int = 1 << 20, averaging=None, device: str = "cuda",
+                 stream=None, dcfr=None, schedule: str = "simultaneous", precision: str = "f32"):
+        import torch
+
+        self._lib = N.load()
+        self.variant = variant
+        self.precision = precision
+        args = GameArgs(game)
+        cfg = make_config(variant, averaging, False, "node", dcfr, schedule, False, precision)
+        info = N.CfrPlanInfo()
+        parts = ctypes.c_int32()
+        host_bytes = ctypes.c_int64()
+        N.check(self._lib.cfr_plan_partitioned(ctypes.byref(args.struct), ctypes.byref(cfg),
+                                               int(cut_level), int(max_window_nodes),
+                                               ctypes.byref(info), ctypes.byref(parts),
+                                               ctypes.byref(host_bytes)))
+        self.info = {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
+        self.n_partitions = int(parts.value)
+        self.host_bytes = int(host_bytes.value)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8,
+                                     device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        N.check(self._lib.cfr_build_partitioned(ctypes.byref(args.struct), ctypes.byref(cfg),
+                                                int(cut_level), int(max_window_nodes),
+                                                ctypes.c_void_p(self.workspace.data_ptr()),
+                                                ctypes.c_size_t(int(info.workspace_bytes)),
+                                                ctypes.c_void_p(self.stream.cuda_stream),
+                                                ctypes.byref(handle)))
+        self._h = handle
+        self.n_q = int(info.n_q)
+        self.n_nodes = int(info.n_nodes)
+        self._f64 = precision == "f64"
+        self._rdt = np.float64 if self._f64 else np.float32
+        self._sfx = "_f64" if self._f64 else ""
+
+
+def plan_partitioned(game, cut_level: int, max_window_nodes: int, variant: str = "vanilla",
+                     precision: str = "f32", schedule: str = "simultaneous") -> dict:
+    """cfr_plan_partitioned: the sizes, the device workspace, the partition count and the
+    pinned host bytes of a partitioned solver (no GPU needed)."""
+    lib = N.load()
+    args = GameArgs(game)
+    cfg = make_config(variant, None, False, "node", None, schedule, False, precision)
+    info = N.CfrPlanInfo()
+    parts = ctypes.c_int32()
+    host_bytes = ctypes.c_int64()
+    N.check(lib.cfr_plan_partitioned(ctypes.byref(args.struct), ctypes.byref(cfg), int(cut_level),
+                                     int(max_window_nodes), ctypes.byref(info),
+                                     ctypes.byref(parts), ctypes.byref(host_bytes)))
+    out = {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
+    out["partitions"] = int(parts.value)
+    out["host_bytes"] = int(host_bytes.value)
+    return out
+
+
 class BatchSolver(Solver):
     """Many independent games solved together (one forest, one graph replay per iteration).
 

@@ -2,7 +2,9 @@
 // undefined-behaviour sanitizers: flattens and plans every game of a file, reads every array of
 // the host layout export, and plans the file's games as one batch (with and without subtree
 // packs), exercising the same host code cfr_build and cfr_build_batch run before they touch a
-// GPU.
+// GPU; and cuts every game into subtree partitions at every level with several window sizes,
+// checking each partition's window against the canonical layout (parents, child ranges, the
+// level-cut nodes' patched child ranges, level offsets).
 //
 // File format (little endian): int32 n_games; per game: int64 n_nodes, int32 parent[n],
 // int32 node_infoset[n], int32 node_action[n], int32 n_infosets, int8 infoset_player[h],
@@ -16,6 +18,7 @@
 #include "../../include/cfr.h"
 #include "../../paper_2408_14778_amd/csrc/flatten.hpp"
 #include "../../paper_2408_14778_amd/csrc/host_plan.hpp"
+#include "../../paper_2408_14778_amd/csrc/partition_plan.hpp"
 #include "../../paper_2408_14778_amd/csrc/xplan.hpp"
 
 namespace {
@@ -68,6 +71,57 @@ int read_all(cfr_host_layout* h) {
         ++n;
     }
     return n;
+}
+
+// The window of every partition against the canonical layout: the local id of a canonical node
+// below the cut is found by walking the partition's level ranges independently of the plan.
+// Returns the number of mismatches.
+int64_t check_partitions(const cfr::Layout& L, const cfr::PartPlan& P) {
+    int64_t bad = 0;
+    const int32_t c = P.cut, D = L.D, nl = D - c;
+    if (P.base != L.level_offset[c + 1]) ++bad;
+    int64_t total = 0;
+    for (int32_t p = 0; p < P.parts; ++p) {
+        // canonical range of the partition at each level below the cut
+        std::vector<int64_t> glo(D + 2), ghi(D + 2), off(D + 2);
+        glo[c] = P.a[p];
+        ghi[c] = P.b[p];
+        int64_t w = 0;
+        for (int32_t l = c + 1; l <= D; ++l) {
+            glo[l] = L.child_begin[glo[l - 1]];
+            ghi[l] = L.child_begin[ghi[l - 1]];
+            off[l] = w;
+            w += ghi[l] - glo[l];
+        }
+        if (P.off[p + 1] - P.off[p] != w) ++bad;
+        total += w;
+        auto loc = [&](int32_t l, int64_t g) { return P.base + off[l] + (g - glo[l]); };
+        const int32_t* lo = P.lo.data() + static_cast<size_t>(p) * (nl + 1);
+        for (int32_t l = c + 1; l <= D; ++l)
+            if (lo[l - c - 1] != loc(l, glo[l])) ++bad;
+        if (lo[nl] != P.base + w) ++bad;
+        const int32_t* cb = P.child_begin.data() + P.off[p] + p;
+        for (int32_t l = c + 1; l <= D; ++l) {
+            for (int64_t g = glo[l]; g < ghi[l]; ++g) {
+                const int64_t i = loc(l, g) - P.base, o = P.off[p] + i;
+                const int64_t par = L.parent[g];
+                if (P.parent[o] != (l == c + 1 ? par : loc(l - 1, par))) ++bad;
+                if (P.player[o] != L.node_player[g] || P.infoset[o] != L.node_infoset[g] ||
+                    P.edge[o] != L.node_edge[g])
+                    ++bad;
+                const int64_t k = L.child_begin[g + 1] - L.child_begin[g];
+                if (cb[i + 1] - cb[i] != (l < D ? k : 0)) ++bad;
+                if (l < D && k > 0 && cb[i] != loc(l + 1, L.child_begin[g])) ++bad;
+                if ((L.node_player[g] < 0) != (k == 0)) ++bad;
+            }
+        }
+        for (int64_t j = 0; j <= P.b[p] - P.a[p]; ++j) {
+            const int64_t v = P.a[p] + j;
+            if (P.patch[P.patch_off[p] + j] != loc(c + 1, L.child_begin[v])) ++bad;
+        }
+    }
+    if (total != P.total || P.total != L.N - P.base) ++bad;
+    return bad;
 }
 
 }  // namespace
@@ -126,7 +180,21 @@ int main(int argc, char** argv) {
             std::vector<int8_t> only;
             cfr::upper_level_stats(P, dec, only);
         }
-        std::printf("game %zu: %lld nodes, %d arrays\n", i, static_cast<long long>(d.g.n_nodes), arrays);
+        int parts = 0;
+        for (int32_t cut = 1; cut < L.D; ++cut)
+            for (int64_t window : {int64_t{1}, int64_t{64}, int64_t{1} << 40}) {
+                cfr::PartPlan PP;
+                if (cfr::plan_partitions(L, cut, window, PP, err) != CFR_OK) return 1;
+                const int64_t bad = check_partitions(L, PP);
+                if (bad != 0) {
+                    std::printf("game %zu cut %d window %lld: %lld mismatches\n", i, cut,
+                                static_cast<long long>(window), static_cast<long long>(bad));
+                    return 1;
+                }
+                parts += PP.parts;
+            }
+        std::printf("game %zu: %lld nodes, %d arrays, %d partitions checked\n", i,
+                    static_cast<long long>(d.g.n_nodes), arrays, parts);
     }
     for (uint32_t flags : {0u, static_cast<uint32_t>(CFR_FLAG_SUBTREE_PACKS)}) {
         cfr_host_layout* h = nullptr;

@@ -143,6 +143,42 @@ def test_fp64_plan_and_flag_validation():
     assert N.ERRORS[lib.cfr_plan_batch(arr, 1, ctypes.byref(cfg), ctypes.byref(info))] == "CFR_EINVAL"
 
 
+def test_partition_plans():
+    """cfr_plan_partitioned: one partition per nonempty level-cut subtree at window 1, one for the whole
+    lower tree at an unbounded window; the device workspace shrinks with the window; invalid cut
+    levels, windows and flags are refused."""
+    from paper_2408_14778_amd import CfrError, plan, plan_partitioned
+    from paper_2408_14778_amd.solver import host_layout
+    g = games.leduc_like(3, 2, deal="sequential")
+    D = plan(g)["depth"]
+    lay = host_layout(g, ["level_offset", "node_player"])
+    lo, player = lay["level_offset"], lay["node_player"]
+    for cut in range(1, D):
+        one = plan_partitioned(g, cut, 1)
+        # every level-cut decision node opens a partition; terminal ones join the current one
+        assert one["partitions"] == max(1, int((player[lo[cut]:lo[cut + 1]] >= 0).sum()))
+        whole = plan_partitioned(g, cut, 1 << 40)
+        assert whole["partitions"] == 1
+        assert one["workspace_bytes"] <= whole["workspace_bytes"]
+        assert one["host_bytes"] > 0 and one["n_nodes"] == g.n_nodes
+    assert plan_partitioned(g, 3, 1)["workspace_bytes"] < plan(g, engine="node")["workspace_bytes"]
+    for cut in (0, D, -1):
+        with pytest.raises(CfrError, match="CFR_EINVAL"):
+            plan_partitioned(g, cut, 100)
+    with pytest.raises(CfrError, match="CFR_EINVAL"):
+        plan_partitioned(g, 2, 0)
+    import ctypes
+
+    from paper_2408_14778_amd import _native as N
+    from paper_2408_14778_amd.solver import GameArgs, make_config
+    lib = N.load()
+    args = GameArgs(g)
+    cfg = make_config("cfr+", engine="packs")
+    info = N.CfrPlanInfo()
+    assert N.ERRORS[lib.cfr_plan_partitioned(ctypes.byref(args.struct), ctypes.byref(cfg), 2, 100,
+                                             ctypes.byref(info), None, None)] == "CFR_EINVAL"
+
+
 def test_terminal_with_infoset_rejected():
     from paper_2408_14778_amd import CfrError, plan
     g = _copy(games.kuhn_like(3, "joint"))

@@ -15,7 +15,8 @@ import games
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2408_14778_amd", "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("flatten.cpp", "xplan.cpp", "host_layout.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("flatten.cpp", "xplan.cpp", "host_layout.cpp",
+                                            "partition_plan.cpp")]
 DRIVER = os.path.join(ROOT, "tests", "host_check", "plan_driver.cpp")
 
 
