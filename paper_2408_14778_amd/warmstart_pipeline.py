@@ -3,12 +3,16 @@
     python -m paper_2408_14778_amd.warmstart_pipeline --train-games 20000 --out-weights W.npy
 
 1. Data: seeded subgames (training seeds from 10,000 up, disjoint from the evaluation seeds
-   100-611) are solved in batches by GPU CFR+; each infoset's target is the average strategy
-   GPU CFR+ reaches after K iterations, over its legal action slots.
+   100-611) are solved in batches by GPU CFR+ for K iterations; each infoset gets two targets
+   over its legal action slots: the average strategy (the equilibrium estimate), and the
+   normalised positive regrets (the current CFR+ strategy, what regret matching plays next).
+   One network is trained on each (`--targets`), and the one whose chosen weight gives the
+   lower validation wall time is kept.
 2. Training: minibatch Adam on the masked softmax cross-entropy, all on the GPU with the
    library's BF16-MFMA kernels (features, forward, backward, optimiser).
 3. Weight: the warm-start weight (how strongly the initial regrets commit to the network's
-   strategy) is chosen on validation seeds 9000.. by mean iterations to the target.
+   strategy) is chosen per network on validation seeds 9000..: the least wall time among the
+   weights that speed up the typical game (see select_weight).
 4. Evaluation: on the held-out batch, plain CFR+ from zero regrets against the warm start,
    both checked with the best-response pass every `check_every` iterations; a game is solved
    at its first check with exploitability at most the target, and the batch when every game
@@ -59,10 +63,12 @@ def solve_targets(game_list, iterations: int, per_game: int, rng) -> dict:
     b = BatchSolver(game_list, "cfr+")
     b.iterate(iterations)
     avg = b.average_strategy()
+    cur = b.current_strategy()  # CFR+: the positive regrets normalised (uniform where none)
     expl = b.exploitability()["expl"]
     b.close()
     desc, bel, qoff = ws.descriptors(game_list)
     target, mask = ws.slot_targets(desc, avg, qoff)
+    rtarget, _ = ws.slot_targets(desc, cur, qoff)
     keep = []
     gidx = desc[:, 15].astype(np.int64)
     starts = np.searchsorted(gidx, np.arange(len(game_list)))
@@ -71,17 +77,18 @@ def solve_targets(game_list, iterations: int, per_game: int, rng) -> dict:
         n = e - s
         keep.append(s + (np.arange(n) if n <= per_game else rng.choice(n, per_game, replace=False)))
     keep = np.concatenate(keep)
-    return {"desc": desc[keep], "beliefs": bel, "target": target[keep], "mask": mask[keep],
-            "expl": expl}
+    return {"desc": desc[keep], "beliefs": bel, "target": target[keep],
+            "rtarget": rtarget[keep], "mask": mask[keep], "expl": expl}
 
 
-def train(net, data: dict, epochs: int, batch: int, lr: float, seed: int = 0) -> list:
+def train(net, data: dict, epochs: int, batch: int, lr: float, seed: int = 0,
+          key: str = "target") -> list:
     import torch
     from . import warmstart as ws
     dev = net.device
     x = ws.features(torch.from_numpy(data["desc"]).to(dev), torch.from_numpy(data["beliefs"]).to(dev),
                     net.shape[0])
-    t = torch.from_numpy(data["target"]).to(dev)
+    t = torch.from_numpy(data[key]).to(dev)
     m = torch.from_numpy(data["mask"]).to(dev)
     n = x.shape[0]
     rng = np.random.default_rng(seed)
@@ -94,7 +101,7 @@ def train(net, data: dict, epochs: int, batch: int, lr: float, seed: int = 0) ->
             tot += net.train_step(x[idx].contiguous(), t[idx].contiguous(), m[idx].contiguous(), lr)
             cnt += 1
         losses.append(tot / max(cnt, 1))
-        log(f"epoch {ep}: loss {losses[-1]:.5f}")
+        log(f"{key} epoch {ep}: loss {losses[-1]:.5f}")
     return losses
 
 
@@ -163,23 +170,40 @@ def _arm(solved_it, solved_s) -> dict:
                                     "max": int(solved_it[ok].max())}}
 
 
-def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: int = 10,
-             max_iters: int = 20000, compact: float = 0.05) -> dict:
-    """Plain zero-start CFR+ against the warm start on the same batch, both with the same
-    compaction rule: wall time until every game is solved (the batch's time to the target), and
-    per game the iterations to it."""
+def plain_arm(game_list, target: float = 1e-3, check_every: int = 10, max_iters: int = 20000,
+              compact: float = 0.05) -> tuple:
+    """Zero-start CFR+ on the batch: per game the iteration and wall time it was solved at."""
     import torch
-    from . import warmstart as ws
     from .solver import BatchSolver
-    out = {}
     b = BatchSolver(game_list, "cfr+")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     p_it, p_s, _, b = run_to_target(b, target, check_every, max_iters, t0=t0,
                                     game_list=game_list, compact=compact)
-    out["plain"] = _arm(p_it, p_s)
     b.close()
-    del b
+    return p_it, p_s
+
+
+def _slowest(solved_it, k: int = 3) -> list:
+    """The k games solved last (never-solved first): [index in the batch, iterations]."""
+    key = np.where(solved_it < 0, np.iinfo(np.int64).max, solved_it)
+    return [[int(i), int(solved_it[i])] for i in np.argsort(-key, kind="stable")[:k]]
+
+
+def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: int = 10,
+             max_iters: int = 20000, compact: float = 0.05, plain: tuple = None) -> dict:
+    """Plain zero-start CFR+ against the warm start on the same batch, both with the same
+    compaction rule: wall time until every game is solved (the batch's time to the target), and
+    per game the iterations to it. `plain` takes a plain_arm result of the same batch and
+    settings, so that a weight sweep runs the plain arm once."""
+    import torch
+    from . import warmstart as ws
+    from .solver import BatchSolver
+    out = {}
+    p_it, p_s = plain_arm(game_list, target, check_every, max_iters, compact) if plain is None \
+        else plain
+    out["plain"] = _arm(p_it, p_s)
+    out["plain"]["slowest"] = _slowest(p_it)
     # warm start (one zero-start iteration, network inference, fallback check, then CFR+)
     b = BatchSolver(game_list, "cfr+")
     torch.cuda.synchronize()
@@ -188,6 +212,7 @@ def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: i
     w_it, w_s, _, b = run_to_target(b, target, check_every, max_iters, done=2, t0=t0,
                                     game_list=game_list, compact=compact)
     out["warm"] = _arm(w_it, w_s)
+    out["warm"]["slowest"] = _slowest(w_it)
     out["warm"].update({"warm_start_seconds": info["seconds"],
                         "fallback_games": info["fallback_games"],
                         "first_expl_zero_max": float(np.max(info["expl_zero_start"])),
@@ -199,6 +224,9 @@ def evaluate(game_list, net, weight: float, target: float = 1e-3, check_every: i
                      "warm_faster": int(np.sum(w_it[both] < p_it[both])),
                      "warm_slower": int(np.sum(w_it[both] > p_it[both])),
                      "geomean_iteration_ratio": float(np.exp(np.mean(np.log(ratio)))),
+                     "median_iteration_ratio": float(np.median(ratio)),
+                     "p10_iteration_ratio": float(np.percentile(ratio, 10)),
+                     "p90_iteration_ratio": float(np.percentile(ratio, 90)),
                      "mean_iterations_plain": float(p_it[both].mean()),
                      "mean_iterations_warm": float(w_it[both].mean())}
     return out
@@ -261,25 +289,33 @@ def eval_only(args) -> int:
 
 def select_weight(val, infer, weights, by: str = "seconds") -> tuple:
     """Evaluates each warm-start weight on the validation games; returns (the chosen weight, the
-    sweep). by='seconds': the least wall time until every validation game reaches the target
-    (the metric itself); by='iterations': the fewest mean per-game iterations to it (less
-    noisy, but blind to the slowest games that set the batch's time)."""
+    sweep). A weight qualifies when the warm start speeds up the typical game (paired geometric
+    mean of warm / plain iterations below 1); if none does, all do. by='seconds': among those,
+    the least wall time until every validation game reaches the target (the metric itself);
+    by='iterations': the fewest mean per-game iterations to it (less noisy, but blind to the
+    slowest games that set the batch's time). The wall time alone favours weights that commit
+    hard enough to speed up the slowest games while slowing most of the others."""
     sweep = {}
+    plain = plain_arm(val)
     for w in weights:
-        r = evaluate(val, infer, w)
+        r = evaluate(val, infer, w, plain=plain)
         sweep[w] = r
         log(f"validation weight {w}: plain {r['plain']['seconds']:.3f}s, mean "
             f"{r['paired']['mean_iterations_plain']:.0f} it; warm {r['warm']['seconds']:.3f}s, "
-            f"mean {r['paired']['mean_iterations_warm']:.0f} it")
+            f"mean {r['paired']['mean_iterations_warm']:.0f} it, geomean ratio "
+            f"{r['paired']['geomean_iteration_ratio']:.3f}")
+    ok = [w for w in sweep if sweep[w]["paired"]["geomean_iteration_ratio"] < 1.0] or list(sweep)
     if by == "iterations":
-        return min(sweep, key=lambda w: sweep[w]["paired"]["mean_iterations_warm"]), sweep
-    return min(sweep, key=lambda w: sweep[w]["warm"]["seconds"]), sweep
+        return min(ok, key=lambda w: sweep[w]["paired"]["mean_iterations_warm"]), sweep
+    return min(ok, key=lambda w: sweep[w]["warm"]["seconds"]), sweep
 
 
 def _validation_summary(sweep) -> dict:
     return {str(w): {"plain_s": r["plain"]["seconds"], "warm_s": r["warm"]["seconds"],
                      "plain_mean_it": r["paired"]["mean_iterations_plain"],
-                     "warm_mean_it": r["paired"]["mean_iterations_warm"]}
+                     "warm_mean_it": r["paired"]["mean_iterations_warm"],
+                     "geomean_ratio": r["paired"]["geomean_iteration_ratio"],
+                     "warm_faster": r["paired"]["warm_faster"]}
             for w, r in sweep.items()}
 
 
@@ -328,6 +364,10 @@ def main() -> int:
                     help="warm-start weights tried on the validation games; the best is used")
     ap.add_argument("--select-by", choices=["seconds", "iterations"], default="seconds",
                     help="validation criterion for the weight (see select_weight)")
+    ap.add_argument("--targets", choices=["both", "strategy", "regret"], default="both",
+                    help="training targets: the average strategy after --solve-iters CFR+ "
+                         "iterations, the normalised positive regrets then, or a network for "
+                         "each with the better one on the validation games kept")
     ap.add_argument("--val-games", type=int, default=256)
     ap.add_argument("--eval-games", type=int, default=512)
     ap.add_argument("--workers", type=int, default=16)
@@ -387,36 +427,70 @@ def main() -> int:
     data = {"desc": np.concatenate([p["desc"] for p in parts]),
             "beliefs": np.concatenate([p["beliefs"] for p in parts]),
             "target": np.concatenate([p["target"] for p in parts]),
+            "rtarget": np.concatenate([p["rtarget"] for p in parts]),
             "mask": np.concatenate([p["mask"] for p in parts])}
     del parts
-    net = ws.WarmStartNet(max_batch=4096, seed=1)
-    t1 = time.time()
-    losses = train(net, data, args.epochs, 4096, args.lr)
-    log(f"trained on {len(data['desc'])} samples in {time.time() - t1:.1f}s")
-    os.makedirs(os.path.dirname(args.out_weights), exist_ok=True)
-    np.save(args.out_weights, net.params())
-    log(f"weights written to {args.out_weights}")
-    infer = ws.WarmStartNet(max_batch=65536)
-    infer.set_params(net.params())
-    # the weight is chosen on validation games (seeds disjoint from training and evaluation)
+    kinds = {"strategy": "target", "regret": "rtarget"}
+    names = list(kinds) if args.targets == "both" else [args.targets]
+    nets, losses = {}, {}
+    for name in names:
+        net = ws.WarmStartNet(max_batch=4096, seed=1)
+        t1 = time.time()
+        losses[name] = train(net, data, args.epochs, 4096, args.lr, key=kinds[name])
+        log(f"{name} targets: trained on {len(data['desc'])} samples in {time.time() - t1:.1f}s")
+        nets[name] = net
+    # each network's weight is chosen on validation games (seeds disjoint from training and
+    # evaluation); the network kept is the one whose chosen weight is faster there
     val = pending.get()
     pending = pool.map_async(_subgame, list(range(100, 100 + args.eval_games)), chunksize=4)
-    weight, sweep = select_weight(val, infer, [float(v) for v in args.weights.split(",")],
-                                  args.select_by)
+    infer = ws.WarmStartNet(max_batch=65536)
+    chosen = {}
+    for name in names:
+        infer.set_params(nets[name].params())
+        w, sweep = select_weight(val, infer, [float(v) for v in args.weights.split(",")],
+                                 args.select_by)
+        chosen[name] = {"weight": w, "validation": _validation_summary(sweep),
+                        "validation_warm_s": sweep[w]["warm"]["seconds"],
+                        "validation_paired": sweep[w]["paired"]}
+        log(f"{name} targets: weight {w}, validation warm {sweep[w]['warm']['seconds']:.3f}s")
+    best = min(names, key=lambda n: chosen[n]["validation_warm_s"])
     del val
     gl = pending.get()
     pool.close()
-    res = evaluate(gl, infer, weight)
+    # every trained network is reported on the held-out games; the kept one was chosen above
+    plain = plain_arm(gl)
+    results = {}
+    for name in names:
+        infer.set_params(nets[name].params())
+        results[name] = evaluate(gl, infer, chosen[name]["weight"], plain=plain)
+        results[name].update(chosen[name])
+        results[name]["losses"] = losses[name]
+    net = nets[best]
+    infer.set_params(net.params())
+    res = dict(results[best])
     res["mlp"] = mlp_throughput(infer, net)
     log(f"network throughput: {json.dumps(res['mlp'])}")
-    res.update({"train_games": args.train_games, "solve_iters": args.solve_iters,
-                "samples": int(len(data["desc"])), "losses": losses, "weight": weight,
+    res.update({"targets": best, "train_games": args.train_games,
+                "solve_iters": args.solve_iters, "samples": int(len(data["desc"])),
                 "eval_games": args.eval_games, "eval_seeds": [100, 99 + args.eval_games],
-                "validation": _validation_summary(sweep)})
+                "val_games": args.val_games,
+                "alternatives": {n: results[n] for n in names if n != best}})
     log(json.dumps(res))
-    side = os.path.splitext(args.out_weights)[0] + ".json"
-    with open(side, "w") as f:
-        json.dump({"weight": weight, "shape": list(net.shape), "results": res}, f, indent=1)
+    os.makedirs(os.path.dirname(args.out_weights), exist_ok=True)
+    stem = os.path.splitext(args.out_weights)[0]
+    np.save(args.out_weights, net.params())
+    log(f"{best}-target weights written to {args.out_weights}")
+    with open(stem + ".json", "w") as f:
+        json.dump({"weight": chosen[best]["weight"], "targets": best, "shape": list(net.shape),
+                   "results": res}, f, indent=1)
+    # the other networks beside it (usable with --eval-only --out-weights STEM_NAME.npy)
+    for name in names:
+        if name != best:
+            np.save(f"{stem}_{name}.npy", nets[name].params())
+            with open(f"{stem}_{name}.json", "w") as f:
+                json.dump({"weight": chosen[name]["weight"], "targets": name,
+                           "shape": list(nets[name].shape), "results": results[name]}, f, indent=1)
+            log(f"{name}-target weights written to {stem}_{name}.npy")
     if args.out_json:
         with open(args.out_json, "w") as f:
             json.dump(res, f, indent=1)
