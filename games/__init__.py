@@ -7,9 +7,10 @@ from .tuple import Game, GameBuilder
 from .small import matrix_game, rock_paper_scissors, kuhn_like, leduc_like, random_game
 from .poker import poker_game, large_game, subgame, subgame_spec, template_size
 from .states import random_state, n_player_q
+from .nplayer import normal_form_n, kuhn3, random_game_n
 
 __all__ = [
     "Game", "GameBuilder", "matrix_game", "rock_paper_scissors", "kuhn_like", "leduc_like",
     "random_game", "poker_game", "large_game", "subgame", "subgame_spec", "template_size",
-    "random_state", "n_player_q",
+    "random_state", "n_player_q", "normal_form_n", "kuhn3", "random_game_n",
 ]

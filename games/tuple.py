@@ -37,6 +37,13 @@ class Game:
     payoff_u1: np.ndarray
     payoff_u2: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
+    # general-sum games of n rational players: u(t, i) at payoff[t, i - 1] (terminals; 0
+    # elsewhere), payoff_u1 its first column and payoff_u2 None
+    payoff: np.ndarray | None = None
+
+    @property
+    def n_players(self) -> int:
+        return 2 if self.payoff is None else int(self.payoff.shape[1])
 
     @property
     def n_nodes(self) -> int:
@@ -95,6 +102,7 @@ class Game:
             payoff_u1=self.payoff_u1[inv].astype(np.float64),
             payoff_u2=None if self.payoff_u2 is None else self.payoff_u2[inv].astype(np.float64),
             meta=dict(self.meta),
+            payoff=None if self.payoff is None else self.payoff[inv].astype(np.float64),
         )
 
 
@@ -111,6 +119,7 @@ class GameBuilder:
         self.iplayer: list[int] = []
         self.inact: list[int] = []
         self.cprob: dict[int, list[float]] = {}
+        self.uvec: dict[int, list[float]] = {}  # general-sum terminals: one payoff per player
 
     def node(self, parent: int, action: int) -> int:
         self.parent.append(parent)
@@ -139,10 +148,34 @@ class GameBuilder:
     def terminal(self, v: int, u1: float) -> None:
         self.u1[v] = float(u1)
 
+    def terminal_vec(self, v: int, u) -> None:
+        """A terminal of a general-sum game: u[i - 1] is player i's payoff."""
+        self.uvec[v] = [float(x) for x in u]
+        self.u1[v] = float(u[0])
+
     def build(self, **meta) -> Game:
         chance = [self.cprob[h] for h in range(len(self.iplayer)) if self.iplayer[h] == 0]
         flat = [p for ps in chance for p in ps]
         u1 = np.asarray(self.u1, dtype=np.float64)
+        if self.uvec:
+            n_players = len(next(iter(self.uvec.values())))
+            pay = np.zeros((len(self.parent), n_players), dtype=np.float64)
+            for v, u in self.uvec.items():
+                assert len(u) == n_players
+                pay[v] = u
+            return Game(
+                name=self.name,
+                parent=np.asarray(self.parent, dtype=np.int32),
+                node_infoset=np.asarray(self.infoset, dtype=np.int32),
+                node_action=np.asarray(self.action, dtype=np.int32),
+                infoset_player=np.asarray(self.iplayer, dtype=np.int8),
+                infoset_num_actions=np.asarray(self.inact, dtype=np.int32),
+                chance_prob=np.asarray(flat, dtype=np.float64),
+                payoff_u1=pay[:, 0].copy(),
+                payoff_u2=None,
+                meta=meta,
+                payoff=pay,
+            )
         return Game(
             name=self.name,
             parent=np.asarray(self.parent, dtype=np.int32),
