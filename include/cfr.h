@@ -240,6 +240,35 @@ int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes)
 /* The same for a solver built with CFR_FLAG_FP64, in double precision. */
 int cfr_get_node_values_f64(cfr_solver* s, double* u1, double* reach, int64_t n_nodes);
 
+/* General-sum games of n rational players (Section 3.1 writes the payoff matrix and the
+ * expected-payoff recurrence with one column per rational player of I+; Table tab:properties
+ * of the appendix lists a three-player game). `game` describes the tree, the infosets and
+ * chance as for cfr_plan, with infoset_player in 0 (chance) .. n_players; its payoff_u1 and
+ * payoff_u2 are ignored. payoff (host, n_nodes * n_players doubles, node-major in input node
+ * order): u(t, i) at payoff[t * n_players + (i - 1)], read at terminals only and required
+ * finite there. 2 <= n_players <= 8. The solver runs the node engine (FP32, or FP64 with
+ * CFR_FLAG_FP64) with every player's infosets updated in one pass: at a node d of player i in
+ * infoset h the regret r~(h, a) gathers pi_{-i}(d) (w_a[i] - u[i]), pi_{-i} the product of
+ * chance's and the other players' reaches, and u the node's payoff vector. cfr_iterate,
+ * cfr_get_state / cfr_set_state, cfr_average_strategy, cfr_current_strategy (and their _f64
+ * forms), cfr_get_layout and cfr_destroy apply unchanged. cfr_exploitability returns
+ * CFR_EINVAL (Section 2.2 defines it for two-player zero-sum games), as do cfr_get_node_values
+ * and cfr_set_launch_shape. Config: CFR_FLAG_ALTERNATING and CFR_FLAG_SUBTREE_PACKS give
+ * CFR_EINVAL. Errors: those of cfr_plan / cfr_build, CFR_EINVAL for n_players out of range, a
+ * null payoff or a payoff that is not finite at a terminal. Workspace ownership as in
+ * cfr_build. */
+int cfr_plan_n(const cfr_game* game, int32_t n_players, const double* payoff,
+               const cfr_config* config, cfr_plan_info* out);
+int cfr_build_n(const cfr_game* game, int32_t n_players, const double* payoff,
+                const cfr_config* config, void* workspace, size_t bytes, void* stream,
+                cfr_solver** out);
+/* Per-node payoff vectors and reaches of the last iteration of a general-sum solver, canonical
+ * node order, in double precision whatever the solver's: values[v * n + (i - 1)] = u(v, i), the
+ * expected payoff of player i at node v (a terminal's payoff), and reach[v * (n + 1) + k] =
+ * player k + 1's reach for k < n, chance's for k = n (host, synchronises; either may be NULL).
+ * CFR_EINVAL for a two-player zero-sum solver or n_nodes that does not match. */
+int cfr_get_node_values_n(cfr_solver* s, double* values, double* reach, int64_t n_nodes);
+
 /* Subtree-partitioned, out-of-core iteration (the memory relief the paper's discussion, Section 5,
  * proposes: the iteration computed over root-to-leaf partitions of the tree instead of all of it
  * at once). Levels 0 .. cut_level stay resident on the device; the subtrees hanging from the

@@ -3,8 +3,8 @@ level-ordered game tree, computed by hand-written gfx950 HIP kernels behind a C 
 (include/cfr.h). This package holds the kernels' sources (csrc/), the build step and
 the thin ctypes binding."""
 from ._native import CfrError, load  # noqa: F401
-from .solver import (BatchSolver, PartitionedSolver, Solver, host_layout, plan,  # noqa: F401
-                     plan_partitioned)
+from .solver import (BatchSolver, NPlayerSolver, PartitionedSolver, Solver,  # noqa: F401
+                     host_layout, plan, plan_partitioned)
 
-__all__ = ["Solver", "BatchSolver", "PartitionedSolver", "plan", "plan_partitioned",
-           "host_layout", "CfrError", "load"]
+__all__ = ["Solver", "BatchSolver", "PartitionedSolver", "NPlayerSolver", "plan",
+           "plan_partitioned", "host_layout", "CfrError", "load"]

@@ -88,6 +88,12 @@ SIGNATURES = {
     "cfr_build": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.POINTER(CfrConfig),
                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_void_p)]),
+    "cfr_plan_n": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_int32, _f64p,
+                                  ctypes.POINTER(CfrConfig), ctypes.POINTER(CfrPlanInfo)]),
+    "cfr_build_n": (ctypes.c_int, [ctypes.POINTER(CfrGame), ctypes.c_int32, _f64p,
+                                   ctypes.POINTER(CfrConfig), ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "cfr_get_node_values_n": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p, ctypes.c_int64]),
     "cfr_iterate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "cfr_iterate_timed": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, _i64p,
                                          ctypes.c_int32]),

@@ -25,7 +25,7 @@ struct Work {
     std::vector<int32_t> level_offset;
 };
 
-int validate_and_order(const cfr_game& g, Work& w, std::string& err) {
+int validate_and_order(const cfr_game& g, Work& w, std::string& err, int32_t max_player) {
     if (g.n_nodes < 1 || g.parent == nullptr || g.node_infoset == nullptr ||
         g.node_action == nullptr || g.payoff_u1 == nullptr)
         return fail(err, CFR_EINVAL, "game arrays must be non-null and n_nodes >= 1");
@@ -37,9 +37,10 @@ int validate_and_order(const cfr_game& g, Work& w, std::string& err) {
     const int64_t n = g.n_nodes;
     const int32_t H = g.n_infosets;
     for (int32_t h = 0; h < H; ++h) {
-        if (g.infoset_player[h] < 0 || g.infoset_player[h] > 2)
-            return fail(err, CFR_EINVAL, "infoset %lld: player %lld not in {0,1,2}", h,
-                        g.infoset_player[h]);
+        if (g.infoset_player[h] < 0 || g.infoset_player[h] > max_player)
+            return fail(err, CFR_EINVAL,
+                        "infoset %lld: player %lld is neither chance (0) nor a rational player",
+                        h, g.infoset_player[h]);
         if (g.infoset_num_actions[h] < 1)
             return fail(err, CFR_EACTION, "infoset %lld has %lld actions", h,
                         g.infoset_num_actions[h]);
@@ -144,9 +145,9 @@ int validate_and_order(const cfr_game& g, Work& w, std::string& err) {
 
 }  // namespace
 
-int plan_sizes(const cfr_game& g, Layout& L, std::string& err) {
+int plan_sizes(const cfr_game& g, Layout& L, std::string& err, int32_t max_player) {
     Work w;
-    const int rc = validate_and_order(g, w, err);
+    const int rc = validate_and_order(g, w, err, max_player);
     if (rc != CFR_OK) return rc;
     L.N = g.n_nodes;
     L.D = static_cast<int32_t>(w.level_offset.size()) - 2;
@@ -176,9 +177,9 @@ int plan_sizes(const cfr_game& g, Layout& L, std::string& err) {
     return CFR_OK;
 }
 
-int flatten(const cfr_game& g, Layout& L, std::string& err, bool f64) {
+int flatten(const cfr_game& g, Layout& L, std::string& err, bool f64, int32_t max_player) {
     Work w;
-    int rc = validate_and_order(g, w, err);
+    int rc = validate_and_order(g, w, err, max_player);
     if (rc != CFR_OK) return rc;
     const int64_t n = g.n_nodes;
     const int32_t H = g.n_infosets;

@@ -31,11 +31,11 @@ struct Layout {
     std::vector<int32_t> node_id;        // canonical -> input node
     std::vector<int32_t> parent;         // canonical parent, -1 at root
     std::vector<int32_t> child_begin;    // N + 1
-    std::vector<int8_t> node_player;     // -1 terminal, 0 chance, 1, 2
+    std::vector<int8_t> node_player;     // -1 terminal, 0 chance, 1 .. players
     std::vector<int32_t> node_infoset;   // rational or chance canonical id, -1 terminal
     std::vector<int32_t> node_edge;      // unified edge index into [sigma | sigma_0], -1 root
     std::vector<int32_t> infoset_id;     // canonical rational infoset -> input id
-    std::vector<int8_t> infoset_player;  // 1 or 2
+    std::vector<int8_t> infoset_player;  // 1 .. players
     std::vector<int32_t> q_offset;       // Hp + 1
     std::vector<int32_t> chance_id;      // canonical chance infoset -> input id
     std::vector<int32_t> cq_offset;      // H0 + 1
@@ -50,10 +50,12 @@ struct Layout {
 };
 
 // Validates and flattens. Returns CFR_OK or a CFR_E* code with a message in `err`. f64: also
-// fill chance_prob64 and payoff64 with the input's double values.
-int flatten(const cfr_game& g, Layout& out, std::string& err, bool f64 = false);
+// fill chance_prob64 and payoff64 with the input's double values. max_player: the highest
+// rational player an infoset may name (2, or n for a game of n players).
+int flatten(const cfr_game& g, Layout& out, std::string& err, bool f64 = false,
+            int32_t max_player = 2);
 
 // Validation and sizes only (no layout arrays kept).
-int plan_sizes(const cfr_game& g, Layout& sizes, std::string& err);
+int plan_sizes(const cfr_game& g, Layout& sizes, std::string& err, int32_t max_player = 2);
 
 }  // namespace cfr

@@ -149,6 +149,76 @@ __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
     unsafeAtomicAdd(&pibar[node_infoset[p]], who == 1 ? r1 : r2);
 }
 
+// ---- general-sum games of P rational players (Section 3.1: the payoff matrix and the
+// expected-payoff recurrence carry one column per rational player)
+
+// Values and reach planes at reset: every player's payoff column at terminals, 0 elsewhere;
+// every reach plane 1 at the root (canonical node 0).
+template <class F>
+__global__ void k_reset_nodes_n(int64_t N, int32_t P, const int8_t* node_player, const F* payoff,
+                                F* value, F* reach) {
+    const int64_t v = gid();
+    if (v >= N) return;
+    const bool term = node_player[v] < 0;
+    for (int32_t i = 0; i < P; ++i) value[i * N + v] = term ? payoff[i * N + v] : F(0);
+    if (v == 0)
+        for (int32_t k = 0; k <= P; ++k) reach[k * N] = F(1);
+}
+
+// Top-down reach of one level: a decision node copies its parent's P + 1 planes and multiplies
+// the plane of whoever acted at the parent (plane P for chance) by the edge probability.
+template <class F>
+__global__ void k_reach_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
+                                const int32_t* __restrict__ parent,
+                                const int8_t* __restrict__ node_player,
+                                const int32_t* __restrict__ node_edge, const F* __restrict__ prob,
+                                F* __restrict__ reach) {
+    const int64_t v = lo + gid();
+    if (v >= hi) return;
+    if (node_player[v] < 0) return;
+    const int32_t p = parent[v];
+    const F s = prob[node_edge[v]];
+    const int8_t who = node_player[p];  // 0 chance, 1 .. P
+    const int32_t acted = who == 0 ? P : who - 1;
+    for (int32_t k = 0; k <= P; ++k) {
+        const F r = reach[k * N + p];
+        reach[k * N + v] = k == acted ? r * s : r;
+    }
+}
+
+// Bottom-up values of one level with the regret and own-reach accumulation: every player's
+// column u_i = sum_a s_a w_a[i]; at a node d of player i, r~(h, a) += pi_{-i}(d) (w_a[i] - u_i)
+// with pi_{-i} = pi_c times the other players' planes in player order, and pibar(h) += pi_i(d).
+template <class F>
+__global__ void k_value_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
+                                const int32_t* __restrict__ child_begin,
+                                const int8_t* __restrict__ node_player,
+                                const int32_t* __restrict__ node_infoset,
+                                const int32_t* __restrict__ node_edge, const F* __restrict__ prob,
+                                F* __restrict__ value, const F* __restrict__ reach,
+                                F* __restrict__ rtilde, F* __restrict__ pibar) {
+    const int64_t p = lo + gid();
+    if (p >= hi) return;
+    const int8_t who = node_player[p];
+    if (who < 0) return;
+    const int32_t c0 = child_begin[p], c1 = child_begin[p + 1];
+    F own_u = F(0);
+    for (int32_t i = 0; i < P; ++i) {
+        F u = F(0);
+        for (int32_t c = c0; c < c1; ++c) u = fma_(prob[node_edge[c]], value[i * N + c], u);
+        value[i * N + p] = u;
+        if (i == who - 1) own_u = u;
+    }
+    if (who == 0) return;
+    const int32_t me = who - 1;
+    F cf = reach[P * N + p];
+    for (int32_t j = 0; j < P; ++j)
+        if (j != me) cf *= reach[j * N + p];
+    for (int32_t c = c0; c < c1; ++c)
+        unsafeAtomicAdd(&rtilde[node_edge[c]], cf * (value[me * N + c] - own_u));
+    unsafeAtomicAdd(&pibar[node_infoset[p]], reach[me * N + p]);
+}
+
 // Infoset pass: regret update (vanilla R += r~, CFR+ R = max(R + r~, 0), discounted
 // R = (R + r~) * d+ or d-; Eq. average_counterfactual_regrets_vector in cumulative form),
 // average-strategy accumulation S += w_T * pibar * sigma (discounted: then S *= d_avg; Eq.
@@ -315,7 +385,10 @@ void launch_reset(const DevT<F>& d, hipStream_t st, bool node_arrays) {
     if (d.Hp > 0 && node_arrays)
         hipLaunchKernelGGL(k_reset_h<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
                            d.pibar);
-    if (node_arrays)
+    if (node_arrays && d.players > 0)
+        hipLaunchKernelGGL(k_reset_nodes_n<F>, dim3(blocks_for(d.N)), dim3(kBlock), 0, st, d.N,
+                           d.players, d.node_player, d.payoff, d.value, d.reach);
+    else if (node_arrays)
         hipLaunchKernelGGL(k_reset_nodes<F>, dim3(blocks_for(d.N)), dim3(kBlock), 0, st, d.N,
                            d.node_player, d.payoff, d.value, d.reach);
     if (d.Q0 > 0)
@@ -356,17 +429,14 @@ void launch_iteration(const DevT<F>& d, const int32_t* lo, const UpdateRule& rul
     for (int32_t l = 1; l < d.D; ++l) {
         const int32_t a = lo[l], b = lo[l + 1];
         pre(K_REACH, l, b - a);
-        hipLaunchKernelGGL(k_reach_level<F>, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b,
-                           d.N, d.parent, d.node_player, d.node_edge, d.prob, d.reach);
+        launch_reach_range(d, a, b, st);
         post(K_REACH);
     }
     // bottom-up: levels D-1 .. 0
     for (int32_t l = d.D - 1; l >= 0; --l) {
         const int32_t a = lo[l], b = lo[l + 1];
         pre(K_VALUE, l, b - a);
-        hipLaunchKernelGGL(k_value_level<F>, dim3(blocks_for(b - a)), dim3(kBlock), 0, st, a, b,
-                           d.N, d.child_begin, d.node_player, d.node_infoset, d.node_edge, d.prob,
-                           d.value, d.reach, d.rtilde, d.pibar);
+        launch_value_range(d, a, b, st);
         post(K_VALUE);
     }
     if (d.Hp > 0) {
@@ -385,14 +455,24 @@ void launch_iteration(const DevT<F>& d, const int32_t* lo, const UpdateRule& rul
 
 template <class F>
 void launch_reach_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st) {
-    if (hi > lo)
+    if (hi <= lo) return;
+    if (d.players > 0)
+        hipLaunchKernelGGL(k_reach_level_n<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo,
+                           hi, d.N, d.players, d.parent, d.node_player, d.node_edge, d.prob,
+                           d.reach);
+    else
         hipLaunchKernelGGL(k_reach_level<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo, hi,
                            d.N, d.parent, d.node_player, d.node_edge, d.prob, d.reach);
 }
 
 template <class F>
 void launch_value_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st) {
-    if (hi > lo)
+    if (hi <= lo) return;
+    if (d.players > 0)
+        hipLaunchKernelGGL(k_value_level_n<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo,
+                           hi, d.N, d.players, d.child_begin, d.node_player, d.node_infoset,
+                           d.node_edge, d.prob, d.value, d.reach, d.rtilde, d.pibar);
+    else
         hipLaunchKernelGGL(k_value_level<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo, hi,
                            d.N, d.child_begin, d.node_player, d.node_infoset, d.node_edge, d.prob,
                            d.value, d.reach, d.rtilde, d.pibar);

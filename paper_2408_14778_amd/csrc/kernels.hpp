@@ -14,6 +14,11 @@ template <class F>
 struct DevT {
     int64_t N, Hp, Qp, H0, Q0, M;
     int32_t D;
+    // rational players of a general-sum game (Section 3.1: one payoff column per player), or 0
+    // for a two-player zero-sum game (u_2 = -u_1, one column). With n > 0, payoff and value hold
+    // n columns (player i's at (i - 1) * N + v) and reach n + 1 planes (the players', then
+    // chance's).
+    int32_t players = 0;
     // structure (constant after build)
     int32_t* parent;        // N
     int32_t* child_begin;   // N + 1
@@ -30,15 +35,16 @@ struct DevT {
     int32_t* member_offset; // Hp + 1
     int32_t* members;       // M
     int32_t* q_input;       // Qp
-    F* payoff;              // N
+    F* payoff;              // N (players > 0: players * N)
     // iteration state
     F* prob;                // Qp + Q0: current sigma, then sigma_0
     F* R;                   // Qp cumulative regret
     F* S;                   // Qp cumulative average-strategy weight
     F* rtilde;              // Qp accumulator (zero between iterations)
     F* pibar;               // Hp accumulator (zero between iterations)
-    F* value;               // N  expected payoff of player 1 (terminals hold the payoff)
-    F* reach;               // 3N (pi_1, pi_2, pi_c) planes
+    F* value;               // N  expected payoff of player 1 (terminals hold the payoff);
+                            //    players > 0: players * N, one column per player
+    F* reach;               // 3N (pi_1, pi_2, pi_c) planes; players > 0: (players + 1) N
     int64_t* T;             // iterations done (device copy)
     // exploitability and staging
     F* avgprob;             // Qp + Q0: average strategy, then sigma_0
@@ -79,9 +85,9 @@ struct LaunchTimer {
 // variant 0 vanilla, 1 CFR+ (regrets clipped at zero), 2 discounted (the weighting scheme the
 // paper's discussion names: exponents alpha on positive cumulative regrets, beta on the others,
 // gamma on the strategy sums); linear weights iteration t's strategy by t (variants 0 and 1).
-// players: the players whose infosets a pass updates (bit 0 player 1, bit 1 player 2; the
-// others keep R, S and sigma); count: whether the pass ends the iteration (T += 1). The
-// alternating schedule is a pass with players 1, count 0, then one with players 2, count 1.
+// players: the players whose infosets a pass updates (bit i - 1 player i; the others keep R, S
+// and sigma); count: whether the pass ends the iteration (T += 1). The alternating schedule is a
+// pass with players 1, count 0, then one with players 2, count 1.
 struct UpdateRule {
     int32_t variant = 0;
     int32_t linear = 0;

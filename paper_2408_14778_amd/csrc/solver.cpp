@@ -58,6 +58,7 @@ struct cfr_solver {
     std::vector<int64_t> tier_dec;     // decision nodes of each tier
     cfr::UpdateRule rule;  // regret / average update (variant, linear weights, discounts)
     bool alternating = false;  // two passes per iteration: player 1, then player 2
+    int32_t players = 0;  // general-sum game of n rational players (node engine), else 0
     bool use_graph = true;
     bool level_pure = true;
     int64_t T = 0;
@@ -121,6 +122,7 @@ struct Sizes {
     int32_t n_games = 1;
     bool packs = false;      // subtree packs (their records are on the device)
     bool fp64 = false;       // values, probabilities and state in double precision
+    int32_t players = 0;     // general-sum game of n rational players (node engine), else 0
 };
 
 // Bounds on the subtree packs of a plan over N nodes, M members, Hp infosets and C chance nodes
@@ -152,6 +154,11 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
     d = cfr::Dev{};
     d64 = cfr::Dev64{};
     d.N = N; d.Hp = Hp; d.Qp = Qp; d.H0 = H0; d.Q0 = Q0; d.M = M; d.D = D;
+    // payoff and value columns and reach planes: one per rational player (and chance's plane);
+    // a two-player zero-sum game keeps u_1 only
+    const int64_t cols = z.players > 0 ? z.players : 1;
+    const int64_t planes = (z.players > 0 ? z.players : 2) + 1;
+    d.players = z.players;
     if (z.canonical) {
         d.parent = c.take<int32_t>(N);
         d.child_begin = c.take<int32_t>(N + 1);
@@ -185,12 +192,13 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         d64.member_offset = d.member_offset; d64.members = d.members; d64.q_input = d.q_input;
         d64.T = d.T; d64.best = d.best; d64.out2 = d.out2;
         d64.sq_offset = d.sq_offset; d64.sq_input = d.sq_input;
-        d64.payoff = c.take<double>(N);
+        d64.players = z.players;
+        d64.payoff = c.take<double>(cols * N);
         d64.prob = c.take<double>(Qp + Q0);
         d64.R = c.take<double>(Qp);
         d64.S = c.take<double>(Qp);
-        d64.value = c.take<double>(N);
-        d64.reach = c.take<double>(3 * N);
+        d64.value = c.take<double>(cols * N);
+        d64.reach = c.take<double>(planes * N);
         d64.avgprob = c.take<double>(Qp + Q0);
         d64.br_reach = c.take<double>(N);
         d64.br_value = c.take<double>(N);
@@ -200,12 +208,12 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         x = cfr::XDev{};
         return (c.off + 255) & ~size_t{255};
     }
-    d.payoff = c.take<float>(N);
+    d.payoff = c.take<float>(cols * N);
     d.prob = c.take<float>(Qp + Q0);
     d.R = c.take<float>(Qp);
     d.S = c.take<float>(Qp);
-    d.value = c.take<float>(N);
-    d.reach = c.take<float>(3 * N);
+    d.value = c.take<float>(cols * N);
+    d.reach = c.take<float>(planes * N);
     d.T = c.take<int64_t>(1);
     d.avgprob = c.take<float>(Qp + Q0);
     if (z.engine == ENGINE_NODE) {
@@ -393,27 +401,57 @@ std::vector<int32_t> reach_launch(const cfr_solver* s) {
 }
 
 
-}  // namespace
+// The most rational players of a general-sum game (cfr_build_n).
+constexpr int32_t kMaxPlayers = 8;
 
-extern "C" {
+// A general-sum game of n rational players as the two-player path reads it: the same tree, its
+// first payoff column as u_1 and no u_2 (so no zero-sum check).
+struct GameN {
+    cfr_game g{};
+    std::vector<double> u1;
+};
 
-const char* cfr_last_error(void) { return g_err.c_str(); }
+int game_n(const cfr_game* game, int32_t players, const double* payoff, GameN& out) {
+    if (game == nullptr || payoff == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (players < 2 || players > kMaxPlayers)
+        return set_err(CFR_EINVAL, "a general-sum game has 2 to " + std::to_string(kMaxPlayers) +
+                                       " rational players");
+    if (game->n_nodes < 1) return set_err(CFR_EINVAL, "game arrays must be non-null and n_nodes >= 1");
+    out.g = *game;
+    out.u1.resize(static_cast<size_t>(game->n_nodes));
+    for (int64_t v = 0; v < game->n_nodes; ++v) out.u1[v] = payoff[v * players];
+    out.g.payoff_u1 = out.u1.data();
+    out.g.payoff_u2 = nullptr;
+    return CFR_OK;
+}
 
-int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out) {
-    if (game == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
-    if (const int rc = check_config(config); rc != CFR_OK) return rc;
+// A general-sum solver runs the node engine with the simultaneous schedule.
+int check_config_n(const cfr_config* c) {
+    if (const int rc = check_config(c); rc != CFR_OK) return rc;
+    if (c != nullptr && (c->flags & (CFR_FLAG_ALTERNATING | CFR_FLAG_SUBTREE_PACKS)))
+        return set_err(CFR_EINVAL, "a general-sum game runs the node engine with simultaneous "
+                                   "updates: CFR_FLAG_ALTERNATING and CFR_FLAG_SUBTREE_PACKS do not "
+                                   "apply");
+    return CFR_OK;
+}
+
+// cfr_plan for a two-player zero-sum game (players = 0) or a general-sum game of `players`.
+int plan_impl(const cfr_game* game, const cfr_config* config, int32_t players,
+              cfr_plan_info* out) {
     cfr::Layout L;
     std::string err;
-    const int rc = cfr::plan_sizes(*game, L, err);
+    const int rc = cfr::plan_sizes(*game, L, err, players > 0 ? players : 2);
     if (rc != CFR_OK) return set_err(rc, err);
     Sizes z;
     z.N = L.N; z.Hp = L.Hp; z.Qp = L.Qp; z.H0 = L.H0; z.Q0 = L.Q0; z.M = L.n_members;
     z.terminals = L.n_terminals;
     z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
-    z.engine = choose_engine(L.level_pure, L.max_actions, config ? config->flags : 0u);
+    z.engine = players > 0 ? ENGINE_NODE
+                           : choose_engine(L.level_pure, L.max_actions, config ? config->flags : 0u);
     z.packs = z.engine == ENGINE_BLOCK && L.max_actions <= 4 && config != nullptr &&
               (config->flags & CFR_FLAG_SUBTREE_PACKS) != 0;
     z.fp64 = config != nullptr && (config->flags & CFR_FLAG_FP64) != 0;
+    z.players = players;
     cfr::Dev d{};
     cfr::Dev64 d64{};
     cfr::XDev x{};
@@ -431,6 +469,29 @@ int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out)
     out->workspace_bytes = static_cast<int64_t>(carve(d, d64, x, nullptr, z));
     return CFR_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+const char* cfr_last_error(void) { return g_err.c_str(); }
+
+int cfr_plan(const cfr_game* game, const cfr_config* config, cfr_plan_info* out) {
+    if (game == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (const int rc = check_config(config); rc != CFR_OK) return rc;
+    return plan_impl(game, config, 0, out);
+}
+
+int cfr_plan_n(const cfr_game* game, int32_t n_players, const double* payoff,
+               const cfr_config* config, cfr_plan_info* out) {
+    if (out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (const int rc = check_config_n(config); rc != CFR_OK) return rc;
+    GameN gn;
+    if (const int rc = game_n(game, n_players, payoff, gn); rc != CFR_OK) return rc;
+    return plan_impl(&gn.g, config, n_players, out);
+}
+
+}  // extern "C"
 
 namespace {
 
@@ -622,29 +683,49 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
     return apply_shapes(s, st);
 }
 
-}  // namespace
+// The general-sum payoff matrix (input node-major, n columns) as the device's canonical planes:
+// column i of canonical node v at i * N + v, terminals only (0 elsewhere). CFR_EINVAL for a
+// payoff that is not finite at a terminal.
+template <class F>
+int payoff_planes(const cfr::Layout& L, int32_t players, const double* payoff, std::vector<F>& out) {
+    const int64_t N = L.N;
+    out.assign(static_cast<size_t>(players) * N, F(0));
+    for (int64_t v = 0; v < N; ++v) {
+        if (L.node_player[v] >= 0) continue;
+        const int64_t in = L.node_id[v];
+        for (int32_t i = 0; i < players; ++i) {
+            const double u = payoff[in * players + i];
+            if (!std::isfinite(u))
+                return set_err(CFR_EINVAL, "terminal " + std::to_string(in) + ": payoff of player " +
+                                               std::to_string(i + 1) + " not finite");
+            out[static_cast<size_t>(i) * N + v] = static_cast<F>(u);
+        }
+    }
+    return CFR_OK;
+}
 
-int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, size_t bytes,
-              void* stream, cfr_solver** out) {
-    if (game == nullptr || workspace == nullptr || out == nullptr)
-        return set_err(CFR_EINVAL, "null argument");
-    cfr_config cfg{};
-    cfg.variant = CFR_VANILLA;
-    cfg.averaging = CFR_AVG_DEFAULT;
-    if (config != nullptr) cfg = *config;
-    if (const int rc = check_config(&cfg); rc != CFR_OK) return rc;
+// cfr_build for a two-player zero-sum game (players = 0) or a general-sum game of `players`
+// with its payoff matrix (the node engine, every player's infosets updated in one pass).
+int build_impl(const cfr_game* game, const cfr_config& cfg, int32_t players, const double* payoff,
+               void* workspace, size_t bytes, void* stream, cfr_solver** out) {
     cfr::Layout L;
     std::string err;
     const bool fp64 = (cfg.flags & CFR_FLAG_FP64) != 0;
-    int rc = cfr::flatten(*game, L, err, fp64);
+    int rc = cfr::flatten(*game, L, err, fp64, players > 0 ? players : 2);
     if (rc != CFR_OK) return set_err(rc, err);
+    std::vector<float> pay32;
+    std::vector<double> pay64;
+    if (players > 0 && (rc = fp64 ? payoff_planes(L, players, payoff, pay64)
+                                  : payoff_planes(L, players, payoff, pay32)) != CFR_OK)
+        return rc;
     Sizes z;
     z.N = L.N; z.Hp = L.Hp; z.Qp = L.Qp; z.H0 = L.H0; z.Q0 = L.Q0; z.M = L.n_members;
     z.terminals = L.n_terminals;
     z.C = L.n_chance_nodes; z.L = L.N; z.D = L.D; z.max_actions = L.max_actions;
-    z.engine = choose_engine(L.level_pure, L.max_actions, cfg.flags);
+    z.engine = players > 0 ? ENGINE_NODE : choose_engine(L.level_pure, L.max_actions, cfg.flags);
     z.packs = z.engine == ENGINE_BLOCK && L.max_actions <= 4 && (cfg.flags & CFR_FLAG_SUBTREE_PACKS);
     z.fp64 = fp64;
+    z.players = players;
     cfr::ExecPlan P;
     if (z.engine == ENGINE_BLOCK) {
         // subtree packs are instantiated for at most 4 actions per infoset
@@ -668,6 +749,8 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     s->xdev = x;
     s->engine = z.engine;
     s->rule = rule_of(cfg);
+    if (players > 0) s->rule.players = (1 << players) - 1;
+    s->players = players;
     s->alternating = (cfg.flags & CFR_FLAG_ALTERNATING) != 0;
     s->use_graph = (cfg.flags & CFR_FLAG_NO_GRAPH) == 0;
     s->keep_nodes = (cfg.flags & CFR_FLAG_KEEP_NODE_VALUES) != 0;
@@ -694,7 +777,7 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         if (fp64) prob_tail64[L.Qp + i] = L.chance_prob64[i];
         else prob_tail[L.Qp + i] = L.chance_prob[i];
     }
-    if (fp64 && ((rc = upload(d64.payoff, L.payoff64, st)) ||
+    if (fp64 && ((rc = upload(d64.payoff, players > 0 ? pay64 : L.payoff64, st)) ||
                  (rc = upload(d64.prob, prob_tail64, st)))) {
         discard(s);
         return rc;
@@ -710,7 +793,8 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
         (rc = upload(d.cq_offset, L.cq_offset, st)) ||
         (rc = upload(d.member_offset, L.member_offset, st)) ||
         (rc = upload(d.members, L.members, st)) || (rc = upload(d.q_input, L.q_input, st)) ||
-        (!fp64 && ((rc = upload(d.payoff, L.payoff, st)) || (rc = upload(d.prob, prob_tail, st))))) {
+        (!fp64 && ((rc = upload(d.payoff, players > 0 ? pay32 : L.payoff, st)) ||
+                   (rc = upload(d.prob, prob_tail, st))))) {
         discard(s);
         return rc;
     }
@@ -740,6 +824,38 @@ int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, s
     }
     *out = s;
     return CFR_OK;
+}
+
+cfr_config config_or_default(const cfr_config* config) {
+    cfr_config cfg{};
+    cfg.variant = CFR_VANILLA;
+    cfg.averaging = CFR_AVG_DEFAULT;
+    if (config != nullptr) cfg = *config;
+    return cfg;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cfr_build(const cfr_game* game, const cfr_config* config, void* workspace, size_t bytes,
+              void* stream, cfr_solver** out) {
+    if (game == nullptr || workspace == nullptr || out == nullptr)
+        return set_err(CFR_EINVAL, "null argument");
+    const cfr_config cfg = config_or_default(config);
+    if (const int rc = check_config(&cfg); rc != CFR_OK) return rc;
+    return build_impl(game, cfg, 0, nullptr, workspace, bytes, stream, out);
+}
+
+int cfr_build_n(const cfr_game* game, int32_t n_players, const double* payoff,
+                const cfr_config* config, void* workspace, size_t bytes, void* stream,
+                cfr_solver** out) {
+    if (workspace == nullptr || out == nullptr) return set_err(CFR_EINVAL, "null argument");
+    const cfr_config cfg = config_or_default(config);
+    if (const int rc = check_config_n(&cfg); rc != CFR_OK) return rc;
+    GameN gn;
+    if (const int rc = game_n(game, n_players, payoff, gn); rc != CFR_OK) return rc;
+    return build_impl(&gn.g, cfg, n_players, payoff, workspace, bytes, stream, out);
 }
 
 }  // extern "C"
@@ -1196,6 +1312,9 @@ int cfr_current_strategy_f64(cfr_solver* s, double* out, int64_t n_q, int out_on
 
 int cfr_exploitability(cfr_solver* s, double* expl, double br_value[2]) {
     if (s == nullptr || expl == nullptr) return set_err(CFR_EINVAL, "null argument");
+    if (s->players > 0)
+        return set_err(CFR_EINVAL, "exploitability is defined for two-player zero-sum games; this "
+                                   "solver holds a general-sum game");
     if (s->n_games != 1) return set_err(CFR_EINVAL, "a batch reports cfr_exploitability_batch");
     if (s->partitioned())
         return set_err(CFR_EINVAL, "a partitioned solver keeps no whole tree on the device: read its "
@@ -1364,14 +1483,54 @@ extern "C" {
 
 int cfr_get_node_values(cfr_solver* s, float* u1, float* reach, int64_t n_nodes) {
     if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (s->players > 0) return set_err(CFR_EINVAL, "a general-sum solver: use cfr_get_node_values_n");
     if (const int rc = check_precision(s, false); rc != CFR_OK) return rc;
     return node_values_t(s, s->dev.value, s->dev.reach, u1, reach, n_nodes);
 }
 
 int cfr_get_node_values_f64(cfr_solver* s, double* u1, double* reach, int64_t n_nodes) {
     if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (s->players > 0) return set_err(CFR_EINVAL, "a general-sum solver: use cfr_get_node_values_n");
     if (const int rc = check_precision(s, true); rc != CFR_OK) return rc;
     return node_values_t(s, s->dev64.value, s->dev64.reach, u1, reach, n_nodes);
+}
+
+int cfr_get_node_values_n(cfr_solver* s, double* values, double* reach, int64_t n_nodes) {
+    if (s == nullptr) return set_err(CFR_EINVAL, "null solver");
+    if (s->players <= 0)
+        return set_err(CFR_EINVAL, "a two-player zero-sum solver: use cfr_get_node_values");
+    if (n_nodes != s->dev.N) return set_err(CFR_EINVAL, "n_nodes does not match the game");
+    const int64_t N = s->dev.N, P = s->players;
+    std::vector<double> val(values != nullptr ? P * N : 0), planes(reach != nullptr ? (P + 1) * N : 0);
+    auto fetch = [&](auto* src32, auto* src64, std::vector<double>& dst, int64_t count,
+                     const char* what) -> int {
+        if (s->fp64) {
+            HIP_TRY(hipMemcpyAsync(dst.data(), src64, count * sizeof(double), hipMemcpyDeviceToHost,
+                                   s->stream), what);
+            return CFR_OK;
+        }
+        std::vector<float> tmp(count);
+        HIP_TRY(hipMemcpyAsync(tmp.data(), src32, count * sizeof(float), hipMemcpyDeviceToHost,
+                               s->stream), what);
+        HIP_TRY(hipStreamSynchronize(s->stream), what);
+        for (int64_t i = 0; i < count; ++i) dst[i] = tmp[i];
+        return CFR_OK;
+    };
+    int rc;
+    if (values != nullptr &&
+        (rc = fetch(s->dev.value, s->dev64.value, val, P * N, "value copy")) != CFR_OK)
+        return rc;
+    if (reach != nullptr &&
+        (rc = fetch(s->dev.reach, s->dev64.reach, planes, (P + 1) * N, "reach copy")) != CFR_OK)
+        return rc;
+    HIP_TRY(hipStreamSynchronize(s->stream), "node values synchronise");
+    for (int64_t v = 0; v < N; ++v) {
+        if (values != nullptr)
+            for (int64_t i = 0; i < P; ++i) values[v * P + i] = val[i * N + v];
+        if (reach != nullptr)
+            for (int64_t k = 0; k <= P; ++k) reach[v * (P + 1) + k] = planes[k * N + v];
+    }
+    return CFR_OK;
 }
 
 int cfr_destroy(cfr_solver* s) {

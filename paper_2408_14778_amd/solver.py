@@ -350,6 +350,59 @@ class Solver:
             pass
 
 
+class NPlayerSolver(Solver):
+    """CFR over a general-sum game of n rational players (``game.payoff``: one payoff column
+    per player, Section 3.1) on the node engine, through cfr_plan_n / cfr_build_n: vanilla,
+    CFR+ or discounted, every player's infosets updated in one pass, precision 'f32' or 'f64'.
+    State, strategies and iteration work as in Solver; exploitability() raises (it is defined
+    for two-player zero-sum games), and node_values() returns every player's value column."""
+
+    def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
+                 graph: bool = True, stream=None, dcfr=None, precision: str = "f32"):
+        import torch
+
+        if game.payoff is None:
+            raise ValueError("a general-sum game needs game.payoff (n_nodes x n_players)")
+        self._lib = N.load()
+        self.variant = variant
+        self.precision = precision
+        args = GameArgs(game)
+        self._payoff = np.ascontiguousarray(game.payoff, dtype=np.float64)
+        self.n_players = int(self._payoff.shape[1])
+        cfg = make_config(variant, averaging, graph, "node", dcfr, precision=precision)
+        info = N.CfrPlanInfo()
+        pay = _ptr(self._payoff, ctypes.c_double)
+        N.check(self._lib.cfr_plan_n(ctypes.byref(args.struct), self.n_players, pay,
+                                     ctypes.byref(cfg), ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in N.CfrPlanInfo._fields_ if f != "reserved"}
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8,
+                                     device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        N.check(self._lib.cfr_build_n(ctypes.byref(args.struct), self.n_players, pay,
+                                      ctypes.byref(cfg),
+                                      ctypes.c_void_p(self.workspace.data_ptr()),
+                                      ctypes.c_size_t(int(info.workspace_bytes)),
+                                      ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(handle)))
+        self._h = handle
+        self.n_q = int(info.n_q)
+        self.n_nodes = int(info.n_nodes)
+        self._f64 = precision == "f64"
+        self._rdt = np.float64 if self._f64 else np.float32
+        self._sfx = "_f64" if self._f64 else ""
+
+    def node_values(self):
+        """(values[N, n], reach[N, n + 1]) of the last iteration in canonical node order, as
+        float64: every player's expected payoff, and every player's reach then chance's."""
+        values = np.empty((self.n_nodes, self.n_players), dtype=np.float64)
+        reach = np.empty((self.n_nodes, self.n_players + 1), dtype=np.float64)
+        N.check(self._lib.cfr_get_node_values_n(self._h, _ptr(values, ctypes.c_double),
+                                                _ptr(reach, ctypes.c_double), self.n_nodes))
+        return values, reach
+
+
 class PartitionedSolver(Solver):
     """The subtree-partitioned, out-of-core iteration (cfr_build_partitioned): levels
     0 .. cut_level resident on the device, the subtrees below grouped into partitions of at most

@@ -249,3 +249,49 @@ def test_single_node_game():
     assert p["n_nodes"] == 1 and p["depth"] == 0 and p["n_q"] == 0
     lay = host_layout(g)
     assert lay["level_offset"].tolist() == [0, 1] and lay["payoff"].tolist() == [0.25]
+
+
+def test_nplayer_plan_validation():
+    """cfr_plan_n (no device needed): a general-sum game plans on the node engine with n value
+    columns and n + 1 reach planes (a larger workspace than the same tree's two-player plan);
+    the player count, the payoff pointer, the schedule flags and a payoff that is not finite at
+    a terminal are checked; the two-player call refuses a third player."""
+    import ctypes
+
+    import numpy as np
+
+    from paper_2408_14778_amd import _native as N
+    from paper_2408_14778_amd.solver import GameArgs, _ptr, make_config
+
+    EINVAL = -1  # CFR_EINVAL
+    lib = N.load()
+    g = games.kuhn3()
+    args = GameArgs(g)
+    pay = np.ascontiguousarray(g.payoff)
+    pp = _ptr(pay, ctypes.c_double)
+
+    def plan_n(n, payoff=pp, cfg=None):
+        info = N.CfrPlanInfo()
+        rc = lib.cfr_plan_n(ctypes.byref(args.struct), n, payoff,
+                            None if cfg is None else ctypes.byref(cfg), ctypes.byref(info))
+        return rc, info
+
+    rc, info = plan_n(3)
+    assert rc == 0 and info.engine == 0 and info.n_nodes == 617 and info.n_q == 96
+    # the same tree as a two-player game (players renamed 1, 2) needs fewer bytes
+    g2 = games.kuhn3()
+    g2.infoset_player[g2.infoset_player == 3] = 2
+    a2 = GameArgs(g2)
+    i2 = N.CfrPlanInfo()
+    cfg2 = make_config("vanilla", engine="node")
+    assert lib.cfr_plan(ctypes.byref(a2.struct), ctypes.byref(cfg2), ctypes.byref(i2)) == 0
+    assert info.workspace_bytes > i2.workspace_bytes
+    for bad in (1, 9):
+        assert plan_n(bad)[0] == EINVAL
+    assert plan_n(2)[0] == EINVAL  # an infoset of player 3
+    assert plan_n(3, payoff=None)[0] == EINVAL
+    for sched, eng in (("alternating", "node"), ("simultaneous", "packs")):
+        cfg = make_config("cfr+", engine=eng, schedule=sched)
+        assert plan_n(3, cfg=cfg)[0] == EINVAL
+    info = N.CfrPlanInfo()
+    assert lib.cfr_plan(ctypes.byref(args.struct), None, ctypes.byref(info)) == EINVAL

@@ -1,0 +1,145 @@
+"""GPU parity of the general-sum path (cfr_build_n: the node engine with one value column per
+rational player and n + 1 reach planes) against the n-player FP64 oracle (oracle/cfr_n.py).
+
+Bounds are those of the two-player tests: one iteration from an identical seeded state within
+1e-6 norm-wise in FP32 and 1e-12 in FP64 (max|gpu - oracle| / max|oracle|, for R', S', every
+player's node values and every reach plane), the next strategy elementwise outside regret
+matching's uniform-fallback discontinuity. After T iterations, where FP32 rounding decorrelates
+the regret-matching switches, the FP64 path is held to 1e-9 on R and S and the FP32 path to
+1e-3 on each player's expected payoff under the average strategy (payoff scale 1 to 2).
+"""
+import numpy as np
+import pytest
+
+import games
+from oracle import cfr, cfr_n
+
+pytestmark = pytest.mark.gpu
+
+
+def _normal3():
+    rng = np.random.default_rng(4)
+    return games.normal_form_n(rng.integers(-64, 65, size=(3, 2, 4, 3)) / 64.0, name="nf3")
+
+
+def _bimatrix():
+    rng = np.random.default_rng(5)
+    return games.normal_form_n(rng.integers(-64, 65, size=(4, 3, 2)) / 64.0, name="bimatrix")
+
+
+GAMES = {
+    "kuhn3": lambda: games.kuhn3(),
+    "kuhn3_joint": lambda: games.kuhn3(deal="joint"),
+    "rand3": lambda: games.random_game_n(3, 3),
+    "rand4": lambda: games.random_game_n(7, 4, depth=5),
+    "rand5": lambda: games.random_game_n(11, 5, depth=4, max_actions=4),
+    "nf3": _normal3,
+    "bimatrix": _bimatrix,
+}
+
+
+def _rel(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = max(float(np.abs(ref).max()) if ref.size else 0.0, 1e-300)
+    return float(np.abs(gpu - ref).max()) / scale if ref.size else 0.0
+
+
+def _solver(g, variant, precision):
+    from paper_2408_14778_amd import NPlayerSolver
+    s = NPlayerSolver(g, variant, precision=precision)
+    assert s.info["engine"] == 0 and s.n_players == g.n_players
+    return s
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+", "dcfr"])
+@pytest.mark.parametrize("name", sorted(GAMES))
+def test_one_iteration_parity(name, variant, precision, tol):
+    g = GAMES[name]()
+    T, R, S = games.random_state(g, seed=len(name) + 2, nonnegative=(variant == "cfr+"))
+    s = _solver(g, variant, precision)
+    dt = np.float64 if precision == "f64" else np.float32
+    s.set_state(T, R.astype(dt), S.astype(dt))
+    s.iterate(1)
+    T2, R2, S2 = s.get_state()
+    sig2 = s.current_strategy()
+    vals, reach = s.node_values()
+    tree = cfr_n.TreeN(g)
+    new, info = cfr_n.iterate(tree, cfr.State(T, [float(x) for x in R], [float(x) for x in S]),
+                              variant, record=True)
+    assert T2 == T + 1
+    errs = {"R": _rel(R2, new.R), "S": _rel(S2, new.S)}
+    nid = s.layout("node_id")
+    ref_u = np.asarray([info["node_u"][v] for v in nid])
+    for i in range(g.n_players):
+        errs[f"u{i + 1}"] = _rel(vals[:, i], ref_u[:, i])
+    dec = s.layout("node_player") >= 0
+    ref_reach = np.asarray([info["node_reach"][v] for v in nid])
+    for k in range(g.n_players + 1):
+        errs[f"reach{k}"] = _rel(reach[dec, k], ref_reach[dec, k])
+    print(name, variant, precision, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= tol, errs
+    ref_sig = np.asarray(info["next_sigma"])
+    scale = max(float(np.abs(new.R).max()), 1e-300)
+    for h in tree.rational:
+        o, k = tree.qoff[h], tree.nact[h]
+        pos = sum(max(x, 0.0) for x in new.R[o:o + k])
+        if 0.0 < pos < 1e3 * tol * scale:  # regret matching's uniform-fallback discontinuity
+            continue
+        np.testing.assert_allclose(sig2[o:o + k], ref_sig[o:o + k], rtol=0, atol=10 * tol)
+
+
+@pytest.mark.parametrize("name,variant,iters", [("kuhn3", "cfr+", 300), ("rand4", "vanilla", 200),
+                                                ("nf3", "dcfr", 200)])
+def test_fp64_after_T_iterations(name, variant, iters):
+    g = GAMES[name]()
+    s = _solver(g, variant, "f64")
+    s.iterate(iters)
+    T, R, S = s.get_state()
+    ref = cfr_n.solve(cfr_n.TreeN(g), iters, variant)
+    assert T == iters == ref.T
+    assert _rel(R, ref.R) <= 1e-9 and _rel(S, ref.S) <= 1e-9
+
+
+@pytest.mark.parametrize("name,variant,iters", [("kuhn3", "cfr+", 300), ("rand3", "cfr+", 300),
+                                                ("nf3", "vanilla", 200)])
+def test_fp32_expected_payoffs_after_T_iterations(name, variant, iters):
+    g = GAMES[name]()
+    s = _solver(g, variant, "f32")
+    s.iterate(iters)
+    tree = cfr_n.TreeN(g)
+    got = cfr_n.expected_values(tree, [float(x) for x in s.average_strategy()])
+    ref = cfr_n.expected_values(tree, cfr.average_strategy(tree, cfr_n.solve(tree, iters, variant).S))
+    print(name, variant, got, ref, flush=True)
+    assert np.abs(np.asarray(got) - np.asarray(ref)).max() <= 1e-3
+
+
+def test_kuhn3_values_add_up_to_zero_on_the_gpu():
+    g = GAMES["kuhn3"]()
+    s = _solver(g, "cfr+", "f64")
+    s.iterate(50)
+    vals, _ = s.node_values()
+    assert abs(vals[0].sum()) <= 1e-12  # the root (canonical node 0): a zero-sum game
+
+
+def test_two_player_calls_are_refused():
+    from paper_2408_14778_amd import CfrError, Solver
+    g = GAMES["kuhn3"]()
+    s = _solver(g, "cfr+", "f32")
+    s.iterate(2)
+    with pytest.raises(CfrError, match="CFR_EINVAL"):
+        s.exploitability()
+    with pytest.raises(CfrError, match="CFR_EINVAL"):
+        Solver.node_values(s)  # the two-player export
+    with pytest.raises(CfrError, match="CFR_EINVAL"):
+        s.set_launch_shape(up_threads=128)
+    # and a two-player zero-sum solver refuses the n-column export
+    import ctypes
+
+    from paper_2408_14778_amd import _native as N
+    z = Solver(games.kuhn_like(3, "joint"), "cfr+", engine="node")
+    buf = np.empty(2 * z.n_nodes, dtype=np.float64)
+    with pytest.raises(CfrError, match="CFR_EINVAL"):
+        N.check(z._lib.cfr_get_node_values_n(z._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             None, z.n_nodes))
