@@ -92,6 +92,23 @@ def algorithmic_bytes(kernel: str, counts: list, reach_launch=None, real: int = 
                   "value_level": values, "infoset_update": infoset}.get(kernel, 0.0))
 
 
+def algorithmic_bytes_n(kernel: str, counts: list, players: int, real: int = 4) -> float:
+    """The same streaming model for a general-sum game of `players` rational players on the node
+    engine, which keeps one value column per player and players + 1 reach planes: top-down, per
+    internal non-root node, parent index and edge label 8, the parent's planes and its own
+    2 (players + 1) r; bottom-up, per node read as a child its players values and its structure
+    8, per internal node its players values written and its players + 1 reach planes read; per
+    pair 9r and per infoset 2r as for two players."""
+    r, P = real, players
+    D = len(counts) - 1
+    reach = sum((8 + 2 * (P + 1) * r) * counts[l]["decision"] for l in range(1, D))
+    values = sum((8 + P * r) * counts[l + 1]["nodes"] + (2 * P + 1) * r * counts[l]["decision"]
+                 for l in range(D))
+    infoset = sum(9 * r * c["q"] + 2 * r * c["infosets"] for c in counts)
+    return float({"reach_level": reach, "value_level": values,
+                  "infoset_update": infoset}.get(kernel, 0.0))
+
+
 LAYOUT_FOR_COUNTS = ["level_offset", "node_player", "parent", "q_offset", "child_begin",
                      "member_offset", "members"]
 
@@ -208,6 +225,91 @@ def bench_batch(args, gl) -> dict:
                                "seconds_first": br_s[0], "seconds": min(br_s[1:])}}
 
 
+PCIE_PEAK_GBS = 64.0  # PCIe 5.0 x16 host link, per direction (nominal)
+NPLAYER_GAME = dict(seed=6, n_players=3, n_types=12, depth=9, max_actions=3, p_terminal=0.15)
+
+
+def _timed(solver, steps: int):
+    """steps iterations between hipEvents on the solver's stream (torch's current stream):
+    (wall seconds, event seconds) per iteration."""
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    assert solver.stream == torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(solver.stream)
+    solver.iterate(steps)
+    ev1.record(solver.stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, ev0.elapsed_time(ev1) * 1e-3 / steps
+
+
+def bench_nplayer(args, g) -> dict:
+    """A three-player general-sum game (games.random_game_n, NPLAYER_GAME) on the node engine's
+    general-sum kernels (cfr_build_n), CFR+: node-updates/s and the roofline of the dominant
+    kernel under algorithmic_bytes_n."""
+    from paper_2408_14778_amd import NPlayerSolver
+
+    real = 8 if args.precision == "f64" else 4
+    s = NPlayerSolver(g, "cfr+", precision=args.precision)
+    s.iterate(args.warmup)
+    wall_s, gpu_s = _timed(s, args.steps)
+    kt = s.iterate_timed(args.timed_kernel_steps)
+    lay = {k: s.layout(k) for k in LAYOUT_FOR_COUNTS}
+    counts = level_counts(lay)
+    dom = max(kt, key=lambda k: kt[k][1])
+    launches, total_ms = kt[dom]
+    share = total_ms / sum(v[1] for v in kt.values())
+    avg_s = gpu_s * share / (launches / args.timed_kernel_steps)
+    P = g.n_players
+    bytes_per_launch = (algorithmic_bytes_n(dom, counts, P, real) * args.timed_kernel_steps /
+                        launches)
+    achieved = bytes_per_launch / avg_s / 1e9
+    iter_bytes = float(sum(algorithmic_bytes_n(k, counts, P, real)
+                           for k in ("reach_level", "value_level", "infoset_update")))
+    s.close()
+    return {"metric": METRIC, "value": g.n_nodes / wall_s, "unit": "node-updates/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall_s * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+            "config": {"workload": "three-player general-sum random game (private types 12 per "
+                                   "player, public depth 9), CFR+, node engine",
+                       "game": NPLAYER_GAME, "nodes": g.n_nodes, "q": s.n_q, "players": P},
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": None, "bytes_per_launch": bytes_per_launch,
+                         "avg_launch_us": avg_s * 1e6, "iteration_us_events": gpu_s * 1e6,
+                         "iteration_bytes": iter_bytes, "iteration_gbs": iter_bytes / gpu_s / 1e9},
+            "kernels": {k: {"launches": n, "avg_us": ms / n * 1e3} for k, (n, ms) in kt.items()}}
+
+
+def bench_partitioned(args, g) -> dict:
+    """The large game through the subtree-partitioned, out-of-core iteration (cut at level 8,
+    windows of at most 2^21 nodes), CFR+: node-updates/s, and the host link it is bound by:
+    every iteration streams each partition's window (the pinned bytes) host to device."""
+    from paper_2408_14778_amd import PartitionedSolver
+
+    s = PartitionedSolver(g, "cfr+", cut_level=8, max_window_nodes=1 << 21,
+                          precision=args.precision)
+    s.iterate(args.warmup)
+    wall_s, gpu_s = _timed(s, args.steps)
+    achieved = s.host_bytes / gpu_s / 1e9
+    out = {"metric": METRIC, "value": g.n_nodes / wall_s, "unit": "node-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": wall_s * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.precision, "data": "synthetic",
+           "config": {"workload": "large poker game, subtree-partitioned out-of-core iteration "
+                                  "(cut level 8, windows <= 2^21 nodes), CFR+",
+                      "nodes": g.n_nodes, "partitions": s.n_partitions,
+                      "device_workspace_bytes": int(s.info["workspace_bytes"]),
+                      "pinned_host_bytes": s.host_bytes},
+           "roofline": {"bound": "pcie", "achieved": achieved, "peak": PCIE_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / PCIE_PEAK_GBS, "traffic": None,
+                        "bytes_per_iteration": s.host_bytes, "iteration_us_events": gpu_s * 1e6}}
+    s.close()
+    return out
+
+
 def warm_start_eval(game_list) -> dict:
     """Wall time until every one of the 512 held-out subgames reaches exploitability 1e-3: CFR+
     from zero regrets against the stored warm-start network (same solver, same checks)."""
@@ -289,8 +391,11 @@ def main() -> int:
                          "dcfr: discounted CFR with exponents 1.5, 0, 2)")
     ap.add_argument("--schedule", choices=["simultaneous", "alternating"], default="simultaneous",
                     help="alternating: an iteration is a player-1 pass and a player-2 pass")
-    ap.add_argument("--workload", choices=["large", "batch"], default="large",
-                    help="large: the large single game (the reported line); batch: 512 subgames")
+    ap.add_argument("--workload", choices=["large", "batch", "partitioned", "nplayer"],
+                    default="large",
+                    help="large: the large single game (the reported line); batch: 512 "
+                         "subgames; partitioned: the large game out of core; nplayer: a "
+                         "three-player general-sum game")
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the second half of the metric: wall time to exploitability 1e-3 on "
                          "the 512 held-out subgames, zero start vs the stored warm-start network")
@@ -338,6 +443,13 @@ def main() -> int:
         log("copy calibration: 3 x (1 GiB read + 1 GiB written) elementwise copies done")
     if gl is not None:
         print(json.dumps(bench_batch(args, gl)), flush=True)
+        return 0
+    if args.workload in ("nplayer", "partitioned"):
+        t0 = time.perf_counter()
+        g = games.random_game_n(**NPLAYER_GAME) if args.workload == "nplayer" else games.large_game()
+        log(f"game built: {g.n_nodes} nodes in {time.perf_counter() - t0:.1f}s")
+        run = bench_nplayer if args.workload == "nplayer" else bench_partitioned
+        print(json.dumps(run(args, g)), flush=True)
         return 0
     t0 = time.perf_counter()
     g = games.large_game()

@@ -15,6 +15,8 @@ namespace cfr {
 namespace {
 
 constexpr int kBlock = 256;
+// Levels of at most this many nodes run the general-sum values one wavefront per node.
+constexpr int32_t kWideNodes = 4096;
 
 inline unsigned blocks_for(int64_t n) {
     return static_cast<unsigned>((n + kBlock - 1) / kBlock);
@@ -186,17 +188,18 @@ __global__ void k_reach_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
     }
 }
 
-// Bottom-up values of one level with the regret and own-reach accumulation: every player's
-// column u_i = sum_a s_a w_a[i]; at a node d of player i, r~(h, a) += pi_{-i}(d) (w_a[i] - u_i)
-// with pi_{-i} = pi_c times the other players' planes in player order, and pibar(h) += pi_i(d).
+// Bottom-up values of one level: every player's column u_i = sum_a s_a w_a[i]; at a node d of
+// player i, each child's regret contribution pi_{-i}(d) (w_a[i] - u_i), with pi_{-i} = pi_c times
+// the other players' planes in player order, is stored at the child's slot (no atomics: an
+// infoset of a general-sum game can have many members, whose additions to one accumulator would
+// serialise); k_gather_n sums them per infoset.
 template <class F>
 __global__ void k_value_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
                                 const int32_t* __restrict__ child_begin,
                                 const int8_t* __restrict__ node_player,
-                                const int32_t* __restrict__ node_infoset,
                                 const int32_t* __restrict__ node_edge, const F* __restrict__ prob,
                                 F* __restrict__ value, const F* __restrict__ reach,
-                                F* __restrict__ rtilde, F* __restrict__ pibar) {
+                                F* __restrict__ contrib) {
     const int64_t p = lo + gid();
     if (p >= hi) return;
     const int8_t who = node_player[p];
@@ -214,9 +217,76 @@ __global__ void k_value_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
     F cf = reach[P * N + p];
     for (int32_t j = 0; j < P; ++j)
         if (j != me) cf *= reach[j * N + p];
-    for (int32_t c = c0; c < c1; ++c)
-        unsafeAtomicAdd(&rtilde[node_edge[c]], cf * (value[me * N + c] - own_u));
-    unsafeAtomicAdd(&pibar[node_infoset[p]], reach[me * N + p]);
+    for (int32_t c = c0; c < c1; ++c) contrib[c] = cf * (value[me * N + c] - own_u);
+}
+
+// k_value_level_n for a level of few nodes, one wavefront per node: lane l takes children
+// l, l + 64, ... and the lanes' partial sums are added by a fixed butterfly (a node with a wide
+// fan-out, such as a root dealing thousands of private-type combinations, would otherwise walk
+// its children on one thread).
+template <class F>
+__global__ void __launch_bounds__(256) k_value_wide_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
+                                                      const int32_t* __restrict__ child_begin,
+                                                      const int8_t* __restrict__ node_player,
+                                                      const int32_t* __restrict__ node_edge,
+                                                      const F* __restrict__ prob,
+                                                      F* __restrict__ value,
+                                                      const F* __restrict__ reach,
+                                                      F* __restrict__ contrib) {
+    const int64_t p = lo + ((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= hi) return;  // whole wavefronts leave together
+    const int8_t who = node_player[p];
+    if (who < 0) return;
+    const int32_t c0 = child_begin[p], c1 = child_begin[p + 1];
+    F own_u = F(0);
+    for (int32_t i = 0; i < P; ++i) {
+        F u = F(0);
+        for (int32_t c = c0 + lane; c < c1; c += 64)
+            u = fma_(prob[node_edge[c]], value[i * N + c], u);
+        for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
+        if (lane == 0) value[i * N + p] = u;
+        if (i == who - 1) own_u = u;
+    }
+    if (who == 0) return;
+    const int32_t me = who - 1;
+    F cf = reach[P * N + p];
+    for (int32_t j = 0; j < P; ++j)
+        if (j != me) cf *= reach[j * N + p];
+    for (int32_t c = c0 + lane; c < c1; c += 64) contrib[c] = cf * (value[me * N + c] - own_u);
+}
+
+// Per infoset, one wavefront: r~(h, a) = the sum over the members d of their action-a child's
+// contribution, and pibar(h) = the sum of the members' own reaches (Eq. player_reach_probability,
+// own-reach reading); lane l takes members l, l + 64, ... in member order and the lanes' partial
+// sums are added by a fixed butterfly, so the result does not depend on scheduling. Written
+// over the accumulators the infoset update reads (and clears).
+template <class F>
+__global__ void __launch_bounds__(256) k_gather_n(int64_t Hp, int64_t N,
+                                                  const int32_t* __restrict__ q_offset,
+                                                  const int32_t* __restrict__ member_offset,
+                                                  const int32_t* __restrict__ members,
+                                                  const int32_t* __restrict__ child_begin,
+                                                  const int8_t* __restrict__ infoset_player,
+                                                  const F* __restrict__ reach,
+                                                  const F* __restrict__ contrib,
+                                                  F* __restrict__ rtilde, F* __restrict__ pibar) {
+    const int64_t h = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (h >= Hp) return;  // whole wavefronts leave together
+    const int32_t o = q_offset[h], k = q_offset[h + 1] - o;
+    const int32_t m0 = member_offset[h], m1 = member_offset[h + 1];
+    const int64_t own_plane = static_cast<int64_t>(infoset_player[h] - 1) * N;
+    F own = F(0);
+    for (int32_t m = m0 + lane; m < m1; m += 64) own += reach[own_plane + members[m]];
+    for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off, 64);
+    if (lane == 0) pibar[h] = own;
+    for (int32_t a = 0; a < k; ++a) {
+        F sum = F(0);
+        for (int32_t m = m0 + lane; m < m1; m += 64) sum += contrib[child_begin[members[m]] + a];
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        if (lane == 0) rtilde[o + a] = sum;
+    }
 }
 
 // Infoset pass: regret update (vanilla R += r~, CFR+ R = max(R + r~, 0), discounted
@@ -420,6 +490,17 @@ const char* kernel_kind_name(int kind) {
     }
 }
 
+// General-sum games: the per-infoset sums of the children's regret contributions and of the
+// members' own reaches (k_gather_n), before the infoset update.
+template <class F>
+void launch_gather_n(const DevT<F>& d, hipStream_t st) {
+    if (d.players <= 0 || d.Hp <= 0) return;
+    const int64_t threads = d.Hp * 64;
+    hipLaunchKernelGGL(k_gather_n<F>, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256),
+                       0, st, d.Hp, d.N, d.q_offset, d.member_offset, d.members, d.child_begin,
+                       d.infoset_player, d.reach, d.contrib, d.rtilde, d.pibar);
+}
+
 template <class F>
 void launch_iteration(const DevT<F>& d, const int32_t* lo, const UpdateRule& rule, hipStream_t st,
                       LaunchTimer* timer) {
@@ -441,6 +522,7 @@ void launch_iteration(const DevT<F>& d, const int32_t* lo, const UpdateRule& rul
     }
     if (d.Hp > 0) {
         pre(K_INFOSET, -1, d.Hp);
+        launch_gather_n(d, st);
         hipLaunchKernelGGL(k_infoset_update<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
                            d.q_offset, d.infoset_player, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T,
                            rule);
@@ -468,10 +550,14 @@ void launch_reach_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st
 template <class F>
 void launch_value_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st) {
     if (hi <= lo) return;
-    if (d.players > 0)
+    if (d.players > 0 && hi - lo <= kWideNodes)
+        hipLaunchKernelGGL(k_value_wide_n<F>, dim3(static_cast<unsigned>((hi - lo + 3) / 4)),
+                           dim3(256), 0, st, lo, hi, d.N, d.players, d.child_begin, d.node_player,
+                           d.node_edge, d.prob, d.value, d.reach, d.contrib);
+    else if (d.players > 0)
         hipLaunchKernelGGL(k_value_level_n<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo,
-                           hi, d.N, d.players, d.child_begin, d.node_player, d.node_infoset,
-                           d.node_edge, d.prob, d.value, d.reach, d.rtilde, d.pibar);
+                           hi, d.N, d.players, d.child_begin, d.node_player, d.node_edge, d.prob,
+                           d.value, d.reach, d.contrib);
     else
         hipLaunchKernelGGL(k_value_level<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo, hi,
                            d.N, d.child_begin, d.node_player, d.node_infoset, d.node_edge, d.prob,
@@ -480,6 +566,7 @@ void launch_value_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st
 
 template <class F>
 void launch_infoset_pass(const DevT<F>& d, const UpdateRule& rule, hipStream_t st) {
+    launch_gather_n(d, st);
     if (d.Hp > 0)
         hipLaunchKernelGGL(k_infoset_update<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
                            d.q_offset, d.infoset_player, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T,

@@ -42,6 +42,8 @@ struct DevT {
     F* S;                   // Qp cumulative average-strategy weight
     F* rtilde;              // Qp accumulator (zero between iterations)
     F* pibar;               // Hp accumulator (zero between iterations)
+    F* contrib;             // players > 0: N, the regret contribution of each player node's
+                            //   child, summed per infoset by the gather pass
     F* value;               // N  expected payoff of player 1 (terminals hold the payoff);
                             //    players > 0: players * N, one column per player
     F* reach;               // 3N (pi_1, pi_2, pi_c) planes; players > 0: (players + 1) N

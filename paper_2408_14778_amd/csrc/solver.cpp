@@ -204,6 +204,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         d64.br_value = c.take<double>(N);
         d64.stage = c.take<double>(2 * Qp);
         d64.rtilde = c.take<double>(Qp);
+        if (z.players > 0) d64.contrib = c.take<double>(N);
         d64.pibar = c.take<double>(Hp);
         x = cfr::XDev{};
         return (c.off + 255) & ~size_t{255};
@@ -228,6 +229,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
     x = cfr::XDev{};
     if (z.engine == ENGINE_NODE) {
         d.rtilde = c.take<float>(Qp);
+        if (z.players > 0) d.contrib = c.take<float>(N);
         d.pibar = c.take<float>(Hp);
     } else {
         x.N = N; x.Hp = Hp; x.Qp = Qp; x.Q0 = Q0; x.M = M; x.L = z.L; x.C = z.C;

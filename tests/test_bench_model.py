@@ -56,3 +56,18 @@ def test_forest_level_counts_add_up():
         for l in range(len(forest)):
             assert forest[l][key] == sum(c[l][key] for c in each if l < len(c)), (key, l)
     assert sum(c["nodes"] for c in forest) == sum(g.n_nodes for g in gl)
+
+
+def test_nplayer_model_hand_count():
+    """The general-sum streaming model on a 2 x 3 x 2 three-player normal-form game, counted by
+    hand: levels of 1, 2 and 6 decision nodes over 12 terminals, one infoset of 2, 3 and 2
+    actions per level; fp32, 3 value columns, 4 reach planes."""
+    import games
+    from oracle.layout import canonical_layout
+    g = games.normal_form_n(np.zeros((2, 3, 2, 3)))
+    counts = bench.level_counts(canonical_layout(g))
+    assert [c["decision"] for c in counts] == [1, 2, 6, 0]
+    assert bench.algorithmic_bytes_n("reach_level", counts, 3) == (8 + 2 * 4 * 4) * (2 + 6)
+    assert bench.algorithmic_bytes_n("value_level", counts, 3) == \
+        (8 + 12) * (2 + 6 + 12) + 7 * 4 * (1 + 2 + 6)
+    assert bench.algorithmic_bytes_n("infoset_update", counts, 3) == 36 * (2 + 3 + 2) + 8 * 3
