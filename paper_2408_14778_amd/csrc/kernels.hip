@@ -121,11 +121,15 @@ __global__ void k_reach_level(int32_t lo, int32_t hi, int64_t N, const int32_t* 
 }
 
 // Bottom-up values of one level (Eq. expected_payoffs_matrix_recurrence) fused with the
-// node -> infoset-action reductions: for a node d of player i with value u and children
-// values w_a, r~(h, a) += sgn_i * pi_{-i}(d) * (w_a - u) (the multiplied-out form of
-// Eq. instantaneous_counterfactual_regret, with u_2 = -u_1) and pibar(h) += pi_i(d)
-// (Eq. player_reach_probability, own-reach reading).
-template <class F>
+// node -> infoset-action terms: for a node d of player i with value u and children values w_a,
+// the contribution sgn_i * pi_{-i}(d) * (w_a - u) to r~(h, a) (the multiplied-out form of
+// Eq. instantaneous_counterfactual_regret, with u_2 = -u_1) and pi_i(d) to pibar(h) (Eq.
+// player_reach_probability, own-reach reading). kStore: the contribution is stored at the
+// child's slot and a gather pass sums it per infoset in member order (no atomics; pibar is
+// summed from the reach planes there); otherwise both are added to the per-pair and
+// per-infoset accumulators by atomics (the partitioned iteration, whose windows are overwritten
+// partition by partition, accumulates across them this way).
+template <class F, bool kStore>
 __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
                               const int32_t* __restrict__ child_begin,
                               const int8_t* __restrict__ node_player,
@@ -133,7 +137,7 @@ __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
                               const int32_t* __restrict__ node_edge,
                               const F* __restrict__ prob, F* __restrict__ value,
                               const F* __restrict__ reach, F* __restrict__ rtilde,
-                              F* __restrict__ pibar) {
+                              F* __restrict__ pibar, F* __restrict__ contrib) {
     const int64_t p = lo + gid();
     if (p >= hi) return;
     const int8_t who = node_player[p];
@@ -146,6 +150,10 @@ __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
     const F r1 = reach[p], r2 = reach[N + p], rc = reach[2 * N + p];
     const F cf = (who == 1 ? r2 : r1) * rc;
     const F w = who == 1 ? cf : -cf;
+    if (kStore) {
+        for (int32_t c = c0; c < c1; ++c) contrib[c] = w * (value[c] - u);
+        return;
+    }
     for (int32_t c = c0; c < c1; ++c)
         unsafeAtomicAdd(&rtilde[node_edge[c]], w * (value[c] - u));
     unsafeAtomicAdd(&pibar[node_infoset[p]], who == 1 ? r1 : r2);
@@ -490,11 +498,12 @@ const char* kernel_kind_name(int kind) {
     }
 }
 
-// General-sum games: the per-infoset sums of the children's regret contributions and of the
-// members' own reaches (k_gather_n), before the infoset update.
+// With stored contributions (d.contrib): the per-infoset sums of the children's regret
+// contributions and of the members' own reaches (k_gather_n, a wavefront per infoset), before
+// the infoset update.
 template <class F>
-void launch_gather_n(const DevT<F>& d, hipStream_t st) {
-    if (d.players <= 0 || d.Hp <= 0) return;
+void launch_gather(const DevT<F>& d, hipStream_t st) {
+    if (d.contrib == nullptr || d.Hp <= 0) return;
     const int64_t threads = d.Hp * 64;
     hipLaunchKernelGGL(k_gather_n<F>, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256),
                        0, st, d.Hp, d.N, d.q_offset, d.member_offset, d.members, d.child_begin,
@@ -522,7 +531,7 @@ void launch_iteration(const DevT<F>& d, const int32_t* lo, const UpdateRule& rul
     }
     if (d.Hp > 0) {
         pre(K_INFOSET, -1, d.Hp);
-        launch_gather_n(d, st);
+        launch_gather(d, st);
         hipLaunchKernelGGL(k_infoset_update<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
                            d.q_offset, d.infoset_player, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T,
                            rule);
@@ -558,15 +567,19 @@ void launch_value_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st
         hipLaunchKernelGGL(k_value_level_n<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo,
                            hi, d.N, d.players, d.child_begin, d.node_player, d.node_edge, d.prob,
                            d.value, d.reach, d.contrib);
+    else if (d.contrib != nullptr)
+        hipLaunchKernelGGL((k_value_level<F, true>), dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st,
+                           lo, hi, d.N, d.child_begin, d.node_player, d.node_infoset, d.node_edge,
+                           d.prob, d.value, d.reach, d.rtilde, d.pibar, d.contrib);
     else
-        hipLaunchKernelGGL(k_value_level<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo, hi,
-                           d.N, d.child_begin, d.node_player, d.node_infoset, d.node_edge, d.prob,
-                           d.value, d.reach, d.rtilde, d.pibar);
+        hipLaunchKernelGGL((k_value_level<F, false>), dim3(blocks_for(hi - lo)), dim3(kBlock), 0,
+                           st, lo, hi, d.N, d.child_begin, d.node_player, d.node_infoset,
+                           d.node_edge, d.prob, d.value, d.reach, d.rtilde, d.pibar, d.contrib);
 }
 
 template <class F>
 void launch_infoset_pass(const DevT<F>& d, const UpdateRule& rule, hipStream_t st) {
-    launch_gather_n(d, st);
+    launch_gather(d, st);
     if (d.Hp > 0)
         hipLaunchKernelGGL(k_infoset_update<F>, dim3(blocks_for(d.Hp)), dim3(kBlock), 0, st, d.Hp,
                            d.q_offset, d.infoset_player, d.R, d.S, d.prob, d.rtilde, d.pibar, d.T,

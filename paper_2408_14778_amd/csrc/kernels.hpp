@@ -42,8 +42,11 @@ struct DevT {
     F* S;                   // Qp cumulative average-strategy weight
     F* rtilde;              // Qp accumulator (zero between iterations)
     F* pibar;               // Hp accumulator (zero between iterations)
-    F* contrib;             // players > 0: N, the regret contribution of each player node's
-                            //   child, summed per infoset by the gather pass
+    F* contrib;             // N, the regret contribution of each player node's child, summed
+                            //   per infoset by the gather pass: general-sum games and games whose
+                            //   infosets average more than 16 members (many atomic additions to
+                            //   one accumulator serialise); null: the value kernels add to rtilde
+                            //   and pibar by atomics
     F* value;               // N  expected payoff of player 1 (terminals hold the payoff);
                             //    players > 0: players * N, one column per player
     F* reach;               // 3N (pi_1, pi_2, pi_c) planes; players > 0: (players + 1) N

@@ -123,6 +123,9 @@ struct Sizes {
     bool packs = false;      // subtree packs (their records are on the device)
     bool fp64 = false;       // values, probabilities and state in double precision
     int32_t players = 0;     // general-sum game of n rational players (node engine), else 0
+    // node engine: regret contributions may be stored per child and gathered per infoset (false:
+    // always added by atomics, for the partitioned iteration's windows)
+    bool gather = true;
 };
 
 // Bounds on the subtree packs of a plan over N nodes, M members, Hp infosets and C chance nodes
@@ -156,6 +159,9 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
     d.N = N; d.Hp = Hp; d.Qp = Qp; d.H0 = H0; d.Q0 = Q0; d.M = M; d.D = D;
     // payoff and value columns and reach planes: one per rational player (and chance's plane);
     // a two-player zero-sum game keeps u_1 only
+    // regret contributions stored and gathered per infoset where atomics would contend: every
+    // general-sum game (its kernels store them) and infosets of more than 16 members on average
+    const bool store = z.gather && (z.players > 0 || M > 16 * Hp);
     const int64_t cols = z.players > 0 ? z.players : 1;
     const int64_t planes = (z.players > 0 ? z.players : 2) + 1;
     d.players = z.players;
@@ -204,7 +210,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         d64.br_value = c.take<double>(N);
         d64.stage = c.take<double>(2 * Qp);
         d64.rtilde = c.take<double>(Qp);
-        if (z.players > 0) d64.contrib = c.take<double>(N);
+        if (store) d64.contrib = c.take<double>(N);
         d64.pibar = c.take<double>(Hp);
         x = cfr::XDev{};
         return (c.off + 255) & ~size_t{255};
@@ -229,7 +235,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
     x = cfr::XDev{};
     if (z.engine == ENGINE_NODE) {
         d.rtilde = c.take<float>(Qp);
-        if (z.players > 0) d.contrib = c.take<float>(N);
+        if (store) d.contrib = c.take<float>(N);
         d.pibar = c.take<float>(Hp);
     } else {
         x.N = N; x.Hp = Hp; x.Qp = Qp; x.Q0 = Q0; x.M = M; x.L = z.L; x.C = z.C;
@@ -882,6 +888,7 @@ Sizes partitioned_sizes(const cfr::Layout& L, const cfr::PartPlan& P, bool fp64)
     z.terminals = 0; z.C = 0; z.L = z.N; z.D = L.D; z.max_actions = L.max_actions;
     z.engine = ENGINE_NODE;
     z.fp64 = fp64;
+    z.gather = false;
     return z;
 }
 

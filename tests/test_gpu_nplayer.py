@@ -143,3 +143,25 @@ def test_two_player_calls_are_refused():
     with pytest.raises(CfrError, match="CFR_EINVAL"):
         N.check(z._lib.cfr_get_node_values_n(z._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                              None, z.n_nodes))
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
+def test_two_player_gather_path_parity(variant, precision, tol):
+    """A two-player zero-sum game whose infosets average 40 members: the node engine stores the
+    regret contributions and gathers them per infoset (as for general-sum games) instead of
+    adding them by atomics. One iteration against the two-player oracle."""
+    from oracle.tree import Tree
+    from paper_2408_14778_amd import Solver
+    g = games.random_game(47, n_types=(40, 40), depth=4, deal="joint")
+    rational = g.infoset_player[g.node_infoset[g.node_infoset >= 0]] > 0
+    assert rational.sum() > 16 * int((g.infoset_player > 0).sum()), "infosets too small"
+    T, R, S = games.random_state(g, seed=3, nonnegative=(variant == "cfr+"))
+    s = Solver(g, variant, engine="node", precision=precision)
+    dt = np.float64 if precision == "f64" else np.float32
+    s.set_state(T, R.astype(dt), S.astype(dt))
+    s.iterate(1)
+    _, R2, S2 = s.get_state()
+    new, _ = cfr.iterate(Tree(g), cfr.State(T, [float(x) for x in R], [float(x) for x in S]),
+                         variant)
+    assert _rel(R2, new.R) <= tol and _rel(S2, new.S) <= tol
