@@ -322,7 +322,8 @@ def warm_start_eval(game_list) -> dict:
     if not (os.path.exists(wp.WEIGHTS_PATH) and os.path.exists(meta_path)):
         return {"skipped": "no trained network"}
     with open(meta_path) as f:
-        weight = json.load(f)["weight"]
+        meta = json.load(f)
+    weight = meta["weight"]
     net = ws.WarmStartNet(max_batch=65536)
     net.set_params(np.load(wp.WEIGHTS_PATH))
     log("warm start: evaluating plain vs warm on 512 held-out subgames")
@@ -333,7 +334,13 @@ def warm_start_eval(game_list) -> dict:
            "speedup": r["plain"]["seconds"] / r["warm"]["seconds"],
            "plain_mean_iterations": r["paired"]["mean_iterations_plain"],
            "warm_mean_iterations": r["paired"]["mean_iterations_warm"],
-           "warm_faster_subgames": r["paired"]["warm_faster"]}
+           "warm_faster_subgames": r["paired"]["warm_faster"],
+           "warm_slower_subgames": r["paired"]["warm_slower"],
+           "paired_iteration_ratio": {k: r["paired"][f"{k}_iteration_ratio"]
+                                      for k in ("geomean", "median", "p10", "p90")},
+           "seconds_until_solved_fraction": {"plain": r["plain"]["seconds_until_solved_fraction"],
+                                             "warm": r["warm"]["seconds_until_solved_fraction"]},
+           "targets": meta.get("targets", "strategy"), "weight": weight}
     log(f"warm start: {json.dumps(res)}")
     return res
 

@@ -37,7 +37,8 @@ WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning"
 
 
 def log(msg):
-    print(f"[warmstart] {msg}", flush=True)
+    # progress goes to stderr: a caller's stdout (bench.py's one JSON line) stays clean
+    print(f"[warmstart] {msg}", file=sys.stderr, flush=True)
 
 
 def _subgame(seed):
