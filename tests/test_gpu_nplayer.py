@@ -165,3 +165,34 @@ def test_two_player_gather_path_parity(variant, precision, tol):
     new, _ = cfr.iterate(Tree(g), cfr.State(T, [float(x) for x in R], [float(x) for x in S]),
                          variant)
     assert _rel(R2, new.R) <= tol and _rel(S2, new.S) <= tol
+
+
+@pytest.fixture(scope="module")
+def bench_game():
+    import bench
+    return games.random_game_n(**bench.NPLAYER_GAME)
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
+def test_bench_game_one_iteration_full_size(bench_game, precision, tol):
+    """The three-player game `bench.py --workload nplayer` times (2,127,169 nodes, a 1,728-way
+    root, infosets of about 180 members: the wide-level kernel and the wavefront gather), CFR+ as
+    timed, one iteration from a seeded state against the oracle over every pair and node."""
+    g = bench_game
+    T, R, S = games.random_state(g, seed=1, nonnegative=True)
+    s = _solver(g, "cfr+", precision)
+    dt = np.float64 if precision == "f64" else np.float32
+    s.set_state(T, R.astype(dt), S.astype(dt))
+    s.iterate(1)
+    _, R2, S2 = s.get_state()
+    vals, _ = s.node_values()
+    tree = cfr_n.TreeN(g)
+    new, info = cfr_n.iterate(tree, cfr.State(T, [float(x) for x in R], [float(x) for x in S]),
+                              "cfr+", record=True)
+    errs = {"R": _rel(R2, new.R), "S": _rel(S2, new.S)}
+    nid = s.layout("node_id")
+    ref_u = np.asarray([info["node_u"][v] for v in nid])
+    for i in range(g.n_players):
+        errs[f"u{i + 1}"] = _rel(vals[:, i], ref_u[:, i])
+    print(precision, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= tol, errs
