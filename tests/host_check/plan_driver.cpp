@@ -11,6 +11,7 @@
 // int32 infoset_num_actions[h], int64 n_chance, double chance_prob[n_chance],
 // double payoff_u1[n].
 #include <cstdint>
+#include <algorithm>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -160,20 +161,30 @@ int main(int argc, char** argv) {
     std::vector<cfr_game> gs;
     for (size_t i = 0; i < games.size(); ++i) {
         GameData& d = games[i];
-        gs.push_back(d.g);
-        cfr_host_layout* h = nullptr;
-        if (cfr_host_layout_create(&d.g, CFR_FLAG_SUBTREE_PACKS, &h) != CFR_OK) {
-            std::printf("game %zu: %s\n", i, cfr_last_error());
-            return 1;
+        // a game of more than two rational players: flattened with its player bound (as the
+        // general-sum build does) and partitioned; the public-block plan is for two players
+        int32_t max_player = 2;
+        for (int8_t pl : d.player) max_player = std::max<int32_t>(max_player, pl);
+        int arrays = 0;
+        if (max_player == 2) {
+            gs.push_back(d.g);
+            cfr_host_layout* h = nullptr;
+            if (cfr_host_layout_create(&d.g, CFR_FLAG_SUBTREE_PACKS, &h) != CFR_OK) {
+                std::printf("game %zu: %s\n", i, cfr_last_error());
+                return 1;
+            }
+            arrays = read_all(h);
+            cfr_host_layout_destroy(h);
         }
-        const int arrays = read_all(h);
-        cfr_host_layout_destroy(h);
         // the per-level tables the solver derives from a plan, with and without packs
         cfr::Layout L;
         std::string err;
-        if (cfr::flatten(d.g, L, err) != CFR_OK) return 1;
+        if (cfr::flatten(d.g, L, err, false, max_player) != CFR_OK) {
+            std::printf("game %zu: %s\n", i, err.c_str());
+            return 1;
+        }
         for (bool packs : {true, false}) {
-            if (!L.level_pure) break;
+            if (!L.level_pure || max_player > 2) break;
             cfr::ExecPlan P;
             if (cfr::build_exec_plan(L, P, err, packs) != CFR_OK) return 1;
             std::vector<int64_t> dec;
@@ -198,7 +209,8 @@ int main(int argc, char** argv) {
     }
     for (uint32_t flags : {0u, static_cast<uint32_t>(CFR_FLAG_SUBTREE_PACKS)}) {
         cfr_host_layout* h = nullptr;
-        if (cfr_host_layout_create_batch(gs.data(), n_games, flags, &h) != CFR_OK) {
+        const int32_t n_batch = static_cast<int32_t>(gs.size());  // the two-player games
+        if (cfr_host_layout_create_batch(gs.data(), n_batch, flags, &h) != CFR_OK) {
             std::printf("batch: %s\n", cfr_last_error());
             return 1;
         }
@@ -207,7 +219,7 @@ int main(int argc, char** argv) {
         std::vector<cfr::ExecPlan> plans;
         int32_t max_actions = 0;
         std::string err;
-        if (cfr::plan_games(gs.data(), n_games, plans, max_actions, err, flags != 0) != CFR_OK) return 1;
+        if (cfr::plan_games(gs.data(), n_batch, plans, max_actions, err, flags != 0) != CFR_OK) return 1;
         cfr::ExecPlan F;
         if (cfr::build_forest_plan(plans, F, err) != CFR_OK) return 1;
         std::vector<int64_t> dec;

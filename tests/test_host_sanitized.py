@@ -1,7 +1,8 @@
 """The host planners (flattening, the public-block plan with its subtree packs, the batch
 forest, the per-level tables the solver derives) built with the address and
 undefined-behaviour sanitizers, in a plain g++ build of their sources (they make no HIP calls),
-and run over the layout games and a batch of them. Any out-of-bounds access, use after free,
+and run over the layout games (two-player ones and general-sum ones of 3 and 4 players) and a
+batch of them. Any out-of-bounds access, use after free,
 leak or undefined operation ends the run with a report."""
 import os
 import shutil
@@ -30,6 +31,8 @@ def _games():
                              p_chance=0.05),
            games.random_game(43, n_types=(150, 3), depth=4, deal="joint")]
     out += [games.subgame(s) for s in (102, 103, 104, 109, 111, 113)]
+    # general-sum games of 3 and 4 players (flattened with their player bound, partitioned)
+    out += [games.kuhn3(), games.random_game_n(3, 3), games.random_game_n(7, 4, depth=5)]
     return out
 
 
