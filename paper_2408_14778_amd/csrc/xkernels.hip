@@ -59,12 +59,22 @@ __device__ __forceinline__ int32_t child_of(const int32_t* __restrict__ child_be
     return st != 0 ? cb + a * st : child_list[cb + a];
 }
 
+// A member record's child stride and k | player byte: with packed records (XDev::kp_packed) the
+// stride is the low 24 bits of the last word (signed) and the byte its top 8 bits; otherwise the
+// word is the stride and the byte comes from mem_kp.
+__device__ __forceinline__ int32_t rec_stride(int32_t w, int32_t packed) {
+    return packed ? static_cast<int32_t>(static_cast<uint32_t>(w) << 8) >> 8 : w;
+}
+__device__ __forceinline__ int rec_kp(int32_t w, int32_t packed, const int8_t* mem_kp, int32_t m) {
+    return packed ? static_cast<int>(static_cast<uint32_t>(w) >> 24) : mem_kp[m];
+}
+
 // ---- top-down (reach)
 
 // Reach of NPT nodes x = first + u * stride: the factor of whoever acted into the node (meta
 // bits 2-3) is multiplied by the edge probability (sigma or sigma_0). Terminal nodes need no
 // reach. All loads of the NPT nodes are issued before any of them is used, and a node's parent
-// and edge are loaded together with its kind. The chance plane depends on sigma_0 alone: FULL
+// and edge are loaded together with its kind (with edge_kind, both in one word). The chance plane depends on sigma_0 alone: FULL
 // computes all three planes (once, when the solver is set up); otherwise only the two player
 // planes are written, a chance edge copies them and the chance plane is left as it is.
 template <int NPT, bool FULL>
@@ -73,7 +83,8 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
                                             const int32_t* __restrict__ edge,
                                             const int8_t* __restrict__ meta,
                                             const float* __restrict__ prob,
-                                            float* __restrict__ reach) {
+                                            float* __restrict__ reach,
+                                            const int32_t* __restrict__ edge_kind = nullptr) {
     int64_t xs[NPT];
     int kind[NPT];
     int32_t p[NPT], e[NPT];
@@ -83,9 +94,15 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
         kind[u] = 0;
         p[u] = e[u] = 0;
         if (xs[u] < hi) {  // every node below the root has a parent and an edge
-            kind[u] = meta[xs[u]];
             p[u] = parent[xs[u]];
-            e[u] = edge[xs[u]];
+            if (edge_kind != nullptr) {  // the edge in the low 24 bits, the kind byte on top
+                const uint32_t w = static_cast<uint32_t>(edge_kind[xs[u]]);
+                kind[u] = static_cast<int>(w >> 24);
+                e[u] = static_cast<int32_t>(w & 0xFFFFFFu);
+            } else {
+                kind[u] = meta[xs[u]];
+                e[u] = edge[xs[u]];
+            }
         }
     }
     float r1[NPT], r2[NPT], rc[NPT], s[NPT];
@@ -123,11 +140,12 @@ __global__ void __launch_bounds__(1024) k_x_reach(int32_t t0, int64_t N,
                                                   const int32_t* __restrict__ edge,
                                                   const int8_t* __restrict__ meta,
                                                   const float* __restrict__ prob,
-                                                  float* __restrict__ reach) {
+                                                  float* __restrict__ reach,
+                                                  const int32_t* __restrict__ edge_kind) {
     const int32_t t = t0 + static_cast<int32_t>(xcd_tile());
     const int32_t lo = tile_lo[t], hi = tile_hi[t];
     reach_nodes<NPT, false>(lo + static_cast<int64_t>(threadIdx.x), blockDim.x, hi, N, parent, edge,
-                            meta, prob, reach);
+                            meta, prob, reach, edge_kind);
 }
 
 // Several small levels in one launch without a barrier between them: the node of each lane
@@ -242,6 +260,7 @@ struct UpArgs {
     // probability on the factor of whoever acted (the top-down products), computed and stored
     // here
     int32_t derive_reach;
+    int32_t kp_packed;  // member records carry the k | player byte (XDev::kp_packed)
     const int32_t* parent;
     const int32_t* edge;
     const int8_t* meta;
@@ -399,8 +418,8 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
                 x[u] = r.x;
                 q[u] = r.y;
                 cb[u] = r.z;
-                st[u] = r.w;
-                kp[u] = a.mem_kp[m];
+                st[u] = rec_stride(r.w, a.kp_packed);
+                kp[u] = rec_kp(r.w, a.kp_packed, a.mem_kp, m);
             }
         }
         float w[MPT][KMAX], sg[MPT][KMAX], r1[MPT], r2[MPT], rc[MPT];
@@ -442,8 +461,8 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
         for (int32_t mi = tid; mi < nm; mi += CH) {
             const int32_t m = m0 + mi;
             const int4 r = a.mem_rec[m];
-            const int32_t xm = r.x, qm = r.y, cbm = r.z, stm = r.w;
-            const int kpm = a.mem_kp[m];
+            const int32_t xm = r.x, qm = r.y, cbm = r.z, stm = rec_stride(r.w, a.kp_packed);
+            const int kpm = rec_kp(r.w, a.kp_packed, a.mem_kp, m);
             const int kk = kpm & 31;
             float w[KMAX];
             float v = 0.0f;
@@ -943,6 +962,7 @@ struct BrArgs {
     const float* avgprob;
     const float* br_reach;
     float* br_value;
+    int32_t kp_packed;  // member records carry the k | player byte (XDev::kp_packed)
 };
 
 // One level. Chunks (one thread per member): the acting player i's plane takes, per infoset,
@@ -999,8 +1019,8 @@ __global__ void __launch_bounds__(CH) k_x_br_level(BrArgs a, int32_t klo, int32_
             const int32_t m = m0 + tid;
             const int4 r = a.mem_rec[m];
             x = r.x;
-            const int32_t q = r.y, cb = r.z, st = r.w;
-            const int kp = a.mem_kp[m];
+            const int32_t q = r.y, cb = r.z, st = rec_stride(r.w, a.kp_packed);
+            const int kp = rec_kp(r.w, a.kp_packed, a.mem_kp, m);
             const int k = kp & 31;
             resp = (kp & 64) ? 1 : 0;
             const float pr = a.br_reach[resp * N + x];
@@ -1025,8 +1045,8 @@ __global__ void __launch_bounds__(CH) k_x_br_level(BrArgs a, int32_t klo, int32_
         for (int32_t mi = tid; mi < nm; mi += CH) {
             const int32_t m = m0 + mi;
             const int4 r = a.mem_rec[m];
-            const int32_t xm = r.x, q = r.y, cb = r.z, st = r.w;
-            const int kp = a.mem_kp[m];
+            const int32_t xm = r.x, q = r.y, cb = r.z, st = rec_stride(r.w, a.kp_packed);
+            const int kp = rec_kp(r.w, a.kp_packed, a.mem_kp, m);
             const int k = kp & 31;
             const int rp = (kp & 64) ? 1 : 0;
             const float pr = a.br_reach[rp * N + xm];
@@ -1085,8 +1105,8 @@ __global__ void __launch_bounds__(CH) k_x_br_level(BrArgs a, int32_t klo, int32_
         for (int32_t mi = tid; mi < nm; mi += CH) {
             const int32_t m = m0 + mi;
             const int4 r = a.mem_rec[m];
-            const int32_t xm = r.x, cb = r.z, st = r.w;
-            const int rp = (a.mem_kp[m] & 64) ? 1 : 0;
+            const int32_t xm = r.x, cb = r.z, st = rec_stride(r.w, a.kp_packed);
+            const int rp = (rec_kp(r.w, a.kp_packed, a.mem_kp, m) & 64) ? 1 : 0;
             const int32_t ch = st != 0 ? cb + b * st : a.child_list[cb + b];
             a.br_value[rp * N + xm] = a.br_value[rp * N + ch];
         }
@@ -1173,6 +1193,7 @@ UpArgs up_args(const XDev& x, const UpdateRule& rule) {
     a.T = x.T;
     a.rule = rule;
     a.derive_reach = 0;
+    a.kp_packed = x.kp_packed;
     a.parent = x.parent;
     a.edge = x.edge;
     a.meta = x.meta;
@@ -1211,19 +1232,20 @@ void launch_up(const XDev& x, const UpArgs& a, int32_t l, hipStream_t st) {
 void launch_reach_level(const XDev& x, int32_t l, hipStream_t st) {
     const int32_t t0 = x.t_level_offset_host[l], nt = x.t_level_offset_host[l + 1] - t0;
     if (nt == 0) return;
+    const int32_t* ek = x.ek_packed ? x.edge_kind : nullptr;
     const int threads = x.reach_threads_host[l];
     switch (x.reach_npt_host[l]) {
         case 2:
             hipLaunchKernelGGL(k_x_reach<2>, dim3(nt), dim3(threads), 0, st, t0, x.N, x.tile_lo,
-                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach);
+                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach, ek);
             break;
         case 4:
             hipLaunchKernelGGL(k_x_reach<4>, dim3(nt), dim3(threads), 0, st, t0, x.N, x.tile_lo,
-                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach);
+                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach, ek);
             break;
         default:
             hipLaunchKernelGGL(k_x_reach<1>, dim3(nt), dim3(threads), 0, st, t0, x.N, x.tile_lo,
-                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach);
+                               x.tile_hi, x.parent, x.edge, x.meta, x.prob, x.reach, ek);
             break;
     }
 }
@@ -1473,6 +1495,7 @@ void launch_x_best_response(const XDev& x, const float* avgprob, hipStream_t st)
     a.chunk_m = x.chunk_m;
     a.mem_rec = x.mem_rec;
     a.mem_kp = x.mem_kp;
+    a.kp_packed = x.kp_packed;
     a.set_rec = x.set_rec;
     a.child_begin = x.child_begin;
     a.child_stride = x.child_stride;

@@ -97,6 +97,10 @@ struct XDev {
     int32_t* parent;
     int32_t* edge;
     int8_t* meta;
+    // edge | meta << 24 per node (ek_packed = 1 when every edge index fits 24 bits): the per-level
+    // top-down launches read a node's edge and kind in one word
+    int32_t* edge_kind;
+    int32_t ek_packed;
     int32_t* child_begin;
     int32_t* child_stride;
     int32_t* child_list;
@@ -109,6 +113,9 @@ struct XDev {
     // k | (player 2 ? 64 : 0)
     int4* mem_rec;
     int8_t* mem_kp;
+    // 1: mem_rec.w holds the child stride in its low 24 bits (signed) and the k | player byte in
+    // its top byte (mem_kp is then read by the other kernels only)
+    int32_t kp_packed;
     // infoset records: {first pair, first member, end of members, k | (player 2 ? 64 : 0)}
     int4* set_rec;
     int32_t* chance_nodes;
