@@ -147,6 +147,61 @@ def measured_traffic(kernel: str):
     return rec.get(kernel, {}).get("bytes_per_launch")
 
 
+def write_traffic(fetch_csv: str, write_csv: str) -> dict:
+    """profiles/traffic_large_game.txt from two rocprofv3 counter runs of this script with
+    --calibrate-copy (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch): each counter is scaled
+    so that the calibration copy (2^28 floats read and written, 1 GiB each way) reads 1 GiB, then
+    averaged over the dispatches of each kernel family (block_reach: the top-down launches;
+    block_up: the bottom-up ones), with the SHA-256 of the kernel source they were taken on."""
+    import collections
+    import csv
+    import hashlib
+
+    def family(name):
+        if "k_x_up_level" in name or "k_x_up_top" in name:
+            return "block_up"
+        if "k_x_reach" in name and "k_x_reach_full" not in name:
+            return "block_reach"
+        return None
+
+    def read(path, counter):
+        per, calib = collections.defaultdict(list), []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                if "AUnaryFunctor" in r["Kernel_Name"] and int(r["Grid_Size"]) == 2**26:
+                    calib.append(v)
+                per[r["Kernel_Name"]].append(v)
+        if not calib:
+            raise SystemExit(f"{path}: no calibration copy (run with --calibrate-copy)")
+        return per, (2**30 / 1024) / (sum(calib) / len(calib))
+
+    fetch, fscale = read(fetch_csv, "FETCH_SIZE")
+    write, wscale = read(write_csv, "WRITE_SIZE")
+    agg = collections.defaultdict(lambda: [0, 0.0, 0.0])
+    for name in set(fetch) | set(write):
+        k = family(name)
+        if k is None:
+            continue
+        f, w = fetch.get(name, []), write.get(name, [])
+        a = agg[k]
+        a[0] += max(len(f), len(w))
+        a[1] += sum(f) * 1024 * fscale
+        a[2] += sum(w) * 1024 * wscale
+    src = "paper_2408_14778_amd/csrc/xkernels.hip"
+    with open(os.path.join(ROOT, src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    out = {k: {"dispatches": d, "bytes_per_launch": (fb + wb) / d, "fetch_bytes_per_launch": fb / d,
+               "write_bytes_per_launch": wb / d} for k, (d, fb, wb) in agg.items()}
+    out.update({"kernel_source": src, "kernel_source_sha256": sha,
+                "calibration": {"fetch_scale": fscale, "write_scale": wscale}})
+    with open(os.path.join(ROOT, "profiles", "traffic_large_game.txt"), "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def copy_bandwidth(mbytes: int = 1024, copies: int = 3, reps: int = 12) -> float:
     """GB/s of a plain elementwise copy (dst = src * 1) moving `mbytes` MB per launch (half read,
     half written), timed with hipEvents: the attainable bandwidth the roofline is read against.
@@ -406,10 +461,16 @@ def main() -> int:
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the second half of the metric: wall time to exploitability 1e-3 on "
                          "the 512 held-out subgames, zero start vs the stored warm-start network")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_large_game.txt from two rocprofv3 counter "
+                         "collections of this script run with --calibrate-copy, then exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain elementwise copy of 1 GiB (dst = src * 1) 3 times: a "
                          "kernel of known size for scaling hardware byte counters")
     args = ap.parse_args()
+    if args.write_traffic:
+        print(json.dumps(write_traffic(*args.write_traffic), indent=1))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding is a design, not part of this build.", file=sys.stderr)
