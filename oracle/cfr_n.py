@@ -23,6 +23,9 @@ One iteration with the simultaneous schedule:
    (the multiplied-out instantaneous regret and the own-reach player reach, as in the
    two-player oracle, where u_2 = -u_1 turns w_a[2] - u[2] into -(w_a[1] - u[1])).
 3.-5. The regret and average updates and T += 1, as in ``oracle.cfr.iterate``.
+
+The alternating schedule (``iterate_alternating``) makes a pass per player in seat order, each
+updating that player's infosets only, under the strategies the earlier passes produced.
 """
 from __future__ import annotations
 
@@ -43,9 +46,11 @@ class TreeN(Tree):
 
 
 def iterate(tree: TreeN, state: State, variant: str = VANILLA, record: bool = False,
-            dcfr=DCFR_DEFAULT):
+            dcfr=DCFR_DEFAULT, players=None, count: bool = True):
     """One simultaneous iteration. Returns (new_state, info) with sigma, r~, pibar, the root's
-    payoff vector and, if ``record``, per node its payoff vector and reach vector."""
+    payoff vector and, if ``record``, per node its payoff vector and reach vector. ``players``:
+    whose infosets the call updates (default all; the others keep R and S); ``count``: whether
+    it ends the iteration (T += 1)."""
     n_pl = tree.n_players
     sigma = current_strategy(tree, state.R)
     rt = [0.0] * tree.Q
@@ -101,6 +106,8 @@ def iterate(tree: TreeN, state: State, variant: str = VANILLA, record: bool = Fa
     if variant == DCFR:
         d_pos, d_neg, d_avg = dcfr_factors(state.T + 1, dcfr)
     for h in tree.rational:
+        if players is not None and tree.player[h] not in players:
+            continue
         o, k = tree.qoff[h], tree.nact[h]
         for a in range(k):
             q = o + a
@@ -121,7 +128,20 @@ def iterate(tree: TreeN, state: State, variant: str = VANILLA, record: bool = Fa
     if record:
         info["node_u"] = node_u
         info["node_reach"] = node_reach
-    return State(state.T + 1, R, S), info
+    return State(state.T + (1 if count else 0), R, S), info
+
+
+def iterate_alternating(tree: TreeN, state: State, variant: str = VANILLA, dcfr=DCFR_DEFAULT):
+    """One iteration of the alternating schedule for n players: a pass per player in seat order,
+    each updating only that player's infosets and seeing the strategies the earlier passes
+    produced, all with t = T + 1 (the two-player schedule of ``oracle.cfr`` extended to every
+    rational player). Returns (new_state, info of the last pass)."""
+    st = state
+    info = None
+    for i in range(1, tree.n_players + 1):
+        st, info = iterate(tree, st, variant, dcfr=dcfr, players=(i,),
+                           count=(i == tree.n_players))
+    return st, info
 
 
 def solve(tree: TreeN, iterations: int, variant: str = VANILLA, state: State | None = None,

@@ -149,3 +149,40 @@ def test_strictly_dominant_action_wins_the_average():
     avg = cfr.average_strategy(tree, st.S)
     o = tree.qoff[tree.rational[2]]
     assert avg[o] > 0.99
+
+
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+", "dcfr"])
+@pytest.mark.parametrize("make", [lambda: games.kuhn_like(3, "joint"),
+                                  lambda: games.leduc_like(3, 2, deal="sequential")])
+def test_two_player_alternating_is_the_two_player_oracle(make, variant):
+    """The n-pass alternating schedule on two-player zero-sum games is the two-player oracle's
+    alternating schedule."""
+    g = make()
+    t2, tn = Tree(g), cfr_n.TreeN(_as_general_sum(g))
+    T, R, S = games.random_state(g, seed=8, nonnegative=(variant == "cfr+"))
+    a = cfr.State(T, [float(x) for x in R], [float(x) for x in S])
+    b = a.copy()
+    for _ in range(3):
+        a, _ = cfr.iterate_alternating(t2, a, variant)
+        b, _ = cfr_n.iterate_alternating(tn, b, variant)
+    assert a.T == b.T
+    scale = max(1.0, max(abs(x) for x in a.R + a.S))
+    assert max(abs(x - y) for x, y in zip(a.R, b.R)) <= 1e-12 * scale
+    assert max(abs(x - y) for x, y in zip(a.S, b.S)) <= 1e-12 * scale
+
+
+def test_alternating_passes_update_one_player_each():
+    """On a three-player normal-form game, the first pass changes only player 1's regrets, the
+    second sees player 1's new strategy, and the iteration counts once."""
+    A, g = _normal_form_case((2, 3, 2), seed=5)
+    tree = cfr_n.TreeN(g)
+    T, R, S = games.random_state(g, seed=2)
+    st = cfr.State(T, [float(x) for x in R], [float(x) for x in S])
+    one, _ = cfr_n.iterate(tree, st, "vanilla", players=(1,), count=False)
+    assert one.T == T and one.R[2:] == st.R[2:] and one.R[:2] != st.R[:2]
+    full, _ = cfr_n.iterate_alternating(tree, st, "vanilla")
+    assert full.T == T + 1 and full.R[:2] == one.R[:2]
+    # the second pass plays player 1's updated strategy: its regrets for player 2 are those of a
+    # simultaneous iteration from the state after the first pass
+    two, _ = cfr_n.iterate(tree, one, "vanilla", players=(2,), count=False)
+    assert full.R[2:5] == two.R[2:5]
