@@ -247,14 +247,15 @@ int cfr_get_node_values_f64(cfr_solver* s, double* u1, double* reach, int64_t n_
  * payoff_u2 are ignored. payoff (host, n_nodes * n_players doubles, node-major in input node
  * order): u(t, i) at payoff[t * n_players + (i - 1)], read at terminals only and required
  * finite there. 2 <= n_players <= 8. The solver runs the node engine (FP32, or FP64 with
- * CFR_FLAG_FP64) with every player's infosets updated in one pass: at a node d of player i in
+ * CFR_FLAG_FP64) with every player's infosets updated in one pass (CFR_FLAG_ALTERNATING: a
+ * pass per player in seat order, each under the strategies the earlier passes produced, the
+ * iteration counted by the last): at a node d of player i in
  * infoset h the regret r~(h, a) gathers pi_{-i}(d) (w_a[i] - u[i]), pi_{-i} the product of
  * chance's and the other players' reaches, and u the node's payoff vector. cfr_iterate,
  * cfr_get_state / cfr_set_state, cfr_average_strategy, cfr_current_strategy (and their _f64
  * forms), cfr_get_layout and cfr_destroy apply unchanged. cfr_exploitability returns
  * CFR_EINVAL (Section 2.2 defines it for two-player zero-sum games), as do cfr_get_node_values
- * and cfr_set_launch_shape. Config: CFR_FLAG_ALTERNATING and CFR_FLAG_SUBTREE_PACKS give
- * CFR_EINVAL. Errors: those of cfr_plan / cfr_build, CFR_EINVAL for n_players out of range, a
+ * and cfr_set_launch_shape. Config: CFR_FLAG_SUBTREE_PACKS gives CFR_EINVAL. Errors: those of cfr_plan / cfr_build, CFR_EINVAL for n_players out of range, a
  * null payoff or a payoff that is not finite at a terminal. Workspace ownership as in
  * cfr_build. */
 int cfr_plan_n(const cfr_game* game, int32_t n_players, const double* payoff,

@@ -314,12 +314,14 @@ void launch_one_iteration(cfr_solver* s, hipStream_t st, cfr::LaunchTimer* timer
         pass(s->rule);
         return;
     }
-    cfr::UpdateRule first = s->rule, second = s->rule;
-    first.players = 1;
-    first.count = 0;
-    second.players = 2;
-    pass(first);
-    pass(second);
+    // a pass per rational player in seat order, the iteration counted by the last
+    const int32_t n = s->players > 0 ? s->players : 2;
+    for (int32_t i = 1; i <= n; ++i) {
+        cfr::UpdateRule r = s->rule;
+        r.players = 1 << (i - 1);
+        r.count = i == n ? s->rule.count : 0;
+        pass(r);
+    }
 }
 
 int capture(cfr_solver* s) {
@@ -434,13 +436,12 @@ int game_n(const cfr_game* game, int32_t players, const double* payoff, GameN& o
     return CFR_OK;
 }
 
-// A general-sum solver runs the node engine with the simultaneous schedule.
+// A general-sum solver runs the node engine (no subtree packs).
 int check_config_n(const cfr_config* c) {
     if (const int rc = check_config(c); rc != CFR_OK) return rc;
-    if (c != nullptr && (c->flags & (CFR_FLAG_ALTERNATING | CFR_FLAG_SUBTREE_PACKS)))
-        return set_err(CFR_EINVAL, "a general-sum game runs the node engine with simultaneous "
-                                   "updates: CFR_FLAG_ALTERNATING and CFR_FLAG_SUBTREE_PACKS do not "
-                                   "apply");
+    if (c != nullptr && (c->flags & CFR_FLAG_SUBTREE_PACKS))
+        return set_err(CFR_EINVAL, "a general-sum game runs the node engine: "
+                                   "CFR_FLAG_SUBTREE_PACKS does not apply");
     return CFR_OK;
 }
 
@@ -736,7 +737,7 @@ int payoff_planes(const cfr::Layout& L, int32_t players, const double* payoff, s
 }
 
 // cfr_build for a two-player zero-sum game (players = 0) or a general-sum game of `players`
-// with its payoff matrix (the node engine, every player's infosets updated in one pass).
+// with its payoff matrix (the node engine; simultaneous or, alternating, a pass per player).
 int build_impl(const cfr_game* game, const cfr_config& cfg, int32_t players, const double* payoff,
                void* workspace, size_t bytes, void* stream, cfr_solver** out) {
     cfr::Layout L;

@@ -353,12 +353,14 @@ class Solver:
 class NPlayerSolver(Solver):
     """CFR over a general-sum game of n rational players (``game.payoff``: one payoff column
     per player, Section 3.1) on the node engine, through cfr_plan_n / cfr_build_n: vanilla,
-    CFR+ or discounted, every player's infosets updated in one pass, precision 'f32' or 'f64'.
+    CFR+ or discounted, every player's infosets updated in one pass (``schedule``
+    'simultaneous') or a pass per player in seat order ('alternating'), precision 'f32' or 'f64'.
     State, strategies and iteration work as in Solver; exploitability() raises (it is defined
     for two-player zero-sum games), and node_values() returns every player's value column."""
 
     def __init__(self, game, variant: str = "vanilla", averaging=None, device: str = "cuda",
-                 graph: bool = True, stream=None, dcfr=None, precision: str = "f32"):
+                 graph: bool = True, stream=None, dcfr=None, precision: str = "f32",
+                 schedule: str = "simultaneous"):
         import torch
 
         if game.payoff is None:
@@ -369,7 +371,7 @@ class NPlayerSolver(Solver):
         args = GameArgs(game)
         self._payoff = np.ascontiguousarray(game.payoff, dtype=np.float64)
         self.n_players = int(self._payoff.shape[1])
-        cfg = make_config(variant, averaging, graph, "node", dcfr, precision=precision)
+        cfg = make_config(variant, averaging, graph, "node", dcfr, schedule, precision=precision)
         info = N.CfrPlanInfo()
         pay = _ptr(self._payoff, ctypes.c_double)
         N.check(self._lib.cfr_plan_n(ctypes.byref(args.struct), self.n_players, pay,

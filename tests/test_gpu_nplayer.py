@@ -90,6 +90,26 @@ def test_one_iteration_parity(name, variant, precision, tol):
         np.testing.assert_allclose(sig2[o:o + k], ref_sig[o:o + k], rtol=0, atol=10 * tol)
 
 
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+", "dcfr"])
+@pytest.mark.parametrize("name", ["kuhn3", "rand4", "rand5", "nf3"])
+def test_alternating_one_iteration_parity(name, variant, precision, tol):
+    """The alternating schedule: a pass per player in seat order, each under the strategies the
+    earlier passes produced, against the oracle's n-pass iteration."""
+    from paper_2408_14778_amd import NPlayerSolver
+    g = GAMES[name]()
+    T, R, S = games.random_state(g, seed=len(name) + 9, nonnegative=(variant == "cfr+"))
+    s = NPlayerSolver(g, variant, precision=precision, schedule="alternating")
+    dt = np.float64 if precision == "f64" else np.float32
+    s.set_state(T, R.astype(dt), S.astype(dt))
+    s.iterate(1)
+    T2, R2, S2 = s.get_state()
+    new, _ = cfr_n.iterate_alternating(
+        cfr_n.TreeN(g), cfr.State(T, [float(x) for x in R], [float(x) for x in S]), variant)
+    assert T2 == T + 1
+    assert _rel(R2, new.R) <= tol and _rel(S2, new.S) <= tol, (_rel(R2, new.R), _rel(S2, new.S))
+
+
 @pytest.mark.parametrize("name,variant,iters", [("kuhn3", "cfr+", 300), ("rand4", "vanilla", 200),
                                                 ("nf3", "dcfr", 200)])
 def test_fp64_after_T_iterations(name, variant, iters):
@@ -145,25 +165,27 @@ def test_two_player_calls_are_refused():
                                              None, z.n_nodes))
 
 
+@pytest.mark.parametrize("schedule", ["simultaneous", "alternating"])
 @pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
 @pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
-def test_two_player_gather_path_parity(variant, precision, tol):
+def test_two_player_gather_path_parity(variant, precision, tol, schedule):
     """A two-player zero-sum game whose infosets average 40 members: the node engine stores the
     regret contributions and gathers them per infoset (as for general-sum games) instead of
-    adding them by atomics. One iteration against the two-player oracle."""
+    adding them by atomics. One iteration against the two-player oracle, with both schedules
+    (the alternating one gathers once per pass)."""
     from oracle.tree import Tree
     from paper_2408_14778_amd import Solver
     g = games.random_game(47, n_types=(40, 40), depth=4, deal="joint")
     rational = g.infoset_player[g.node_infoset[g.node_infoset >= 0]] > 0
     assert rational.sum() > 16 * int((g.infoset_player > 0).sum()), "infosets too small"
     T, R, S = games.random_state(g, seed=3, nonnegative=(variant == "cfr+"))
-    s = Solver(g, variant, engine="node", precision=precision)
+    s = Solver(g, variant, engine="node", precision=precision, schedule=schedule)
     dt = np.float64 if precision == "f64" else np.float32
     s.set_state(T, R.astype(dt), S.astype(dt))
     s.iterate(1)
     _, R2, S2 = s.get_state()
-    new, _ = cfr.iterate(Tree(g), cfr.State(T, [float(x) for x in R], [float(x) for x in S]),
-                         variant)
+    step = cfr.iterate_alternating if schedule == "alternating" else cfr.iterate
+    new, _ = step(Tree(g), cfr.State(T, [float(x) for x in R], [float(x) for x in S]), variant)
     assert _rel(R2, new.R) <= tol and _rel(S2, new.S) <= tol
 
 
