@@ -59,6 +59,18 @@ __device__ __forceinline__ int32_t child_of(const int32_t* __restrict__ child_be
     return st != 0 ? cb + a * st : child_list[cb + a];
 }
 
+// A 16-byte record read once per iteration, loaded with the non-temporal hint. The member and
+// infoset records of the bottom-up pass and the parent and edge words of the top-down pass are
+// streamed once per iteration; with the hint they stop displacing, from the caches, the values,
+// reaches and strategies that the next launches read again (the large-game iteration: 247.7 to
+// 224-226 us). The same hint on the reaches, the children's values or the regret and strategy
+// sums made it slower: those lines are read again.
+__device__ __forceinline__ int4 nt_load4(const int4* p) {
+    typedef int v4 __attribute__((ext_vector_type(4)));
+    const v4 v = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
 // A member record's child stride and k | player byte: with packed records (XDev::kp_packed) the
 // stride is the low 24 bits of the last word (signed) and the byte its top 8 bits; otherwise the
 // word is the stride and the byte comes from mem_kp.
@@ -94,9 +106,9 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
         kind[u] = 0;
         p[u] = e[u] = 0;
         if (xs[u] < hi) {  // every node below the root has a parent and an edge
-            p[u] = parent[xs[u]];
+            p[u] = __builtin_nontemporal_load(&parent[xs[u]]);
             if (edge_kind != nullptr) {  // the edge in the low 24 bits, the kind byte on top
-                const uint32_t w = static_cast<uint32_t>(edge_kind[xs[u]]);
+                const uint32_t w = static_cast<uint32_t>(__builtin_nontemporal_load(&edge_kind[xs[u]]));
                 kind[u] = static_cast<int>(w >> 24);
                 e[u] = static_cast<int32_t>(w & 0xFFFFFFu);
             } else {
@@ -398,7 +410,7 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
     int player = 1;
     float pr[KMAX], ps[KMAX], pp[KMAX];
     if (tid < nh) {
-        const int4 hr = a.set_rec[h0 + tid];
+        const int4 hr = nt_load4(&a.set_rec[h0 + tid]);
         o = hr.x;
         slo = hr.y - m0;
         shi = hr.z - m0;
@@ -414,7 +426,7 @@ __device__ __forceinline__ void up_chunk(const UpArgs& a, int32_t c, float (*s_c
             x[u] = q[u] = cb[u] = st[u] = kp[u] = 0;
             if (mi < nm) {
                 const int32_t m = m0 + mi;
-                const int4 r = a.mem_rec[m];
+                const int4 r = nt_load4(&a.mem_rec[m]);
                 x[u] = r.x;
                 q[u] = r.y;
                 cb[u] = r.z;
