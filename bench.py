@@ -429,7 +429,7 @@ def cpu_baseline(seconds_min: float = 10.0) -> dict:
         iters += 1
     dt = time.perf_counter() - t0
     return {"value": g.n_nodes * iters / dt, "unit": "node-updates/s", "cores": 1,
-            "kind": "oracle", "cpu": cpu_model(),
+            "kind": "oracle", "sampled": True, "cpu": cpu_model(),
             "sample": f"{iters} CFR+ iterations of the recursive FP64 oracle on the first 16 of "
                       f"156 deals of the same game ({g.n_nodes} nodes); host {cpu_model()}, "
                       f"os.cpu_count()={os.cpu_count()}"}
