@@ -9,6 +9,9 @@ with I+ = {1, ..., n}; Section 3.1 gives the payoff matrix one column per ration
   players act in seat order with check or bet 1 until someone bets, after which every other
   player, in seat order from the bettor, calls or folds; the highest rank among the players
   still in takes the pot. Zero-sum (the payoffs of a terminal add up to 0);
+* ``with_silent_players``: a two-player zero-sum game's tree with its payoffs as the columns
+  (u_1, -u_1) and one seeded column per extra player who owns no infoset (a rational player
+  who never moves: only the payoff recurrence carries that player's column);
 * ``random_game_n``: chance deals every player a private type (one joint chance node), then a
   random public tree of player, chance and terminal nodes follows; an infoset is (player, own
   type, public history), so the game has perfect recall and level-pure infosets. Every
@@ -107,6 +110,22 @@ def kuhn3(ranks: int = 4, deal: str = "sequential") -> Game:
     else:
         raise ValueError(deal)
     return b.build(kind="kuhn3", ranks=ranks, deal=deal, players=n)
+
+
+def with_silent_players(game: Game, extra: int, seed: int) -> Game:
+    """The tree of the two-player zero-sum ``game`` as a general-sum game of 2 + ``extra``
+    players: columns u_1, -u_1, then ``extra`` columns of multiples of 1/64 in [-1, 1] at the
+    terminals (0 at decision nodes). Players 3 .. 2 + extra own no infoset."""
+    from dataclasses import replace
+    rng = np.random.default_rng(seed)
+    n = len(game.parent)
+    term = game.node_infoset < 0
+    cols = [game.payoff_u1, -game.payoff_u1]
+    for _ in range(extra):
+        cols.append(np.where(term, rng.integers(-64, 65, size=n) / 64.0, 0.0))
+    meta = dict(game.meta, players=2 + extra)
+    return replace(game, name=f"{game.name}_silent{extra}", payoff=np.stack(cols, axis=1),
+                   payoff_u2=None, meta=meta)
 
 
 def random_game_n(seed: int, n_players: int = 3, n_types: int = 2, depth: int = 4,

@@ -294,3 +294,37 @@ def test_nplayer_plan_validation():
     assert plan_n(3, cfg=make_config("cfr+", engine="node", schedule="alternating"))[0] == 0
     info = N.CfrPlanInfo()
     assert lib.cfr_plan(ctypes.byref(args.struct), None, ctypes.byref(info)) == EINVAL
+
+
+def test_nplayer_plan_edges():
+    """cfr_plan_n at the edges: eight players (the most) plan, the same game as seven is refused
+    (an infoset of player 8), a silent player (no infosets) is accepted, and a game of one
+    terminal node plans with no infosets and depth 0."""
+    import ctypes
+
+    import numpy as np
+
+    from paper_2408_14778_amd import _native as N
+    from paper_2408_14778_amd.solver import GameArgs, _ptr
+
+    lib = N.load()
+
+    def plan_n(g, n):
+        args = GameArgs(g)
+        pay = np.ascontiguousarray(g.payoff)
+        info = N.CfrPlanInfo()
+        rc = lib.cfr_plan_n(ctypes.byref(args.struct), n, _ptr(pay, ctypes.c_double), None,
+                            ctypes.byref(info))
+        return rc, info
+
+    g8 = games.random_game_n(seed=26, n_players=8, n_types=2, depth=6, max_actions=2,
+                             p_terminal=0.15, p_chance=0.1)
+    rc, info = plan_n(g8, 8)
+    assert rc == 0 and info.engine == 0 and info.n_nodes == 9729
+    assert plan_n(g8, 7)[0] == -1  # CFR_EINVAL
+    rc, info = plan_n(games.with_silent_players(games.kuhn_like(3, "joint"), 6, seed=1), 8)
+    assert rc == 0 and info.n_nodes == 55
+    b = games.GameBuilder("single3")
+    b.terminal_vec(b.node(-1, -1), [0.25, -0.5, 1.0])
+    rc, info = plan_n(b.build(players=3), 3)
+    assert rc == 0 and info.n_nodes == 1 and info.n_infosets == 0 and info.depth == 0

@@ -10,7 +10,10 @@ the mathematics fix, not against itself:
   the weight times the number of the infoset's nodes times sigma;
 * the root's payoff vector is the expected payoff summed over terminals by path probability;
 * three-player Kuhn is zero-sum, so the players' values add up to 0 under any strategy;
-* a strictly dominant action wins the average strategy.
+* a strictly dominant action wins the average strategy;
+* players who own no infoset change nothing for the others: the first two players' updates are
+  the two-player oracle's on the same tree, at 3 and at 8 (the most) players;
+* a game that is one terminal node has its payoff vector as the root's value and no state.
 """
 import json
 import os
@@ -23,6 +26,11 @@ from oracle import cfr, cfr_n
 from oracle.tree import Tree
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+
+# eight players (the most the GPU path takes), each with two private types: a 256-way deal and
+# infosets of up to 128 members; every player owns infosets
+RANDOM8 = dict(seed=26, n_players=8, n_types=2, depth=6, max_actions=2, p_terminal=0.15,
+               p_chance=0.1)
 
 
 def test_kuhn3_matches_the_paper_table():
@@ -73,7 +81,7 @@ def _normal_form_case(shape, seed):
 
 
 @pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
-@pytest.mark.parametrize("shape", [(3, 4), (2, 3, 2), (2, 2, 3, 2)])
+@pytest.mark.parametrize("shape", [(3, 4), (2, 3, 2), (2, 2, 3, 2), (1, 1, 3), (2,) * 8])
 def test_normal_form_regrets_are_the_closed_form(shape, variant):
     A, g = _normal_form_case(shape, seed=len(shape) * 7 + shape[0])
     n = len(shape)
@@ -104,7 +112,8 @@ def test_normal_form_regrets_are_the_closed_form(shape, variant):
 
 
 @pytest.mark.parametrize("make", [lambda: games.kuhn3(), lambda: games.random_game_n(3, 3),
-                                  lambda: games.random_game_n(7, 4, depth=5)])
+                                  lambda: games.random_game_n(7, 4, depth=5),
+                                  lambda: games.random_game_n(**RANDOM8)])
 def test_root_value_is_the_expected_payoff_by_enumeration(make):
     g = make()
     tree = cfr_n.TreeN(g)
@@ -186,3 +195,39 @@ def test_alternating_passes_update_one_player_each():
     # simultaneous iteration from the state after the first pass
     two, _ = cfr_n.iterate(tree, one, "vanilla", players=(2,), count=False)
     assert full.R[2:5] == two.R[2:5]
+
+
+@pytest.mark.parametrize("variant", ["vanilla", "cfr+", "dcfr"])
+@pytest.mark.parametrize("extra", [1, 6])
+def test_silent_players_leave_the_two_player_game_unchanged(extra, variant):
+    """A rational player who owns no infoset never multiplies an edge into anyone's reach (its
+    plane stays 1), so with u_2 = -u_1 the first two players' regrets and strategy sums are the
+    two-player oracle's on the same tree, exactly; every silent player's root value is its
+    payoff's expectation under the profile (summed over terminals by path probability)."""
+    g2 = games.kuhn_like(3, "joint")
+    g = games.with_silent_players(g2, extra, seed=6)
+    assert g.n_players == 2 + extra and set(g.infoset_player.tolist()) == {0, 1, 2}
+    t2, tn = Tree(g2), cfr_n.TreeN(g)
+    T, R, S = games.random_state(g2, seed=5, nonnegative=(variant == "cfr+"))
+    a = cfr.State(T, [float(x) for x in R], [float(x) for x in S])
+    b = a.copy()
+    for _ in range(3):
+        a, ia = cfr.iterate(t2, a, variant)
+        b, ib = cfr_n.iterate(tn, b, variant)
+        assert ib["root_value"][0] == pytest.approx(ia["root_value"], abs=1e-12)
+        ev = cfr_n.expected_values(tn, ib["sigma"])
+        assert ib["root_value"][2:] == pytest.approx(ev[2:], abs=1e-12)
+    assert a.T == b.T
+    scale = max(1.0, max(abs(x) for x in a.R + a.S))
+    assert max(abs(x - y) for x, y in zip(a.R, b.R)) <= 1e-12 * scale
+    assert max(abs(x - y) for x, y in zip(a.S, b.S)) <= 1e-12 * scale
+
+
+def test_single_terminal_game():
+    b = games.GameBuilder("single3")
+    b.terminal_vec(b.node(-1, -1), [0.25, -0.5, 1.0])
+    g = b.build(players=3)
+    tree = cfr_n.TreeN(g)
+    st, info = cfr_n.iterate(tree, cfr.State.zeros(tree), "cfr+", record=True)
+    assert info["root_value"] == [0.25, -0.5, 1.0]
+    assert st.T == 1 and st.R == [] and st.S == []
