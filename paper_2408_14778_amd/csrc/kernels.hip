@@ -15,8 +15,11 @@ namespace cfr {
 namespace {
 
 constexpr int kBlock = 256;
-// Levels of at most this many nodes run the general-sum values one wavefront per node.
+// Levels of at most this many nodes run the general-sum values one wavefront per node, and of at
+// most kWideTop nodes (a root dealing many private types, the levels just below it) a
+// workgroup of 1024 per node.
 constexpr int32_t kWideNodes = 4096;
+constexpr int32_t kWideTop = 16;
 
 inline unsigned blocks_for(int64_t n) {
     return static_cast<unsigned>((n + kBlock - 1) / kBlock);
@@ -198,16 +201,17 @@ __global__ void k_reach_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
 
 // Bottom-up values of one level: every player's column u_i = sum_a s_a w_a[i]; at a node d of
 // player i, each child's regret contribution pi_{-i}(d) (w_a[i] - u_i), with pi_{-i} = pi_c times
-// the other players' planes in player order, is stored at the child's slot (no atomics: an
-// infoset of a general-sum game can have many members, whose additions to one accumulator would
-// serialise); k_gather_n sums them per infoset.
+// the other players' planes in player order, then d's own reach pi_i(d), are stored at d's
+// member-order slot (node_slot: one short contiguous run per node; no atomics: an infoset of a
+// general-sum game can have many members, whose additions to one accumulator would serialise);
+// k_gather_slots sums them per infoset.
 template <class F>
 __global__ void k_value_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
                                 const int32_t* __restrict__ child_begin,
                                 const int8_t* __restrict__ node_player,
                                 const int32_t* __restrict__ node_edge, const F* __restrict__ prob,
-                                F* __restrict__ value, const F* __restrict__ reach,
-                                F* __restrict__ contrib) {
+                                const int32_t* __restrict__ node_slot, F* __restrict__ value,
+                                const F* __restrict__ reach, F* __restrict__ contrib) {
     const int64_t p = lo + gid();
     if (p >= hi) return;
     const int8_t who = node_player[p];
@@ -225,75 +229,187 @@ __global__ void k_value_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
     F cf = reach[P * N + p];
     for (int32_t j = 0; j < P; ++j)
         if (j != me) cf *= reach[j * N + p];
-    for (int32_t c = c0; c < c1; ++c) contrib[c] = cf * (value[me * N + c] - own_u);
+    F* slot = contrib + node_slot[p];
+    for (int32_t c = c0; c < c1; ++c) slot[c - c0] = cf * (value[me * N + c] - own_u);
+    slot[c1 - c0] = reach[me * N + p];
 }
 
-// k_value_level_n for a level of few nodes, one wavefront per node: lane l takes children
-// l, l + 64, ... and the lanes' partial sums are added by a fixed butterfly (a node with a wide
-// fan-out, such as a root dealing thousands of private-type combinations, would otherwise walk
-// its children on one thread).
-template <class F>
-__global__ void __launch_bounds__(256) k_value_wide_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
-                                                      const int32_t* __restrict__ child_begin,
-                                                      const int8_t* __restrict__ node_player,
-                                                      const int32_t* __restrict__ node_edge,
-                                                      const F* __restrict__ prob,
-                                                      F* __restrict__ value,
-                                                      const F* __restrict__ reach,
-                                                      F* __restrict__ contrib) {
-    const int64_t p = lo + ((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
-    const int lane = threadIdx.x & 63;
-    if (p >= hi) return;  // whole wavefronts leave together
+// k_value_level_n for a level of few nodes, W wavefronts per node: thread t takes children
+// t, t + 64 W, ..., summing every player's column in the one walk over them; the partial sums
+// are added by a fixed butterfly in each wavefront, then over the wavefronts in order (a node
+// with a wide fan-out, such as a root dealing thousands of private-type combinations, would
+// otherwise walk its children on one thread). W = 1: a workgroup of 256 holds four nodes, one
+// per wavefront; W > 1: the workgroup is the node's (grid = the level's node count).
+template <class F, int W>
+__global__ void __launch_bounds__(W == 1 ? 256 : 64 * W)
+    k_value_wide_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
+                   const int32_t* __restrict__ child_begin, const int8_t* __restrict__ node_player,
+                   const int32_t* __restrict__ node_edge, const F* __restrict__ prob,
+                   const int32_t* __restrict__ node_slot, F* __restrict__ value,
+                   const F* __restrict__ reach, F* __restrict__ contrib) {
+    constexpr int kT = 64 * W;  // threads per node
+    const int tid = W == 1 ? static_cast<int>(threadIdx.x & 63) : static_cast<int>(threadIdx.x);
+    const int64_t p = W == 1 ? lo + ((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6)
+                             : lo + static_cast<int64_t>(blockIdx.x);
+    if (p >= hi) return;  // whole wavefronts (W = 1) or the whole workgroup (W > 1) leave together
     const int8_t who = node_player[p];
     if (who < 0) return;
     const int32_t c0 = child_begin[p], c1 = child_begin[p + 1];
+    F u[kMaxPlayers];
+#pragma unroll
+    for (int i = 0; i < kMaxPlayers; ++i) u[i] = F(0);
+    for (int32_t c = c0 + tid; c < c1; c += kT) {
+        const F s = prob[node_edge[c]];
+#pragma unroll
+        for (int i = 0; i < kMaxPlayers; ++i)
+            if (i < P) u[i] = fma_(s, value[i * N + c], u[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxPlayers; ++i)
+        if (i < P)
+            for (int off = 32; off > 0; off >>= 1) u[i] += __shfl_xor(u[i], off, 64);
     F own_u = F(0);
-    for (int32_t i = 0; i < P; ++i) {
-        F u = F(0);
-        for (int32_t c = c0 + lane; c < c1; c += 64)
-            u = fma_(prob[node_edge[c]], value[i * N + c], u);
-        for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
-        if (lane == 0) value[i * N + p] = u;
-        if (i == who - 1) own_u = u;
+    if constexpr (W == 1) {
+        if (tid == 0)
+            for (int32_t i = 0; i < P; ++i) value[i * N + p] = u[i];
+#pragma unroll
+        for (int i = 0; i < kMaxPlayers; ++i)
+            if (i == who - 1) own_u = u[i];
+    } else {
+        __shared__ F s_part[W][kMaxPlayers];
+        __shared__ F s_u[kMaxPlayers];
+        const int wave = tid >> 6;
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int i = 0; i < kMaxPlayers; ++i) s_part[wave][i] = u[i];
+        __syncthreads();
+        if (tid < P) {
+            F sum = F(0);
+#pragma unroll
+            for (int w = 0; w < W; ++w) sum += s_part[w][tid];
+            value[tid * N + p] = sum;
+            s_u[tid] = sum;
+        }
+        __syncthreads();
+        if (who > 0) own_u = s_u[who - 1];
     }
     if (who == 0) return;
     const int32_t me = who - 1;
     F cf = reach[P * N + p];
     for (int32_t j = 0; j < P; ++j)
         if (j != me) cf *= reach[j * N + p];
-    for (int32_t c = c0 + lane; c < c1; c += 64) contrib[c] = cf * (value[me * N + c] - own_u);
+    F* slot = contrib + node_slot[p];
+    for (int32_t c = c0 + tid; c < c1; c += kT) slot[c - c0] = cf * (value[me * N + c] - own_u);
+    if (tid == 0) slot[c1 - c0] = reach[me * N + p];
 }
 
-// Per infoset, one wavefront: r~(h, a) = the sum over the members d of their action-a child's
-// contribution, and pibar(h) = the sum of the members' own reaches (Eq. player_reach_probability,
-// own-reach reading); lane l takes members l, l + 64, ... in member order and the lanes' partial
-// sums are added by a fixed butterfly, so the result does not depend on scheduling. Written
-// over the accumulators the infoset update reads (and clears).
-template <class F>
-__global__ void __launch_bounds__(256) k_gather_n(int64_t Hp, int64_t N,
-                                                  const int32_t* __restrict__ q_offset,
-                                                  const int32_t* __restrict__ member_offset,
-                                                  const int32_t* __restrict__ members,
-                                                  const int32_t* __restrict__ child_begin,
-                                                  const int8_t* __restrict__ infoset_player,
-                                                  const F* __restrict__ reach,
-                                                  const F* __restrict__ contrib,
-                                                  F* __restrict__ rtilde, F* __restrict__ pibar) {
-    const int64_t h = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (h >= Hp) return;  // whole wavefronts leave together
+// Per infoset of a general-sum game, one workgroup of W wavefronts sums its members' slots
+// (node_slot: k + 1 values per member, the infoset's members contiguous): r~(h, a) = the sum of
+// the members' action-a contributions, pibar(h) = the sum of their own reaches (Eq.
+// player_reach_probability, own-reach reading). Thread t takes members t, t + 64 W, ..., up to
+// kGatherActions of the k + 1 sums at once; the partial sums are added by a fixed butterfly in
+// each wavefront, then over the wavefronts in order, so the result does not depend on
+// scheduling. Written over the accumulators the infoset update reads (and clears). Grid: one
+// workgroup per infoset.
+constexpr int kGatherActions = 4;
+
+template <class F, int W>
+__global__ void __launch_bounds__(64 * W) k_gather_slots(int64_t Hp,
+                                                        const int32_t* __restrict__ q_offset,
+                                                        const int32_t* __restrict__ member_offset,
+                                                        const int32_t* __restrict__ slot_base,
+                                                        const F* __restrict__ contrib,
+                                                        F* __restrict__ rtilde,
+                                                        F* __restrict__ pibar) {
+    constexpr int kT = 64 * W, KB = kGatherActions;
+    __shared__ F s_part[W][KB];
+    const int64_t h = blockIdx.x;
+    if (h >= Hp) return;  // the whole workgroup leaves together
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int32_t o = q_offset[h], k = q_offset[h + 1] - o;
+    const int32_t n = member_offset[h + 1] - member_offset[h];
+    const F* slots = contrib + slot_base[h];
+    for (int32_t r0 = 0; r0 <= k; r0 += KB) {  // sums 0 .. k
+        F acc[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] = F(0);
+        for (int32_t m = tid; m < n; m += kT)
+#pragma unroll
+            for (int j = 0; j < KB; ++j)
+                if (r0 + j <= k) acc[j] += slots[m * (k + 1) + r0 + j];
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, 64);
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int j = 0; j < KB; ++j) s_part[wave][j] = acc[j];
+        __syncthreads();
+        if (tid < KB && r0 + tid <= k) {
+            F sum = F(0);
+#pragma unroll
+            for (int w = 0; w < W; ++w) sum += s_part[w][tid];
+            if (r0 + tid < k) rtilde[o + r0 + tid] = sum;
+            else pibar[h] = sum;
+        }
+        __syncthreads();  // s_part is reused by the next sums
+    }
+}
+
+// The two-player node engine's gather (contributions at each child's slot, k_value_level with
+// kStore). Per infoset, one workgroup of W wavefronts: r~(h, a) = the sum over the members d of
+// their action-a child's contribution, and pibar(h) = the sum of the members' own reaches (Eq.
+// player_reach_probability, own-reach reading). Thread t takes members t, t + 64 W, ... in member
+// order, each member's node and child offset loaded once for up to kGatherActions actions; the
+// partial sums are added by a fixed butterfly in each wavefront, then over the wavefronts in
+// order, so the result does not depend on scheduling. An infoset of more actions walks its
+// members once per kGatherActions. Written over the accumulators the infoset update reads (and
+// clears). Grid: one workgroup per infoset.
+template <class F, int W>
+__global__ void __launch_bounds__(64 * W) k_gather_n(int64_t Hp, int64_t N,
+                                                     const int32_t* __restrict__ q_offset,
+                                                     const int32_t* __restrict__ member_offset,
+                                                     const int32_t* __restrict__ members,
+                                                     const int32_t* __restrict__ child_begin,
+                                                     const int8_t* __restrict__ infoset_player,
+                                                     const F* __restrict__ reach,
+                                                     const F* __restrict__ contrib,
+                                                     F* __restrict__ rtilde, F* __restrict__ pibar) {
+    constexpr int kT = 64 * W, KB = kGatherActions;
+    __shared__ F s_part[W][KB + 1];
+    const int64_t h = blockIdx.x;
+    if (h >= Hp) return;  // the whole workgroup leaves together
+    const int tid = threadIdx.x, wave = tid >> 6;
     const int32_t o = q_offset[h], k = q_offset[h + 1] - o;
     const int32_t m0 = member_offset[h], m1 = member_offset[h + 1];
     const int64_t own_plane = static_cast<int64_t>(infoset_player[h] - 1) * N;
-    F own = F(0);
-    for (int32_t m = m0 + lane; m < m1; m += 64) own += reach[own_plane + members[m]];
-    for (int off = 32; off > 0; off >>= 1) own += __shfl_xor(own, off, 64);
-    if (lane == 0) pibar[h] = own;
-    for (int32_t a = 0; a < k; ++a) {
-        F sum = F(0);
-        for (int32_t m = m0 + lane; m < m1; m += 64) sum += contrib[child_begin[members[m]] + a];
-        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
-        if (lane == 0) rtilde[o + a] = sum;
+    // the first walk also sums the own reaches (slot KB), so it runs even for k = 0
+    for (int32_t a0 = 0; a0 == 0 || a0 < k; a0 += KB) {
+        F acc[KB + 1];
+#pragma unroll
+        for (int j = 0; j <= KB; ++j) acc[j] = F(0);
+        for (int32_t m = m0 + tid; m < m1; m += kT) {
+            const int32_t x = members[m];
+            const int32_t cb = child_begin[x] + a0;
+            if (a0 == 0) acc[KB] += reach[own_plane + x];
+#pragma unroll
+            for (int j = 0; j < KB; ++j)
+                if (a0 + j < k) acc[j] += contrib[cb + j];
+        }
+#pragma unroll
+        for (int j = 0; j <= KB; ++j)
+            for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_xor(acc[j], off, 64);
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int j = 0; j <= KB; ++j) s_part[wave][j] = acc[j];
+        __syncthreads();
+        if (tid <= KB) {
+            F sum = F(0);
+#pragma unroll
+            for (int w = 0; w < W; ++w) sum += s_part[w][tid];
+            if (tid < KB && a0 + tid < k) rtilde[o + a0 + tid] = sum;
+            if (tid == KB && a0 == 0) pibar[h] = sum;
+        }
+        __syncthreads();  // s_part is reused by the next walk
     }
 }
 
@@ -501,13 +617,27 @@ const char* kernel_kind_name(int kind) {
 // With stored contributions (d.contrib): the per-infoset sums of the children's regret
 // contributions and of the members' own reaches (k_gather_n, a wavefront per infoset), before
 // the infoset update.
+template <class F, int W>
+void launch_gather_w(const DevT<F>& d, hipStream_t st) {
+    if (d.players > 0)
+        hipLaunchKernelGGL((k_gather_slots<F, W>), dim3(static_cast<unsigned>(d.Hp)), dim3(64 * W),
+                           0, st, d.Hp, d.q_offset, d.member_offset, d.slot_base, d.contrib,
+                           d.rtilde, d.pibar);
+    else
+        hipLaunchKernelGGL((k_gather_n<F, W>), dim3(static_cast<unsigned>(d.Hp)), dim3(64 * W), 0,
+                           st, d.Hp, d.N, d.q_offset, d.member_offset, d.members, d.child_begin,
+                           d.infoset_player, d.reach, d.contrib, d.rtilde, d.pibar);
+}
+
+// The wavefronts per infoset follow the mean member count (one pass of the workgroup over the
+// members of an average infoset, at most four wavefronts).
 template <class F>
 void launch_gather(const DevT<F>& d, hipStream_t st) {
     if (d.contrib == nullptr || d.Hp <= 0) return;
-    const int64_t threads = d.Hp * 64;
-    hipLaunchKernelGGL(k_gather_n<F>, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256),
-                       0, st, d.Hp, d.N, d.q_offset, d.member_offset, d.members, d.child_begin,
-                       d.infoset_player, d.reach, d.contrib, d.rtilde, d.pibar);
+    const int64_t mean = (d.M + d.Hp - 1) / d.Hp;
+    if (mean <= 64) launch_gather_w<F, 1>(d, st);
+    else if (mean <= 128) launch_gather_w<F, 2>(d, st);
+    else launch_gather_w<F, 4>(d, st);
 }
 
 template <class F>
@@ -559,14 +689,18 @@ void launch_reach_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st
 template <class F>
 void launch_value_range(const DevT<F>& d, int32_t lo, int32_t hi, hipStream_t st) {
     if (hi <= lo) return;
-    if (d.players > 0 && hi - lo <= kWideNodes)
-        hipLaunchKernelGGL(k_value_wide_n<F>, dim3(static_cast<unsigned>((hi - lo + 3) / 4)),
+    if (d.players > 0 && hi - lo <= kWideTop)
+        hipLaunchKernelGGL((k_value_wide_n<F, 16>), dim3(static_cast<unsigned>(hi - lo)), dim3(1024),
+                           0, st, lo, hi, d.N, d.players, d.child_begin, d.node_player,
+                           d.node_edge, d.prob, d.node_slot, d.value, d.reach, d.contrib);
+    else if (d.players > 0 && hi - lo <= kWideNodes)
+        hipLaunchKernelGGL((k_value_wide_n<F, 1>), dim3(static_cast<unsigned>((hi - lo + 3) / 4)),
                            dim3(256), 0, st, lo, hi, d.N, d.players, d.child_begin, d.node_player,
-                           d.node_edge, d.prob, d.value, d.reach, d.contrib);
+                           d.node_edge, d.prob, d.node_slot, d.value, d.reach, d.contrib);
     else if (d.players > 0)
         hipLaunchKernelGGL(k_value_level_n<F>, dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st, lo,
                            hi, d.N, d.players, d.child_begin, d.node_player, d.node_edge, d.prob,
-                           d.value, d.reach, d.contrib);
+                           d.node_slot, d.value, d.reach, d.contrib);
     else if (d.contrib != nullptr)
         hipLaunchKernelGGL((k_value_level<F, true>), dim3(blocks_for(hi - lo)), dim3(kBlock), 0, st,
                            lo, hi, d.N, d.child_begin, d.node_player, d.node_infoset, d.node_edge,

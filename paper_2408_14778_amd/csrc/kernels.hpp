@@ -7,6 +7,10 @@
 
 namespace cfr {
 
+// The most rational players of a general-sum game (the general-sum value kernels hold one
+// register per player).
+constexpr int32_t kMaxPlayers = 8;
+
 // All pointers are device memory inside the caller's workspace, canonical order. F is the
 // arithmetic type of the values, probabilities and state: float (the default path) or double
 // (the FP64 path of the node engine).
@@ -35,6 +39,12 @@ struct DevT {
     int32_t* member_offset; // Hp + 1
     int32_t* members;       // M
     int32_t* q_input;       // Qp
+    // general-sum games (players > 0): the gather pass reads each infoset's regret contributions
+    // and own reaches in member order, contiguously. Infoset h owns n_h (k_h + 1) values of
+    // contrib from slot_base[h]: for its j-th member v, from node_slot[v] = slot_base[h] +
+    // j (k_h + 1), v's k_h action contributions, then v's own reach (unused at other nodes)
+    int32_t* node_slot;     // N (players > 0)
+    int32_t* slot_base;     // Hp + 1 (players > 0)
     F* payoff;              // N (players > 0: players * N)
     // iteration state
     F* prob;                // Qp + Q0: current sigma, then sigma_0
@@ -43,10 +53,11 @@ struct DevT {
     F* rtilde;              // Qp accumulator (zero between iterations)
     F* pibar;               // Hp accumulator (zero between iterations)
     F* contrib;             // N, the regret contribution of each player node's child, summed
-                            //   per infoset by the gather pass: general-sum games and games whose
-                            //   infosets average more than 16 members (many atomic additions to
-                            //   one accumulator serialise); null: the value kernels add to rtilde
-                            //   and pibar by atomics
+                            //   per infoset by the gather pass: games whose infosets average
+                            //   more than 16 members (many atomic additions to one accumulator
+                            //   serialise); players > 0: N + M in the member-order slots of
+                            //   node_slot; null: the value kernels add to rtilde and pibar by
+                            //   atomics
     F* value;               // N  expected payoff of player 1 (terminals hold the payoff);
                             //    players > 0: players * N, one column per player
     F* reach;               // 3N (pi_1, pi_2, pi_c) planes; players > 0: (players + 1) N

@@ -181,7 +181,13 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         d.member_offset = c.take<int32_t>(Hp + 1);
         d.members = c.take<int32_t>(M);
         d.q_input = c.take<int32_t>(Qp);
+        if (z.players > 0) {
+            d.node_slot = c.take<int32_t>(N);
+            d.slot_base = c.take<int32_t>(Hp + 1);
+        }
     }
+    // general-sum games store the contributions and own reaches in member order
+    const int64_t n_contrib = z.players > 0 ? N + M : N;
     if (z.fp64) {
         // the node engine in double precision: structure shared with d, values here
         d.T = c.take<int64_t>(1);
@@ -196,6 +202,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         d64.infoset_player = d.infoset_player; d64.q_offset = d.q_offset;
         d64.chance_id = d.chance_id; d64.cq_offset = d.cq_offset;
         d64.member_offset = d.member_offset; d64.members = d.members; d64.q_input = d.q_input;
+        d64.node_slot = d.node_slot; d64.slot_base = d.slot_base;
         d64.T = d.T; d64.best = d.best; d64.out2 = d.out2;
         d64.sq_offset = d.sq_offset; d64.sq_input = d.sq_input;
         d64.players = z.players;
@@ -210,7 +217,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         d64.br_value = c.take<double>(N);
         d64.stage = c.take<double>(2 * Qp);
         d64.rtilde = c.take<double>(Qp);
-        if (store) d64.contrib = c.take<double>(N);
+        if (store) d64.contrib = c.take<double>(n_contrib);
         d64.pibar = c.take<double>(Hp);
         x = cfr::XDev{};
         return (c.off + 255) & ~size_t{255};
@@ -235,7 +242,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
     x = cfr::XDev{};
     if (z.engine == ENGINE_NODE) {
         d.rtilde = c.take<float>(Qp);
-        if (store) d.contrib = c.take<float>(N);
+        if (store) d.contrib = c.take<float>(n_contrib);
         d.pibar = c.take<float>(Hp);
     } else {
         x.N = N; x.Hp = Hp; x.Qp = Qp; x.Q0 = Q0; x.M = M; x.L = z.L; x.C = z.C;
@@ -412,9 +419,6 @@ std::vector<int32_t> reach_launch(const cfr_solver* s) {
 }
 
 
-// The most rational players of a general-sum game (cfr_build_n).
-constexpr int32_t kMaxPlayers = 8;
-
 // A general-sum game of n rational players as the two-player path reads it: the same tree, its
 // first payoff column as u_1 and no u_2 (so no zero-sum check).
 struct GameN {
@@ -424,8 +428,8 @@ struct GameN {
 
 int game_n(const cfr_game* game, int32_t players, const double* payoff, GameN& out) {
     if (game == nullptr || payoff == nullptr) return set_err(CFR_EINVAL, "null argument");
-    if (players < 2 || players > kMaxPlayers)
-        return set_err(CFR_EINVAL, "a general-sum game has 2 to " + std::to_string(kMaxPlayers) +
+    if (players < 2 || players > cfr::kMaxPlayers)
+        return set_err(CFR_EINVAL, "a general-sum game has 2 to " + std::to_string(cfr::kMaxPlayers) +
                                        " rational players");
     if (game->n_nodes < 1) return set_err(CFR_EINVAL, "game arrays must be non-null and n_nodes >= 1");
     out.g = *game;
@@ -736,6 +740,24 @@ int payoff_planes(const cfr::Layout& L, int32_t players, const double* payoff, s
     return CFR_OK;
 }
 
+// The member-order slots of a general-sum game's contributions (DevT::node_slot): infoset h's
+// n_h members, k_h + 1 values each, start at slot_base[h], in canonical infoset order.
+void member_slots(const cfr::Layout& L, std::vector<int32_t>& node_slot,
+                  std::vector<int32_t>& slot_base) {
+    node_slot.assign(static_cast<size_t>(L.N), 0);
+    slot_base.assign(static_cast<size_t>(L.Hp) + 1, 0);
+    int64_t at = 0;
+    for (int64_t h = 0; h < L.Hp; ++h) {
+        const int32_t m0 = L.member_offset[h], n = L.member_offset[h + 1] - m0;
+        const int32_t k = L.q_offset[h + 1] - L.q_offset[h];
+        slot_base[h] = static_cast<int32_t>(at);
+        for (int32_t j = 0; j < n; ++j)
+            node_slot[L.members[m0 + j]] = static_cast<int32_t>(at + static_cast<int64_t>(j) * (k + 1));
+        at += static_cast<int64_t>(n) * (k + 1);
+    }
+    slot_base[L.Hp] = static_cast<int32_t>(at);
+}
+
 // cfr_build for a two-player zero-sum game (players = 0) or a general-sum game of `players`
 // with its payoff matrix (the node engine; simultaneous or, alternating, a pass per player).
 int build_impl(const cfr_game* game, const cfr_config& cfg, int32_t players, const double* payoff,
@@ -829,6 +851,15 @@ int build_impl(const cfr_game* game, const cfr_config& cfg, int32_t players, con
                    (rc = upload(d.prob, prob_tail, st))))) {
         discard(s);
         return rc;
+    }
+    std::vector<int32_t> node_slot;
+    std::vector<int32_t> slot_base;
+    if (players > 0) {
+        member_slots(L, node_slot, slot_base);
+        if ((rc = upload(d.node_slot, node_slot, st)) || (rc = upload(d.slot_base, slot_base, st))) {
+            discard(s);
+            return rc;
+        }
     }
     if (s->engine == ENGINE_BLOCK) {
         cfr_default_launch_shape(&s->shape);

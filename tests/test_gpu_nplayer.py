@@ -53,6 +53,7 @@ GAMES = {
     "nf8": _normal8,
     "nf_k1": _single_action,
     "rand8": lambda: games.random_game_n(**RANDOM8),
+    "rand3_t9": lambda: games.random_game_n(5, 3, n_types=9, depth=4),  # 81 members per infoset
     "silent3": lambda: games.with_silent_players(games.kuhn_like(3, "joint"), 1, seed=6),
     "silent8": lambda: games.with_silent_players(games.leduc_like(3, 2, deal="sequential"), 6,
                                                  seed=7),
@@ -225,19 +226,35 @@ def test_two_player_calls_are_refused():
                                              None, z.n_nodes))
 
 
-@pytest.mark.parametrize("schedule", ["simultaneous", "alternating"])
-@pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
-@pytest.mark.parametrize("variant", ["vanilla", "cfr+"])
-def test_two_player_gather_path_parity(variant, precision, tol, schedule):
-    """A two-player zero-sum game whose infosets average 40 members: the node engine stores the
-    regret contributions and gathers them per infoset (as for general-sum games) instead of
-    adding them by atomics. One iteration against the two-player oracle, with both schedules
-    (the alternating one gathers once per pass)."""
+def _mean_members(g):
+    """Members per rational infoset, rounded up: what picks the gather's workgroup (one
+    wavefront up to 64, two up to 128, else four)."""
+    rational = g.infoset_player[g.node_infoset[g.node_infoset >= 0]] > 0
+    H = int((g.infoset_player > 0).sum())
+    return -(-int(rational.sum()) // H)
+
+
+def test_gather_workgroup_sizes_are_covered():
+    assert _mean_members(GAMES["kuhn3"]()) <= 64
+    assert 64 < _mean_members(GAMES["rand3_t9"]()) <= 128
+
+
+_GATHER_CASES = [(t, v, p, s) for t in (40, 90) for v in ("vanilla", "cfr+")
+                 for p in ("f32", "f64") for s in ("simultaneous", "alternating")] + \
+                [(150, v, p, "simultaneous") for v in ("vanilla", "cfr+") for p in ("f32", "f64")]
+
+
+@pytest.mark.parametrize("types,variant,precision,schedule", _GATHER_CASES)
+def test_two_player_gather_path_parity(types, variant, precision, schedule):
+    """A two-player zero-sum game whose infosets average 40, 90 or 150 members (the gather's
+    workgroup of one, two or four wavefronts): the node engine stores the regret contributions
+    and gathers them per infoset instead of adding them by atomics. One iteration against the
+    two-player oracle, with both schedules (the alternating one gathers once per pass)."""
     from oracle.tree import Tree
     from paper_2408_14778_amd import Solver
-    g = games.random_game(47, n_types=(40, 40), depth=4, deal="joint")
-    rational = g.infoset_player[g.node_infoset[g.node_infoset >= 0]] > 0
-    assert rational.sum() > 16 * int((g.infoset_player > 0).sum()), "infosets too small"
+    tol = 1e-6 if precision == "f32" else 1e-12
+    g = games.random_game(47, n_types=(types, types), depth=4, deal="joint")
+    assert _mean_members(g) == types
     T, R, S = games.random_state(g, seed=3, nonnegative=(variant == "cfr+"))
     s = Solver(g, variant, engine="node", precision=precision, schedule=schedule)
     dt = np.float64 if precision == "f64" else np.float32
@@ -258,8 +275,9 @@ def bench_game():
 @pytest.mark.parametrize("precision,tol", [("f32", 1e-6), ("f64", 1e-12)])
 def test_bench_game_one_iteration_full_size(bench_game, precision, tol):
     """The three-player game `bench.py --workload nplayer` times (2,127,169 nodes, a 1,728-way
-    root, infosets of about 180 members: the wide-level kernel and the wavefront gather), CFR+ as
-    timed, one iteration from a seeded state against the oracle over every pair and node."""
+    root, infosets of about 180 members: the wide-level kernels and the four-wavefront gather),
+    CFR+ as timed, one iteration from a seeded state against the oracle over every pair and
+    node."""
     g = bench_game
     T, R, S = games.random_state(g, seed=1, nonnegative=True)
     s = _solver(g, "cfr+", precision)
