@@ -217,21 +217,37 @@ __global__ void k_value_level_n(int32_t lo, int32_t hi, int64_t N, int32_t P,
     const int8_t who = node_player[p];
     if (who < 0) return;
     const int32_t c0 = child_begin[p], c1 = child_begin[p + 1];
+    // a player node's reaches and slot first: their loads overlap the children's
+    const int32_t me = who - 1;
+    F cf = F(0), own_r = F(0);
+    int32_t at = 0;
+    if (who > 0) {
+        cf = reach[P * N + p];
+        for (int32_t j = 0; j < P; ++j)
+            if (j != me) cf *= reach[j * N + p];
+        own_r = reach[me * N + p];
+        at = node_slot[p];
+    }
+    // every player's column in one walk over the children (each sum in child order)
+    F u[kMaxPlayers];
+#pragma unroll
+    for (int i = 0; i < kMaxPlayers; ++i) u[i] = F(0);
+    for (int32_t c = c0; c < c1; ++c) {
+        const F s = prob[node_edge[c]];
+#pragma unroll
+        for (int i = 0; i < kMaxPlayers; ++i)
+            if (i < P) u[i] = fma_(s, value[i * N + c], u[i]);
+    }
     F own_u = F(0);
-    for (int32_t i = 0; i < P; ++i) {
-        F u = F(0);
-        for (int32_t c = c0; c < c1; ++c) u = fma_(prob[node_edge[c]], value[i * N + c], u);
-        value[i * N + p] = u;
-        if (i == who - 1) own_u = u;
+#pragma unroll
+    for (int i = 0; i < kMaxPlayers; ++i) {
+        if (i < P) value[i * N + p] = u[i];
+        if (i == me) own_u = u[i];
     }
     if (who == 0) return;
-    const int32_t me = who - 1;
-    F cf = reach[P * N + p];
-    for (int32_t j = 0; j < P; ++j)
-        if (j != me) cf *= reach[j * N + p];
-    F* slot = contrib + node_slot[p];
+    F* slot = contrib + at;
     for (int32_t c = c0; c < c1; ++c) slot[c - c0] = cf * (value[me * N + c] - own_u);
-    slot[c1 - c0] = reach[me * N + p];
+    slot[c1 - c0] = own_r;
 }
 
 // k_value_level_n for a level of few nodes, W wavefronts per node: thread t takes children
