@@ -146,11 +146,19 @@ __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
     const int8_t who = node_player[p];
     if (who < 0) return;
     const int32_t c0 = child_begin[p], c1 = child_begin[p + 1];
+    // a player node's reaches (and infoset) first: their loads overlap the children's
+    F r1 = F(0), r2 = F(0), rc = F(0);
+    int32_t h = 0;
+    if (who > 0) {
+        r1 = reach[p];
+        r2 = reach[N + p];
+        rc = reach[2 * N + p];
+        if (!kStore) h = node_infoset[p];
+    }
     F u = F(0);
     for (int32_t c = c0; c < c1; ++c) u = fma_(prob[node_edge[c]], value[c], u);
     value[p] = u;
     if (who == 0) return;
-    const F r1 = reach[p], r2 = reach[N + p], rc = reach[2 * N + p];
     const F cf = (who == 1 ? r2 : r1) * rc;
     const F w = who == 1 ? cf : -cf;
     if (kStore) {
@@ -159,7 +167,7 @@ __global__ void k_value_level(int32_t lo, int32_t hi, int64_t N,
     }
     for (int32_t c = c0; c < c1; ++c)
         unsafeAtomicAdd(&rtilde[node_edge[c]], w * (value[c] - u));
-    unsafeAtomicAdd(&pibar[node_infoset[p]], who == 1 ? r1 : r2);
+    unsafeAtomicAdd(&pibar[h], who == 1 ? r1 : r2);
 }
 
 // ---- general-sum games of P rational players (Section 3.1: the payoff matrix and the
