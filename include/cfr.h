@@ -251,7 +251,9 @@ int cfr_get_node_values_f64(cfr_solver* s, double* u1, double* reach, int64_t n_
  * pass per player in seat order, each under the strategies the earlier passes produced, the
  * iteration counted by the last): at a node d of player i in
  * infoset h the regret r~(h, a) gathers pi_{-i}(d) (w_a[i] - u[i]), pi_{-i} the product of
- * chance's and the other players' reaches, and u the node's payoff vector. cfr_iterate,
+ * chance's and the other players' reaches, and u the node's payoff vector. No step adds by
+ * atomics, so the results do not depend on scheduling: the same game, configuration and state
+ * give the same bits on every run. cfr_iterate,
  * cfr_get_state / cfr_set_state, cfr_average_strategy, cfr_current_strategy (and their _f64
  * forms), cfr_get_layout and cfr_destroy apply unchanged. cfr_exploitability returns
  * CFR_EINVAL (Section 2.2 defines it for two-player zero-sum games), as do cfr_get_node_values

@@ -157,6 +157,24 @@ def test_fp32_expected_payoffs_after_T_iterations(name, variant, iters):
     assert np.abs(np.asarray(got) - np.asarray(ref)).max() <= 1e-3
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["rand8", "rand3_t9"])
+def test_runs_are_bit_identical(name, precision):
+    """No step of the general-sum path adds by atomics: two solvers of the same game from the
+    same state agree bit for bit after T iterations."""
+    g = GAMES[name]()
+    T, R, S = games.random_state(g, seed=4, nonnegative=True)
+    dt = np.float64 if precision == "f64" else np.float32
+    runs = []
+    for _ in range(2):
+        s = _solver(g, "cfr+", precision)
+        s.set_state(T, R.astype(dt), S.astype(dt))
+        s.iterate(25)
+        runs.append(s.get_state())
+    assert runs[0][0] == runs[1][0] == T + 25
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
+
+
 def test_kuhn3_values_add_up_to_zero_on_the_gpu():
     g = GAMES["kuhn3"]()
     s = _solver(g, "cfr+", "f64")
