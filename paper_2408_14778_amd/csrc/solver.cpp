@@ -250,7 +250,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         x.parent = c.take<int32_t>(N);
         x.edge = c.take<int32_t>(N);
         x.meta = c.take<int8_t>(N);
-        x.edge_kind = c.take<int32_t>(N);
+        x.parent_ek = c.take<int64_t>(N);
         x.child_begin = c.take<int32_t>(N);
         x.child_stride = c.take<int32_t>(N);
         x.child_list = c.take<int32_t>(z.L);
@@ -607,17 +607,20 @@ int upload_plan(cfr_solver* s, const cfr::ExecPlan& P, hipStream_t st) {
             mem_rec[m].w = static_cast<int32_t>((static_cast<uint32_t>(mem_rec[m].w) & 0xFFFFFFu) |
                                                 (static_cast<uint32_t>(mem_kp[m]) << 24));
     // edge and kind in one word for the top-down launches, when every edge index fits 24 bits
-    std::vector<int32_t> edge_kind(P.N);
+    // (with the parent beside them in one 8-byte record)
+    std::vector<int64_t> parent_ek(P.N);
     bool ek_fits = true;
     for (int64_t v = 0; v < P.N && ek_fits; ++v) ek_fits = P.edge[v] < (1 << 24);
     x.ek_packed = ek_fits ? 1 : 0;
     if (ek_fits)
-        for (int64_t v = 0; v < P.N; ++v)
-            edge_kind[v] = static_cast<int32_t>(
-                (P.edge[v] < 0 ? 0u : static_cast<uint32_t>(P.edge[v])) |
-                (static_cast<uint32_t>(static_cast<uint8_t>(P.meta[v])) << 24));
+        for (int64_t v = 0; v < P.N; ++v) {
+            const uint32_t ek = (P.edge[v] < 0 ? 0u : static_cast<uint32_t>(P.edge[v])) |
+                                (static_cast<uint32_t>(static_cast<uint8_t>(P.meta[v])) << 24);
+            parent_ek[v] = static_cast<int64_t>((static_cast<uint64_t>(ek) << 32) |
+                                                static_cast<uint32_t>(P.parent[v]));
+        }
     if ((rc = upload(x.parent, P.parent, st)) || (rc = upload(x.edge, P.edge, st)) ||
-        (rc = upload(x.edge_kind, edge_kind, st)) ||
+        (rc = upload(x.parent_ek, parent_ek, st)) ||
         (rc = upload(x.meta, P.meta, st)) || (rc = upload(x.child_begin, P.child_begin, st)) ||
         (rc = upload(x.child_stride, P.child_stride, st)) ||
         (rc = upload(x.child_list, P.child_list, st)) || (rc = upload(x.canon_of, P.canon_of, st)) ||

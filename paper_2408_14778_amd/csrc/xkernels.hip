@@ -86,7 +86,7 @@ __device__ __forceinline__ int rec_kp(int32_t w, int32_t packed, const int8_t* m
 // Reach of NPT nodes x = first + u * stride: the factor of whoever acted into the node (meta
 // bits 2-3) is multiplied by the edge probability (sigma or sigma_0). Terminal nodes need no
 // reach. All loads of the NPT nodes are issued before any of them is used, and a node's parent
-// and edge are loaded together with its kind (with edge_kind, both in one word). The chance plane depends on sigma_0 alone: FULL
+// and edge are loaded together with its kind (with parent_ek, all three in one 8-byte word). The chance plane depends on sigma_0 alone: FULL
 // computes all three planes (once, when the solver is set up); otherwise only the two player
 // planes are written, a chance edge copies them and the chance plane is left as it is.
 template <int NPT, bool FULL>
@@ -96,7 +96,7 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
                                             const int8_t* __restrict__ meta,
                                             const float* __restrict__ prob,
                                             float* __restrict__ reach,
-                                            const int32_t* __restrict__ edge_kind = nullptr) {
+                                            const int64_t* __restrict__ parent_ek = nullptr) {
     int64_t xs[NPT];
     int kind[NPT];
     int32_t p[NPT], e[NPT];
@@ -106,12 +106,14 @@ __device__ __forceinline__ void reach_nodes(int64_t first, int64_t stride, int64
         kind[u] = 0;
         p[u] = e[u] = 0;
         if (xs[u] < hi) {  // every node below the root has a parent and an edge
-            p[u] = __builtin_nontemporal_load(&parent[xs[u]]);
-            if (edge_kind != nullptr) {  // the edge in the low 24 bits, the kind byte on top
-                const uint32_t w = static_cast<uint32_t>(__builtin_nontemporal_load(&edge_kind[xs[u]]));
-                kind[u] = static_cast<int>(w >> 24);
-                e[u] = static_cast<int32_t>(w & 0xFFFFFFu);
+            if (parent_ek != nullptr) {  // parent low; edge in bits 32-55, the kind byte on top
+                const uint64_t w =
+                    static_cast<uint64_t>(__builtin_nontemporal_load(&parent_ek[xs[u]]));
+                p[u] = static_cast<int32_t>(static_cast<uint32_t>(w));
+                kind[u] = static_cast<int>(w >> 56);
+                e[u] = static_cast<int32_t>((w >> 32) & 0xFFFFFFu);
             } else {
+                p[u] = __builtin_nontemporal_load(&parent[xs[u]]);
                 kind[u] = meta[xs[u]];
                 e[u] = edge[xs[u]];
             }
@@ -153,11 +155,11 @@ __global__ void __launch_bounds__(1024) k_x_reach(int32_t t0, int64_t N,
                                                   const int8_t* __restrict__ meta,
                                                   const float* __restrict__ prob,
                                                   float* __restrict__ reach,
-                                                  const int32_t* __restrict__ edge_kind) {
+                                                  const int64_t* __restrict__ parent_ek) {
     const int32_t t = t0 + static_cast<int32_t>(xcd_tile());
     const int32_t lo = tile_lo[t], hi = tile_hi[t];
     reach_nodes<NPT, false>(lo + static_cast<int64_t>(threadIdx.x), blockDim.x, hi, N, parent, edge,
-                            meta, prob, reach, edge_kind);
+                            meta, prob, reach, parent_ek);
 }
 
 // Several small levels in one launch without a barrier between them: the node of each lane
@@ -1244,7 +1246,7 @@ void launch_up(const XDev& x, const UpArgs& a, int32_t l, hipStream_t st) {
 void launch_reach_level(const XDev& x, int32_t l, hipStream_t st) {
     const int32_t t0 = x.t_level_offset_host[l], nt = x.t_level_offset_host[l + 1] - t0;
     if (nt == 0) return;
-    const int32_t* ek = x.ek_packed ? x.edge_kind : nullptr;
+    const int64_t* ek = x.ek_packed ? x.parent_ek : nullptr;
     const int threads = x.reach_threads_host[l];
     switch (x.reach_npt_host[l]) {
         case 2:

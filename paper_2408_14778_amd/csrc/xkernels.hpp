@@ -97,9 +97,10 @@ struct XDev {
     int32_t* parent;
     int32_t* edge;
     int8_t* meta;
-    // edge | meta << 24 per node (ek_packed = 1 when every edge index fits 24 bits): the per-level
-    // top-down launches read a node's edge and kind in one word
-    int32_t* edge_kind;
+    // per node, parent in the low 32 bits and edge | meta << 24 in the high 32 (ek_packed = 1 when
+    // every edge index fits 24 bits): the per-level top-down launches read a node's parent, edge and
+    // kind in one 8-byte load
+    int64_t* parent_ek;
     int32_t ek_packed;
     int32_t* child_begin;
     int32_t* child_stride;
