@@ -250,7 +250,7 @@ size_t carve(cfr::Dev& d, cfr::Dev64& d64, cfr::XDev& x, void* base, const Sizes
         x.parent = c.take<int32_t>(N);
         x.edge = c.take<int32_t>(N);
         x.meta = c.take<int8_t>(N);
-        x.parent_ek = c.take<int64_t>(N);
+        x.parent_ek = c.take<int64_t>(N + 1);  // + 1: the top-down reads records in pairs
         x.child_begin = c.take<int32_t>(N);
         x.child_stride = c.take<int32_t>(N);
         x.child_list = c.take<int32_t>(z.L);

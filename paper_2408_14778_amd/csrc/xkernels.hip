@@ -162,6 +162,70 @@ __global__ void __launch_bounds__(1024) k_x_reach(int32_t t0, int64_t N,
                             meta, prob, reach, parent_ek);
 }
 
+// One level as k_x_reach, with the records read two nodes at a time: thread i takes the pairs of
+// nodes (b + 2j, b + 2j + 1), j = i + u * blockDim, from b = lo rounded down to even, and loads
+// both nodes' {parent, edge | kind << 24} records in one 16-byte load (the record array holds
+// N + 1 entries, so the pair at N - 1 stays in bounds). Nodes outside [lo, hi) are neither
+// computed nor stored. A tile of at most blockDim * NPT nodes spans at most blockDim * NPT / 2 + 1
+// pairs: NPT / 2 + 1 pair slots per thread. The arithmetic is reach_nodes' (bit-identical).
+template <int NPT>
+__global__ void __launch_bounds__(1024) k_x_reach_pairs(int32_t t0, int64_t N,
+                                                        const int32_t* __restrict__ tile_lo,
+                                                        const int32_t* __restrict__ tile_hi,
+                                                        const float* __restrict__ prob,
+                                                        float* __restrict__ reach,
+                                                        const int64_t* __restrict__ parent_ek) {
+    typedef long long v2i64 __attribute__((ext_vector_type(2)));
+    constexpr int NP = NPT / 2 + 1;
+    const int32_t t = t0 + static_cast<int32_t>(xcd_tile());
+    const int64_t lo = tile_lo[t], hi = tile_hi[t];
+    const int64_t base = lo & ~int64_t{1};
+    const int64_t npairs = (hi - base + 1) >> 1;
+    int64_t xs[2 * NP];
+    int kind[2 * NP];
+    int32_t p[2 * NP], e[2 * NP];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+        const int64_t pj = static_cast<int64_t>(threadIdx.x) + static_cast<int64_t>(u) * blockDim.x;
+        xs[2 * u] = base + 2 * pj;
+        xs[2 * u + 1] = base + 2 * pj + 1;
+        uint64_t w[2] = {0, 0};
+        if (pj < npairs) {
+            const v2i64 r = __builtin_nontemporal_load(
+                reinterpret_cast<const v2i64*>(parent_ek + base + 2 * pj));
+            w[0] = static_cast<uint64_t>(r.x);
+            w[1] = static_cast<uint64_t>(r.y);
+        }
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int64_t x = xs[2 * u + v];
+            const bool in = x >= lo && x < hi;
+            p[2 * u + v] = static_cast<int32_t>(static_cast<uint32_t>(w[v]));
+            kind[2 * u + v] = in ? static_cast<int>(w[v] >> 56) : 0;
+            e[2 * u + v] = static_cast<int32_t>((w[v] >> 32) & 0xFFFFFFu);
+        }
+    }
+    float r1[2 * NP], r2[2 * NP], s[2 * NP];
+#pragma unroll
+    for (int u = 0; u < 2 * NP; ++u) {
+        r1[u] = r2[u] = s[u] = 0.0f;
+        if (kind[u] & 3) {
+            r1[u] = reach[p[u]];
+            r2[u] = reach[N + p[u]];
+            if ((kind[u] >> 2) != 1) s[u] = prob[e[u]];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * NP; ++u) {
+        if ((kind[u] & 3) == 0) continue;
+        const int actor = kind[u] >> 2;  // 1 chance, 2 player 1, 3 player 2
+        if (actor == 2) r1[u] *= s[u];
+        else if (actor == 3) r2[u] *= s[u];
+        reach[xs[u]] = r1[u];
+        reach[N + xs[u]] = r2[u];
+    }
+}
+
 // Several small levels in one launch without a barrier between them: the node of each lane
 // (tiles as in k_x_reach, one node per lane) walks up through its ancestors to the first stored
 // level (nodes below `stop`), at most kPathDepth steps, collecting the edge probabilities and
@@ -1248,6 +1312,11 @@ void launch_reach_level(const XDev& x, int32_t l, hipStream_t st) {
     if (nt == 0) return;
     const int64_t* ek = x.ek_packed ? x.parent_ek : nullptr;
     const int threads = x.reach_threads_host[l];
+    if (ek != nullptr && x.reach_npt_host[l] == 2) {
+        hipLaunchKernelGGL(k_x_reach_pairs<2>, dim3(nt), dim3(threads), 0, st, t0, x.N, x.tile_lo,
+                           x.tile_hi, x.prob, x.reach, ek);
+        return;
+    }
     switch (x.reach_npt_host[l]) {
         case 2:
             hipLaunchKernelGGL(k_x_reach<2>, dim3(nt), dim3(threads), 0, st, t0, x.N, x.tile_lo,
